@@ -1,0 +1,182 @@
+/*
+ * rexii.h -- C ABI of the REXII shifted-solve library for MI355X (gfx950).
+ *
+ * The library computes u = exp(tA) f for the linear rotating shallow-water
+ * operator A on a doubly periodic grid by the REXII rational approximation
+ * of Caliari, Einkemmer, Moriggl and Ostermann (arXiv 2008.11607):
+ *
+ *     exp(tA) f  ~  Re sum_{k=1}^{P} alpha_k (A - beta_k I)^{-1} f
+ *
+ * (Sec. 2.2, eqs. REXI_Modified_matrix and modifiedRexiMatrixReducedSum,
+ * written as partial fractions).  Every shifted system is solved
+ * matrix-free on the GPU, all poles concurrently, and the weighted sum is
+ * accumulated in FP64.
+ *
+ * Operator (Sec. 4, with centred differences, gravity g, depth H and
+ * Coriolis parameter f_c; fields f[c][j][i], c in (eta, u, v), j = y index,
+ * i = x index, grid spacing 1/nx and 1/ny on the unit square):
+ *
+ *     A f = ( -dx(H u) - dy(H v),  -g dx eta + f_c v,  -g dy eta - f_c u ),
+ *     dx phi[j][i] = (phi[j][i+1] - phi[j][i-1]) * nx / 2   (periodic).
+ *
+ * Conventions for every entry point
+ *   - Return value: REXII_OK (0) or a negative rexii_status.  Nothing throws
+ *     or aborts across the ABI; rexii_last_error() gives a message for the
+ *     last failing call on the calling thread.
+ *   - Device pointers are HIP device memory owned by the caller; the library
+ *     never frees or keeps them.  Host pointers are plain host memory.
+ *   - Arrays are contiguous, C order, float64, [3][ny][nx] for states.
+ *   - GPU work is enqueued on `stream` (NULL = the null stream).  The calls
+ *     that solve return only after their result is complete on `stream`
+ *     (the host waits for convergence flags it reads back).
+ *   - Workspace: pass NULL/0 and the library allocates what it needs on the
+ *     device and frees it before returning; or pass a device buffer of at
+ *     least rexii_workspace_size() bytes (256-byte aligned).
+ */
+#ifndef REXII_H
+#define REXII_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REXII_OK = 0,
+    REXII_ERR_INVALID_ARG = -1,   /* bad pointer, size, shape or option      */
+    REXII_ERR_NONFINITE = -2,     /* NaN or Inf in the input state or depth  */
+    REXII_ERR_NOT_CONVERGED = -3, /* a shifted solve hit max_iter (u is still
+                                     written, from the best iterates)        */
+    REXII_ERR_BREAKDOWN = -4,     /* Krylov breakdown (p^T K p == 0)         */
+    REXII_ERR_OOM = -5,           /* device allocation failed                */
+    REXII_ERR_HIP = -6,           /* a HIP runtime call failed               */
+    REXII_ERR_WORKSPACE = -7      /* caller workspace too small              */
+} rexii_status;
+
+enum { REXII_PREC_FP64 = 0, REXII_PREC_MIXED = 1 };
+
+/* The operator.  H_field == NULL: constant depth H0.  Otherwise H_field is a
+ * device array [ny][nx] of positive depths and A is in flux form (the depth
+ * sits inside the divergence); H0 is then ignored. */
+typedef struct rexii_swe_op {
+    int32_t nx, ny;          /* grid points in x and y, each >= 4           */
+    double g;                /* gravity, > 0                                */
+    double f_cor;            /* Coriolis parameter                          */
+    double H0;               /* constant depth, > 0                         */
+    const double* H_field;   /* device [ny][nx] or NULL                     */
+} rexii_swe_op;
+
+typedef struct rexii_opts {
+    double h;               /* Gaussian width of the approximation (Sec. 2.1,
+                               best in [0.3, 0.6] per Sec. 3.1); 0 -> 0.5    */
+    double tol;             /* target relative L2 error of u; 0 -> 1e-10 for
+                               FP64, 1e-6 for MIXED.  Sets m0 (Appendix B)
+                               and the per-pole residual tolerance          */
+    int32_t precision;      /* REXII_PREC_FP64 or REXII_PREC_MIXED (FP32
+                               inner Krylov iterations, FP64 residuals,
+                               refinement, weights and pole sum)            */
+    int32_t max_iter;       /* cap on Krylov iterations of one solve, all
+                               refinement rounds together; 0 -> 50000       */
+    int32_t m0;             /* safety term of the M rule; < 0 -> from tol   */
+    double rho;             /* bound on the spectral radius of A; <= 0 ->
+                               computed (exact for constant depth)          */
+    int32_t pole_batch;     /* concurrent solves per batch; 0 -> automatic  */
+    int32_t pair_conjugate; /* 1: when div(u0, v0) == 0 the two poles of a
+                               term share one Krylov solve (exact identity);
+                               0: one solve per pole.  Default 1            */
+    double inner_tol;       /* MIXED: relative residual reduction of one FP32
+                               inner solve; 0 -> 1e-4                      */
+} rexii_opts;
+
+typedef struct rexii_report {
+    int32_t P;               /* number of poles (= 2(N+1))                  */
+    int32_t M, N, m0;        /* M rule (eq. matrixAccuracyBound), N = M + L */
+    int32_t solves;          /* Krylov systems solved (P, or P/2 paired)    */
+    int32_t max_iters;       /* most Krylov iterations of one solve         */
+    int32_t max_refine;      /* most FP64 residual/refinement rounds        */
+    int32_t not_converged;   /* solves that stopped at max_iter            */
+    int64_t total_iters;     /* Krylov iterations summed over solves        */
+    double h, t, rho;
+    double kappa_sum;        /* sum |alpha_k t| / |h mu|: amplification of
+                               per-pole errors in the weighted sum          */
+    double pole_tol;         /* relative residual each solve is driven to   */
+    double max_rel_residual; /* largest final FP64 relative residual        */
+    double seconds;          /* host wall time of the call                  */
+    double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
+} rexii_report;
+
+/* Fill *opts with the defaults described above. */
+void rexii_default_opts(rexii_opts* opts);
+
+/* Poles and weights (host, FP64).  Sec. 2.1 eqs. bm and modifiedRexi give
+ * c_{1,n}, c_{2,n}; Sec. 2.2 gives C_{1,n}, C_{2,n}; the reduced sum
+ * (eq. modifiedRexiMatrixReducedSum) has, for n = 0..N, poles of tA at
+ * alpha_{-n} = h(mu - i n) and -alpha_n = -h(mu + i n); M follows
+ * eq. matrixAccuracyBound: M = ceil(t rho / h) + m0, N = M + 24.
+ *   t > 0, rho > 0, 0 < h < pi; tol in (0, 1) chooses m0 when m0 < 0.
+ *   *P receives the pole count 2(N+1).  If beta and alpha are non-NULL they
+ *   must hold 2*P doubles each and receive (re, im) pairs of
+ *   beta_k = z_k / t and alpha_k = w_k / t, ordered n = 0..N, two per n.
+ *   kappa_sum may be NULL.  Errors: REXII_ERR_INVALID_ARG. */
+rexii_status rexii_coeffs(double t, double rho, double h, double tol, int32_t m0,
+                          int32_t* P, double* beta, double* alpha, double* kappa_sum);
+
+/* Spectral radius bound of A (eq. matrixAccuracyBound needs an upper bound).
+ * Constant depth: exact, sqrt(f_c^2 + g H0 max(s_x^2 + s_y^2)) with
+ * s_x = nx sin(2 pi k / nx).  Variable depth: the guaranteed
+ * sqrt(g max H) sqrt(nx^2 + ny^2) + |f_c| (reads H_field on `stream`). */
+rexii_status rexii_rho(const rexii_swe_op* op, hipStream_t stream, double* rho);
+
+/* Device workspace rexii_apply / rexii_apply_adjoint need for these
+ * arguments (bytes).  t is needed because it fixes the pole count. */
+rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts,
+                                  double t, size_t* bytes);
+
+/* u = exp(tA) f (REXII approximation).  f, u: device [3][ny][nx], must not
+ * overlap.  t >= 0 (t == 0 copies f).  opts may be NULL (defaults); rep may
+ * be NULL.  Errors: INVALID_ARG, NONFINITE (f or H_field), NOT_CONVERGED,
+ * BREAKDOWN, OOM, HIP, WORKSPACE. */
+rexii_status rexii_apply(const rexii_swe_op* op, const double* f, double* u, double t,
+                         const rexii_opts* opts, void* workspace, size_t ws_bytes,
+                         hipStream_t stream, rexii_report* rep);
+
+/* Reverse mode of rexii_apply for a loss J(u).  gbar = dJ/du (device
+ * [3][ny][nx]).  dJdf (device [3][ny][nx], may be NULL) receives
+ * r(tA)^T gbar.  dJdH (host, may be NULL; constant depth only) receives
+ * dJ/dH0 for the same pole set (poles do not move with H0).  The transpose
+ * uses the same poles with weights rearranged (A^T = -W A W^{-1}).
+ * Errors as rexii_apply. */
+rexii_status rexii_apply_adjoint(const rexii_swe_op* op, const double* f, const double* gbar,
+                                 double* dJdf, double* dJdH, double t, const rexii_opts* opts,
+                                 void* workspace, size_t ws_bytes, hipStream_t stream,
+                                 rexii_report* rep);
+
+/* count independent problems in one call: ops[i], f[i], u[i], t[i] as in
+ * rexii_apply (host arrays of device pointers).  All instances' solves share
+ * one persistent pole scheduler.  reps may be NULL or hold count reports. */
+rexii_status rexii_apply_batched(int32_t count, const rexii_swe_op* ops, const double* const* f,
+                                 double* const* u, const double* t, const rexii_opts* opts,
+                                 void* workspace, size_t ws_bytes, hipStream_t stream,
+                                 rexii_report* reps);
+
+/* Single-pole resolvents (Sec. 4, per-term systems): x_k = (tA - z_k I)^{-1} f
+ * for npoles complex shifts z (host, (re, im) pairs), Re z_k != 0.
+ * x: device complex128 [npoles][3][ny][nx] as (re, im) pairs.
+ * Errors as rexii_apply. */
+rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double t, int32_t npoles,
+                                 const double* z, double* x, const rexii_opts* opts,
+                                 void* workspace, size_t ws_bytes, hipStream_t stream,
+                                 rexii_report* rep);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* rexii_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REXII_H */

@@ -1,0 +1,171 @@
+// Host-side FP64 REXII coefficients: poles and weights of the reduced
+// partial-fraction sum, the accuracy rule and the spectral radius bound.
+//
+// Paper: Caliari, Einkemmer, Moriggl, Ostermann, arXiv 2008.11607.
+//   * b_m = e^{-imh} e^{h^2}                                   (Sec. 2.1, eq. bm)
+//   * c_{1,n} = h sum_{k=L1(n)}^{L2(n)} Re(a_k) b_{n-k},
+//     c_{2,n} = h sum_{k=L1(n)}^{L2(n)} Im(a_k) b_{n-k}          (eq. modifiedRexi)
+//   * C_{1,n} = c_{1,n} h mu + c_{2,n} h n,  C_{2,n} = i c_{2,n}  (Sec. 2.2)
+//   * reduced sum over n = 0..N with Gamma_0 = 1, Gamma_n = 2   (eq. modifiedRexiMatrixReducedSum)
+//   * M = ceil(t rho / h) + m0                                  (eq. matrixAccuracyBound)
+//   * m0 from psi_h(z) <= tol for |z| >= c h                     (Appendix B)
+//   * mu and a_0..a_24                                          (Appendix A, Table coef_al)
+//
+// Term n, a rational function of X = tA, is
+//   Gamma_n (C_{1,n} - C_{2,n} X) (alpha_{-n} - X)^{-1} (alpha_n + X)^{-1};
+// its poles alpha_{-n} and -alpha_n differ by 2 h mu, so it splits into
+//   w1 / (X - z1) + w2 / (X - z2),  z1 = h(mu - i n),  z2 = -h(mu + i n),
+//   w1 = -Gamma_n (C1 - C2 z1) / (2 h mu),  w2 = Gamma_n (C1 - C2 z2) / (2 h mu).
+// C1 - C2 z is formed directly: c_{2,n} can be ~1e-9, so the form with
+// C1/C2 would lose accuracy.
+#include "rexii_internal.h"
+
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace rexii {
+
+namespace {
+
+constexpr int kL = 24;
+constexpr double kMu = -5.133333333333333;
+
+// Appendix A: (Re a_l, Im a_l) for l = 0..24.  The sign column of the
+// printed table applies to the real part only; a_{-l} = conj(a_l).
+constexpr double kA[kL + 1][2] = {
+    {-6.520430828919864e+01, 0.0},
+    {4.261818064131437e+01, 2.761406741120911e+01},
+    {-9.801650304425239e+00, -2.189295463610722e+01},
+    {-1.054225194693395e+00, 6.791786454153551e+00},
+    {7.950505668209775e-01, -8.904997258367445e-01},
+    {-1.218558380859130e-01, 3.321241563407446e-02},
+    {7.365401806949337e-03, 2.212802103193251e-03},
+    {-2.801087265991056e-04, -5.566945197754387e-04},
+    {1.254835436432561e-04, -2.467200513365371e-04},
+    {2.295472292491263e-04, -8.494118951459107e-05},
+    {1.858484460459430e-04, 9.242889460185034e-05},
+    {4.068056518449676e-05, 1.653479957565515e-04},
+    {-8.341508001647741e-05, 1.045331460447588e-04},
+    {-9.970528169841103e-05, -5.856228484297677e-06},
+    {-3.499639858693093e-05, -6.129059473910835e-05},
+    {2.295021920298455e-05, -4.099832469456381e-05},
+    {2.931048772724314e-05, 1.708815129697846e-07},
+    {7.502088478301169e-06, 1.525082051744077e-05},
+    {-5.815291167450100e-06, 6.919604247338349e-06},
+    {-4.069948458364005e-06, -1.440010113050771e-06},
+    {7.932524475429588e-08, -1.794169428574330e-06},
+    {6.120984882186265e-07, -1.131894636585849e-07},
+    {5.531365159161319e-08, 1.585749903175946e-07},
+    {-2.867805871375946e-08, 1.239499740327838e-08},
+    {-1.143081277095316e-09, -2.763239274253499e-09},
+};
+
+inline double a_re(int l) { return kA[l < 0 ? -l : l][0]; }
+inline double a_im(int l) { return l >= 0 ? kA[l][1] : -kA[-l][1]; }
+
+}  // namespace
+
+double mu() { return kMu; }
+int terms_L() { return kL; }
+
+int m0_from_tol(double tol) {
+  const double c = 2.0 * std::sqrt(-std::log(std::sqrt(4.0 * M_PI) * tol));
+  return static_cast<int>(std::ceil(c - 1.0));
+}
+
+int m_rule(double t, double rho, double h, int m0) {
+  return static_cast<int>(std::ceil(t * rho / h)) + m0;
+}
+
+void poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w) {
+  using std::complex;
+  const int N = M + kL;
+  z.resize(2 * (N + 1));
+  w.resize(2 * (N + 1));
+  const double eh2 = std::exp(h * h);
+  for (int n = 0; n <= N; ++n) {
+    // c_{1,n}, c_{2,n}: k from L1(n) = max(-L, n-M) to L2(n) = min(L, n+M)
+    complex<double> c1(0.0, 0.0), c2(0.0, 0.0);
+    const int k1 = std::max(-kL, n - M), k2 = std::min(kL, n + M);
+    for (int k = k1; k <= k2; ++k) {
+      const double m = static_cast<double>(n - k);
+      const complex<double> bm = std::polar(eh2, -m * h);  // e^{h^2} e^{-imh}
+      c1 += a_re(k) * bm;
+      c2 += a_im(k) * bm;
+    }
+    c1 *= h;
+    c2 *= h;
+    const complex<double> C1 = c1 * (h * kMu) + c2 * (h * n);
+    const complex<double> C2 = complex<double>(0.0, 1.0) * c2;
+    const double gam = (n == 0) ? 1.0 : 2.0;
+    const complex<double> z1(h * kMu, -h * n);    // alpha_{-n}
+    const complex<double> z2(-h * kMu, -h * n);   // -alpha_n
+    const complex<double> w1 = -gam * (C1 - C2 * z1) / (2.0 * h * kMu);
+    const complex<double> w2 = gam * (C1 - C2 * z2) / (2.0 * h * kMu);
+    z[2 * n] = {z1.real(), z1.imag()};
+    z[2 * n + 1] = {z2.real(), z2.imag()};
+    w[2 * n] = {w1.real(), w1.imag()};
+    w[2 * n + 1] = {w2.real(), w2.imag()};
+  }
+}
+
+double kappa_sum(const std::vector<cplx>& w, double h) {
+  double s = 0.0;
+  for (const cplx& c : w) s += std::hypot(c.re, c.im);
+  return s / std::fabs(h * kMu);
+}
+
+double max_s2(int n) {
+  // max over k of (n sin(2 pi k / n))^2
+  double m = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double s = n * std::sin(2.0 * M_PI * k / n);
+    m = std::max(m, s * s);
+  }
+  return m;
+}
+
+double rho_const(int nx, int ny, double g, double H, double fc) {
+  return std::sqrt(fc * fc + g * H * (max_s2(nx) + max_s2(ny)));
+}
+
+double rho_bound_var(int nx, int ny, double g, double Hmax, double fc) {
+  return std::sqrt(g * Hmax) * std::sqrt(double(nx) * nx + double(ny) * ny) + std::fabs(fc);
+}
+
+}  // namespace rexii
+
+extern "C" rexii_status rexii_coeffs(double t, double rho, double h, double tol, int32_t m0,
+                                     int32_t* P, double* beta, double* alpha, double* kappa) {
+  using namespace rexii;
+  if (!P) return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs: P is NULL");
+  if (!(t > 0.0) || !(rho > 0.0) || !(h > 0.0) || !(h < M_PI) || !std::isfinite(t) ||
+      !std::isfinite(rho))
+    return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs: need t > 0, rho > 0, 0 < h < pi");
+  if (m0 < 0) {
+    if (!(tol > 0.0 && tol < 1.0))
+      return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs: tol must be in (0, 1)");
+    m0 = m0_from_tol(tol);
+  }
+  const double Md = std::ceil(t * rho / h) + m0;
+  if (Md > 5.0e7) return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs: t*rho/h too large");
+  const int M = m_rule(t, rho, h, m0);
+  const int Pn = 2 * (M + terms_L() + 1);
+  *P = Pn;
+  if (!beta && !alpha && !kappa) return clear_error();
+  std::vector<cplx> z, w;
+  poles_weights(M, h, z, w);
+  for (int k = 0; k < Pn; ++k) {
+    if (beta) {
+      beta[2 * k] = z[k].re / t;
+      beta[2 * k + 1] = z[k].im / t;
+    }
+    if (alpha) {
+      alpha[2 * k] = w[k].re / t;
+      alpha[2 * k + 1] = w[k].im / t;
+    }
+  }
+  if (kappa) *kappa = kappa_sum(w, h);
+  return clear_error();
+}

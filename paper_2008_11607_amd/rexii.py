@@ -1,0 +1,223 @@
+"""Python binding of librexii (ctypes).  Argument marshalling only: every step
+of the computation runs in the library's HIP kernels; PyTorch supplies the
+device memory and the stream.
+
+Loading fails loudly (``RuntimeError``) if ``librexii.so`` has not been built;
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librexii.so")
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+STATUS = {
+    0: "REXII_OK", -1: "REXII_ERR_INVALID_ARG", -2: "REXII_ERR_NONFINITE",
+    -3: "REXII_ERR_NOT_CONVERGED", -4: "REXII_ERR_BREAKDOWN", -5: "REXII_ERR_OOM",
+    -6: "REXII_ERR_HIP", -7: "REXII_ERR_WORKSPACE",
+}
+
+
+class RexiiError(RuntimeError):
+    def __init__(self, status, msg, report=None):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.report = report
+
+
+class SweOp(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("g", ctypes.c_double),
+                ("f_cor", ctypes.c_double), ("H0", ctypes.c_double), ("H_field", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("m0", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("pole_batch", ctypes.c_int32), ("pair_conjugate", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("M", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("m0", ctypes.c_int32), ("solves", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("not_converged", ctypes.c_int32),
+                ("total_iters", ctypes.c_int64), ("h", ctypes.c_double), ("t", ctypes.c_double),
+                ("rho", ctypes.c_double), ("kappa_sum", ctypes.c_double),
+                ("pole_tol", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",
+           "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
+           "rexii_shifted_solve", "rexii_last_error"]
+
+_lib = None
+
+
+def load():
+    """Load librexii.so and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2008_11607_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    lib.rexii_default_opts.argtypes = [P(Opts)]
+    lib.rexii_default_opts.restype = None
+    lib.rexii_coeffs.argtypes = [dbl, dbl, dbl, dbl, i32, P(i32), vp, vp, P(dbl)]
+    lib.rexii_coeffs.restype = ctypes.c_int
+    lib.rexii_rho.argtypes = [P(SweOp), vp, P(dbl)]
+    lib.rexii_rho.restype = ctypes.c_int
+    lib.rexii_workspace_size.argtypes = [P(SweOp), P(Opts), dbl, P(sz)]
+    lib.rexii_workspace_size.restype = ctypes.c_int
+    lib.rexii_apply.argtypes = [P(SweOp), vp, vp, dbl, P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_apply.restype = ctypes.c_int
+    lib.rexii_apply_adjoint.argtypes = [P(SweOp), vp, vp, vp, P(dbl), dbl, P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_apply_adjoint.restype = ctypes.c_int
+    lib.rexii_apply_batched.argtypes = [i32, P(SweOp), P(vp), P(vp), P(dbl), P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_apply_batched.restype = ctypes.c_int
+    lib.rexii_shifted_solve.argtypes = [P(SweOp), vp, dbl, i32, vp, vp, P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_shifted_solve.restype = ctypes.c_int
+    lib.rexii_last_error.argtypes = []
+    lib.rexii_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().rexii_last_error().decode()
+
+
+def _check(st, report=None):
+    if st != 0:
+        raise RexiiError(st, last_error(), report)
+
+
+def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=None,
+              pole_batch=None, pair_conjugate=None, inner_tol=None):
+    o = Opts()
+    load().rexii_default_opts(ctypes.byref(o))
+    if h is not None:
+        o.h = h
+    if precision in ("mixed", PREC_MIXED):
+        o.precision = PREC_MIXED
+    elif precision in ("fp64", PREC_FP64):
+        o.precision = PREC_FP64
+    else:
+        raise ValueError(precision)
+    if tol is not None:
+        o.tol = tol
+    if max_iter is not None:
+        o.max_iter = max_iter
+    if m0 is not None:
+        o.m0 = m0
+    if rho is not None:
+        o.rho = rho
+    if pole_batch is not None:
+        o.pole_batch = pole_batch
+    if pair_conjugate is not None:
+        o.pair_conjugate = int(pair_conjugate)
+    if inner_tol is not None:
+        o.inner_tol = inner_tol
+    return o
+
+
+def make_op(nx, ny, g=1.0, fc=10.0, H=1.0, Hfield=None):
+    op = SweOp()
+    op.nx, op.ny, op.g, op.f_cor, op.H0 = int(nx), int(ny), float(g), float(fc), float(H)
+    op.H_field = None if Hfield is None else ctypes.c_void_p(Hfield.data_ptr())
+    return op
+
+
+def coeffs(t, rho, h=0.5, tol=1e-10, m0=-1):
+    """(beta, alpha, kappa_sum): complex numpy arrays of the P poles and
+    weights of exp(tA) ~ Re sum alpha_k (A - beta_k)^{-1} (host, FP64)."""
+    lib = load()
+    P = ctypes.c_int32()
+    _check(lib.rexii_coeffs(t, rho, h, tol, m0, ctypes.byref(P), None, None, None))
+    beta = np.zeros(2 * P.value)
+    alpha = np.zeros(2 * P.value)
+    kap = ctypes.c_double()
+    _check(lib.rexii_coeffs(t, rho, h, tol, m0, ctypes.byref(P), beta.ctypes.data_as(ctypes.c_void_p),
+                            alpha.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kap)))
+    return beta[0::2] + 1j * beta[1::2], alpha[0::2] + 1j * alpha[1::2], kap.value
+
+
+def rho(nx, ny, g=1.0, fc=10.0, H=1.0, Hfield=None):
+    lib = load()
+    op = make_op(nx, ny, g, fc, H, Hfield)
+    out = ctypes.c_double()
+    _check(lib.rexii_rho(ctypes.byref(op), _stream(), ctypes.byref(out)))
+    return out.value
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(x, shape=None):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(x.shape)}")
+    return x
+
+
+def apply(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts):
+    """u = exp(tA) f on the GPU.  f: float64 CUDA tensor [3, ny, nx].
+    Returns (u, report_dict)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    ny, nx = f.shape[1], f.shape[2]
+    if Hfield is not None:
+        _dev_f64(Hfield, (ny, nx))
+    u = torch.empty_like(f) if out is None else _dev_f64(out, f.shape)
+    op = make_op(nx, ny, g, fc, H, Hfield)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_apply(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                         float(t), ctypes.byref(o), None, 0, _stream(), ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return u, rep.as_dict()
+
+
+def shifted_solve(f, t, z, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
+    """x_k = (tA - z_k I)^{-1} f for complex shifts z (host array).
+    Returns (x: complex128 CUDA tensor [npoles, 3, ny, nx], report)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    ny, nx = f.shape[1], f.shape[2]
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=1).ravel())
+    x = torch.empty((len(z), 3, ny, nx), dtype=torch.complex128, device=f.device)
+    op = make_op(nx, ny, g, fc, H, Hfield)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_shifted_solve(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), float(t), len(z),
+                                 zz.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.byref(o), None, 0, _stream(), ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return x, rep.as_dict()
+
+
+def workspace_size(nx, ny, t, g=1.0, fc=10.0, H=1.0, **opts):
+    lib = load()
+    op = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    out = ctypes.c_size_t()
+    _check(lib.rexii_workspace_size(ctypes.byref(op), ctypes.byref(o), float(t), ctypes.byref(out)))
+    return out.value

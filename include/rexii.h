@@ -90,6 +90,10 @@ typedef struct rexii_opts {
                                0: one solve per pole.  Default 1            */
     double inner_tol;       /* MIXED: relative residual reduction of one FP32
                                inner solve; 0 -> 1e-4                      */
+    int32_t profile;        /* 1: launch the inner kernels one by one with
+                               HIP events around each (fills the kernel
+                               timing fields of the report); 0: replay them
+                               from a HIP graph.  Default 0                */
 } rexii_opts;
 
 typedef struct rexii_report {
@@ -107,6 +111,12 @@ typedef struct rexii_report {
     double max_rel_residual; /* largest final FP64 relative residual        */
     double seconds;          /* host wall time of the call                  */
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
+    /* with opts.profile = 1: launches and summed event time of the two inner
+     * Krylov kernels, and their algorithmic bytes (every vector element they
+     * must read or write, once: 3 and 5 complex values per grid point) */
+    int64_t mv_launches, up_launches;
+    double mv_ms, up_ms;
+    double mv_bytes, up_bytes;
 } rexii_report;
 
 /* Fill *opts with the defaults described above. */

@@ -111,6 +111,7 @@ struct Plan {
   bool has_vel;
   int B;               // slots per batch
   int chunk;           // inner iterations per graph replay
+  bool profile = false;
   std::vector<cd> z, w;
   std::vector<SolveDesc> solves;
   double S1 = 0, S2 = 0;
@@ -178,6 +179,7 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   pl.max_iter = o.max_iter;
   pl.inner_eta = (o.precision == REXII_PREC_MIXED) ? o.inner_tol : 0.0;
   pl.has_vel = has_vel;
+  pl.profile = (o.profile != 0);
   pl.paired = (o.pair_conjugate != 0) && div_free;
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
@@ -303,9 +305,15 @@ struct Engine {
   int max_iters = 0, max_rounds = 0, not_conv = 0, breakdowns = 0;
   int64_t total_iters = 0;
   double max_rel_res = 0.0;
+  int stagnated = 0;
+  // profiling (opts.profile)
+  std::vector<hipEvent_t> evs;
+  int64_t mv_launches = 0, up_launches = 0;
+  double mv_ms = 0.0, up_ms = 0.0;
 
   Engine(Plan& p, hipStream_t s) : pl(p), st(s) {}
   ~Engine() {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (hcount) (void)hipHostFree(hcount);
@@ -356,6 +364,42 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(hcount, bt.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   }
 
+  // The same chunk, launched directly, with an event pair around every inner
+  // kernel; elapsed times are collected after the chunk's host sync.
+  template <typename T>
+  void enqueue_chunk_profiled() {
+    if (evs.empty()) {
+      evs.resize(4 * pl.chunk);
+      for (hipEvent_t& e : evs) HIPCHK(hipEventCreate(&e));
+    }
+    launch_outer_update<T>(bt, st);
+    launch_outer_residual<T>(bt, rhs, st);
+    launch_scalars_outer(bt, st);
+    for (int i = 0; i < pl.chunk; ++i) {
+      HIPCHK(hipEventRecord(evs[4 * i], st));
+      launch_inner_mv<T>(bt, st);
+      HIPCHK(hipEventRecord(evs[4 * i + 1], st));
+      launch_scalars_mv(bt, st);
+      HIPCHK(hipEventRecord(evs[4 * i + 2], st));
+      launch_inner_up<T>(bt, st);
+      HIPCHK(hipEventRecord(evs[4 * i + 3], st));
+      launch_scalars_up(bt, st);
+    }
+    launch_count(bt, st);
+    HIPCHK(hipMemcpyAsync(hcount, bt.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  void collect_profile() {
+    for (int i = 0; i < pl.chunk; ++i) {
+      float a = 0.f, b = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, evs[4 * i], evs[4 * i + 1]));
+      HIPCHK(hipEventElapsedTime(&b, evs[4 * i + 2], evs[4 * i + 3]));
+      mv_ms += a;
+      up_ms += b;
+    }
+    mv_launches += pl.chunk;
+    up_launches += pl.chunk;
+  }
+
   template <typename T>
   void build_graph() {
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -377,7 +421,7 @@ struct Engine {
   void run(const double* f, double2* xout) {
     const size_t n = size_t(pl.nx) * pl.ny;
     const int S = int(pl.solves.size());
-    build_graph<T>();
+    if (!pl.profile) build_graph<T>();
     std::vector<Slot> hs(pl.B);
     std::vector<double2> hc0(pl.B), hc1(pl.B), hc2(pl.B), his(pl.B), hm1(pl.B), hm2(pl.B);
     for (int s0 = 0; s0 < S; s0 += pl.B) {
@@ -418,8 +462,14 @@ struct Engine {
       // replay the chunk until no slot is working
       const int max_replays = pl.max_iter / pl.chunk + 64;
       for (int rep = 0; rep < max_replays; ++rep) {
-        HIPCHK(hipGraphLaunch(gexec, st));
-        HIPCHK(hipStreamSynchronize(st));
+        if (pl.profile) {
+          enqueue_chunk_profiled<T>();
+          HIPCHK(hipStreamSynchronize(st));
+          collect_profile();
+        } else {
+          HIPCHK(hipGraphLaunch(gexec, st));
+          HIPCHK(hipStreamSynchronize(st));
+        }
         if (hcount[0] == 0) break;
       }
       if (xout) {
@@ -438,6 +488,7 @@ struct Engine {
         if (sl.status == kFailMaxIter) not_conv++;
         if (sl.status == kFailBreakdown) breakdowns++;
         if (sl.status != kDone && sl.status != kFailMaxIter && sl.status != kFailBreakdown) not_conv++;
+        stagnated += sl.stagnated;
         const double rel = sl.bn2 > 0 ? std::sqrt(sl.rn2 / sl.bn2) : 0.0;
         max_rel_res = std::max(max_rel_res, rel);
       }
@@ -468,6 +519,12 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* e, doub
     const double eb = double(inner_elem_bytes(pl.precision));
     // inner iteration: mv reads r, p and writes p; up reads p, d, r and writes d, r
     rep->alg_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 8.0 * eb;
+    rep->mv_launches = e->mv_launches;
+    rep->up_launches = e->up_launches;
+    rep->mv_ms = e->mv_ms;
+    rep->up_ms = e->up_ms;
+    rep->mv_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 3.0 * eb;
+    rep->up_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 5.0 * eb;
   }
 }
 

@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("m0", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("pole_batch", ctypes.c_int32), ("pair_conjugate", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("profile", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -49,7 +49,10 @@ class Report(ctypes.Structure):
                 ("total_iters", ctypes.c_int64), ("h", ctypes.c_double), ("t", ctypes.c_double),
                 ("rho", ctypes.c_double), ("kappa_sum", ctypes.c_double),
                 ("pole_tol", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("mv_launches", ctypes.c_int64), ("up_launches", ctypes.c_int64),
+                ("mv_ms", ctypes.c_double), ("up_ms", ctypes.c_double),
+                ("mv_bytes", ctypes.c_double), ("up_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,7 +107,7 @@ def _check(st, report=None):
 
 
 def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=None,
-              pole_batch=None, pair_conjugate=None, inner_tol=None):
+              pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None):
     o = Opts()
     load().rexii_default_opts(ctypes.byref(o))
     if h is not None:
@@ -129,6 +132,8 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
         o.pair_conjugate = int(pair_conjugate)
     if inner_tol is not None:
         o.inner_tol = inner_tol
+    if profile is not None:
+        o.profile = int(profile)
     return o
 
 

@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every symbol its header declares, and its
+host-only logic (coefficients, argument checks) is right.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coeffs as oc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rx():
+    from paper_2008_11607_amd import rexii
+    if not os.path.exists(rexii.LIB_PATH):
+        from paper_2008_11607_amd import build
+        build.build()
+    rexii.load()
+    return rexii
+
+
+def _declared_symbols():
+    out = set()
+    for name in os.listdir(os.path.join(ROOT, "include")):
+        if name.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", name)).read()
+            out |= set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(rexii_\w+)\s*\(", text, flags=re.M))
+    return out
+
+
+def test_exports_every_declared_symbol(rx):
+    syms = _declared_symbols()
+    assert {"rexii_apply", "rexii_apply_adjoint", "rexii_coeffs"} <= syms
+    lib = rx.load()
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(rx.EXPORTS) == syms
+
+
+@pytest.mark.parametrize("trho,h,tol", [(100.0, 0.5, 1e-10), (1000.0, 0.5, 1e-6), (37.5, 1.0, 1e-10),
+                                        (500.0, 0.3, 1e-12)])
+def test_coeffs_match_oracle(rx, trho, h, tol):
+    rho = 91.06041950265768
+    t = trho / rho
+    beta, alpha, kap = rx.coeffs(t, rho, h=h, tol=tol)
+    ref = oc.api_coeffs(t, rho, h=h, tol=tol)
+    assert len(beta) == ref["P"]
+    assert np.max(np.abs(beta - ref["beta"])) <= 1e-14 * np.max(np.abs(ref["beta"]))
+    assert np.max(np.abs(alpha - ref["alpha"])) <= 1e-13 * np.max(np.abs(ref["alpha"]))
+    assert abs(kap - ref["kappa_sum"]) <= 1e-12 * ref["kappa_sum"]
+
+
+def test_coeffs_explicit_m0(rx):
+    beta, _, _ = rx.coeffs(1.0, 30.0, h=0.5, m0=11)
+    # M = ceil(30/0.5) + 11 = 71, N = 95, P = 192
+    assert len(beta) == 2 * (71 + 24 + 1)
+
+
+def test_coeffs_query_only(rx):
+    lib = rx.load()
+    P = ctypes.c_int32(-1)
+    assert lib.rexii_coeffs(1.0, 10.0, 0.5, 1e-10, -1, ctypes.byref(P), None, None, None) == 0
+    assert P.value == 2 * (20 + 9 + 24 + 1)
+
+
+@pytest.mark.parametrize("args", [(0.0, 10.0, 0.5, 1e-10), (1.0, -1.0, 0.5, 1e-10), (1.0, 10.0, 4.0, 1e-10),
+                                  (1.0, 10.0, 0.5, 2.0), (float("nan"), 10.0, 0.5, 1e-10)])
+def test_coeffs_invalid(rx, args):
+    lib = rx.load()
+    P = ctypes.c_int32()
+    st = lib.rexii_coeffs(*args, -1, ctypes.byref(P), None, None, None)
+    assert st == -1
+    assert "rexii_coeffs" in rx.last_error()
+
+
+def test_apply_rejects_bad_arguments_before_touching_the_device(rx):
+    lib = rx.load()
+    dummy = ctypes.c_void_p(16)       # never dereferenced: validation fails first
+    rep = rx.Report()
+    o = rx.make_opts()
+    for nx, ny, g, H in [(2, 8, 1.0, 1.0), (8, 3, 1.0, 1.0), (8, 8, 0.0, 1.0), (8, 8, 1.0, -1.0)]:
+        op = rx.make_op(nx, ny, g=g, H=H)
+        st = lib.rexii_apply(ctypes.byref(op), dummy, ctypes.c_void_p(1 << 20), 1.0, ctypes.byref(o),
+                             None, 0, None, ctypes.byref(rep))
+        assert st == -1, (nx, ny, g, H)
+    op = rx.make_op(8, 8)
+    assert lib.rexii_apply(None, dummy, dummy, 1.0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply(ctypes.byref(op), None, dummy, 1.0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply(ctypes.byref(op), dummy, ctypes.c_void_p(1 << 20), -1.0, None, None, 0, None, None) == -1
+
+
+def test_default_opts(rx):
+    o = rx.make_opts()
+    assert o.h == 0.5 and o.m0 == -1 and o.pair_conjugate == 1 and o.precision == 0

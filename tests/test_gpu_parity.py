@@ -1,0 +1,176 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: FP64 path rel-L2 <= 1e-10, mixed path <= 1e-6 (the target accuracies
+of the two precisions); per-pole resolvents <= 1e-10 at tol 1e-12."""
+import numpy as np
+import pytest
+
+from oracle import coeffs as oc
+from oracle import expm_modes as em
+from oracle import lrsw
+from oracle import rexii_modes as rm
+from paper_2008_11607_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2008_11607_amd import rexii
+    rexii.load()
+    return rexii
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(x):
+    return x.detach().cpu().numpy()
+
+
+def _case(nx, ny, trho, g=1.0, H=1.0, fc=10.0, nbumps=1, seed=1, velocity=False):
+    op = lrsw.LRSW(nx, ny, g=g, H=H, fc=fc)
+    rho = lrsw.rho(op)
+    t = trho / rho
+    f = inputs.gaussian_bumps(nx, ny, nbumps=nbumps, seed=seed, velocity=velocity)
+    return op, rho, t, f
+
+
+def test_shifted_solves_match_resolvents(rx):
+    op, rho, t, f = _case(72, 40, 80.0, g=1.3, H=0.8, fc=7.0, nbumps=3, seed=5, velocity=True)
+    c = oc.api_coeffs(t, rho, h=0.5, tol=1e-10)
+    idx = [0, 1, 40, 41, 121, len(c["z"]) - 1]
+    x, rep = rx.shifted_solve(_dev(f), t, c["z"][idx], g=op.g, fc=op.fc, H=op.H, tol=1e-12)
+    x = _host(x)
+    for j, k in enumerate(idx):
+        ref = rm.resolvent_modes(op, f, t, c["z"][k])
+        assert np.linalg.norm(x[j] - ref) <= 1e-10 * np.linalg.norm(ref), (k, c["z"][k])
+
+
+def test_apply_fp64_64_grid(rx):
+    # 64^2, f_c = 10, t rho = 100, one bump (sigma 0.05), FP64, tol 1e-10
+    op, rho, t, f = _case(64, 64, 100.0)
+    u, rep = rx.apply(_dev(f), t, fc=10.0)
+    assert rep["P"] == 468 and rep["not_converged"] == 0
+    ex = em.expm_closed_real(op, f, t)
+    c = oc.api_coeffs(t, rho, h=0.5, tol=1e-10)
+    assert em.rel_l2(_host(u), ex) <= 1e-10
+    assert em.rel_l2(_host(u), rm.rexii_spectral(op, f, t, c["z"], c["w"])) <= 1e-10
+
+
+@pytest.mark.parametrize("nx,ny", [(72, 40), (20, 12), (8, 8)])
+def test_apply_ragged_general_state(rx, nx, ny):
+    # grids that are not multiples of the 64 x 16 tile; non-zero velocities
+    # (unpaired solves); g != H
+    op, rho, t, f = _case(nx, ny, 60.0, g=1.3, H=0.8, fc=7.0, nbumps=3, seed=11, velocity=True)
+    u, rep = rx.apply(_dev(f), t, g=op.g, fc=op.fc, H=op.H)
+    assert rep["solves"] == rep["P"]
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
+def test_apply_small_grid_vs_dense_expm(rx):
+    op, rho, t, f = _case(12, 10, 25.0, g=2.0, H=0.5, fc=3.0, nbumps=2, seed=2, velocity=True)
+    u, _ = rx.apply(_dev(f), t, g=op.g, fc=op.fc, H=op.H)
+    assert em.rel_l2(_host(u), em.expm_dense(op, f, t)) <= 1e-10
+
+
+def test_pairing_matches_unpaired(rx):
+    op, rho, t, f = _case(96, 64, 150.0, nbumps=4, seed=3)
+    fd = _dev(f)
+    up, rp = rx.apply(fd, t, fc=10.0, pair_conjugate=1)
+    uu, ru = rx.apply(fd, t, fc=10.0, pair_conjugate=0)
+    assert rp["solves"] * 2 == rp["P"] and ru["solves"] == ru["P"]
+    assert em.rel_l2(_host(up), _host(uu)) <= 1e-11
+
+
+def test_zero_coriolis(rx):
+    op, rho, t, f = _case(32, 32, 40.0, fc=0.0, nbumps=2, seed=9, velocity=True)
+    u, _ = rx.apply(_dev(f), t, fc=0.0)
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
+@pytest.mark.parametrize("nx,trho", [(64, 100.0), (128, 300.0)])
+def test_apply_mixed(rx, nx, trho):
+    op, rho, t, f = _case(nx, nx, trho, nbumps=16, seed=2)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision="mixed")
+    assert rep["not_converged"] == 0
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-6
+
+
+def test_deterministic(rx):
+    op, rho, t, f = _case(64, 64, 100.0, nbumps=3, seed=4)
+    fd = _dev(f)
+    a, _ = rx.apply(fd, t, fc=10.0)
+    b, _ = rx.apply(fd, t, fc=10.0)
+    assert bool((a == b).all())
+    c, _ = rx.apply(fd, t, fc=10.0, precision="mixed")
+    d, _ = rx.apply(fd, t, fc=10.0, precision="mixed")
+    assert bool((c == d).all())
+
+
+def test_profile_mode_same_result(rx):
+    op, rho, t, f = _case(64, 64, 100.0, nbumps=3, seed=4)
+    fd = _dev(f)
+    a, _ = rx.apply(fd, t, fc=10.0)
+    b, rep = rx.apply(fd, t, fc=10.0, profile=1)
+    assert bool((a == b).all())
+    assert rep["up_launches"] > 0 and rep["up_ms"] > 0 and rep["up_bytes"] > 0
+
+
+def test_t_zero_copies(rx):
+    f = inputs.gaussian_bumps(16, nbumps=2, seed=1, velocity=True)
+    u, _ = rx.apply(_dev(f), 0.0)
+    assert np.array_equal(_host(u), f)
+
+
+def test_nonfinite_input(rx):
+    f = inputs.gaussian_bumps(16, nbumps=1, seed=1)
+    f[1, 3, 4] = np.nan
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(_dev(f), 0.5)
+    assert e.value.status == -2
+
+
+def test_iteration_cap_reports_not_converged(rx):
+    op, rho, t, f = _case(64, 64, 100.0)
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(_dev(f), t, fc=10.0, max_iter=5)
+    assert e.value.status == -3
+    assert e.value.report["not_converged"] > 0
+
+
+def test_caller_workspace(rx):
+    import torch
+    op, rho, t, f = _case(64, 64, 100.0, nbumps=2, seed=7)
+    nbytes = rx.workspace_size(64, 64, t, fc=10.0)
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    fd = _dev(f)
+    u = torch.empty_like(fd)
+    lib = rx.load()
+    import ctypes
+    opx = rx.make_op(64, 64, fc=10.0)
+    o = rx.make_opts()
+    rep = rx.Report()
+    st = lib.rexii_apply(ctypes.byref(opx), ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(u.data_ptr()), t,
+                         ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nbytes, rx._stream(), ctypes.byref(rep))
+    assert st == 0
+    ref, _ = rx.apply(fd, t, fc=10.0)
+    assert bool((u == ref).all())
+    st = lib.rexii_apply(ctypes.byref(opx), ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(u.data_ptr()), t,
+                         ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), 1024, rx._stream(), ctypes.byref(rep))
+    assert st == -7
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_apply_512_grid_full_size(rx, precision, bar):
+    # 512^2, t rho = 1000, 16 bumps (seed 2): the benchmark workload, every
+    # output compared with the exact exponential
+    op, rho, t, f = _case(512, 512, 1000.0, nbumps=16, seed=2)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision=precision)
+    assert rep["P"] == (4068 if precision == "fp64" else 4064)
+    assert rep["not_converged"] == 0
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= bar

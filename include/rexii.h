@@ -111,12 +111,16 @@ typedef struct rexii_report {
     double max_rel_residual; /* largest final FP64 relative residual        */
     double seconds;          /* host wall time of the call                  */
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
-    /* with opts.profile = 1: launches and summed event time of the two inner
-     * Krylov kernels, and their algorithmic bytes (every vector element they
-     * must read or write, once: 3 and 5 complex values per grid point) */
-    int64_t mv_launches, up_launches;
-    double mv_ms, up_ms;
-    double mv_bytes, up_bytes;
+    int32_t stagnated;       /* solves stopped at their FP64 residual floor
+                               (above pole_tol; counted as converged)       */
+    int32_t pad_;
+    /* with opts.profile = 1: launches and summed HIP-event time of the COCG
+     * pass kernel, and the algorithmic bytes of those launches (a pass reads
+     * x, r, p and writes them once: 6 complex values per grid point and
+     * live solve; 3 for the first pass after an FP64 residual) */
+    int64_t kernel_launches;
+    double kernel_ms;
+    double kernel_bytes;
 } rexii_report;
 
 /* Fill *opts with the defaults described above. */

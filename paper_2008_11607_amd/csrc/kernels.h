@@ -10,11 +10,23 @@
 //   sigma = t^2 g H z / den,  zeta = z / sigma,
 //   a1 = t H m1, a2 = t H m2,  eta_k = y_k / sigma_k,
 //   (u, v)_k = M_k ((u0, v0) + t g grad eta_k),  M = m1 I + m2 J, J(a,b) = (b,-a).
-// The solver runs COCG (conjugate orthogonal CG for complex-symmetric
-// matrices) on L - zeta_k, all poles of a batch at once ("slots"), with an
-// FP64 true-residual / refinement loop around inner iterations in FP64 or
-// FP32.  Weighted sums A0 = Re sum c0 y, A1 = Re sum c1 y, A2 = Re sum c2 y
-// are accumulated in FP64 and the output is rebuilt from them.
+//
+// Solver organisation ("slots"): B slots each hold one shifted system at a
+// time.  A slot runs COCG (conjugate orthogonal CG for complex-symmetric
+// matrices) on L - zeta in the inner precision T (FP32 or FP64), inside an
+// FP64 loop of true residuals and refinement.  When its solve is finished
+// the slot's solution is added, in FP64, to the three accumulators of its
+// problem (A0 = Re sum c0 y, A1 = Re sum c1 y, A2 = Re sum c2 y) and the slot
+// takes the next solve from the queue, so every launch works on B live
+// solves until the queue is empty.  Slots of one launch may belong to
+// different problems (grid sizes).
+//
+// One COCG iteration is one pass over x, r and p (the pass also forms
+// the next search direction, with beta from the recurrence
+// r'^T r' = r^T r - 2 alpha q^T r + alpha^2 q^T q), and each slot's scalars
+// are reduced by a one-block-per-slot kernel after the pass (a kernel
+// boundary makes the partial sums of all XCDs visible; a device-scope fence
+// per block would write back the whole L2 each time).
 #ifndef REXII_KERNELS_H
 #define REXII_KERNELS_H
 
@@ -23,96 +35,132 @@
 
 namespace rexii {
 
-// Tile of the stencil kernels: 64 x 16 points, 256 threads (64 x 4), each
-// thread handles 4 rows; LDS holds the tile plus a halo of 2.
+// Stencil tile: 64 x 16 points, 256 threads (64 x 4), 4 rows per thread.
 constexpr int kTX = 64;
 constexpr int kTY = 16;
 constexpr int kNT = 256;
-constexpr int kHalo = 2;
+constexpr int kNDots = 9;   // pq(2) qr(2) qq(2) rr(2) |r|^2(1)
 
 enum SlotStatus : int {
-  kIdle = 0,          // slot holds no pole
-  kOuterPending = 1,  // needs an FP64 residual (first one: the right-hand side)
-  kInner = 2,         // running inner Krylov iterations
+  kIdle = 0,          // slot holds no solve
+  kOuterPending = 1,  // needs an FP64 residual (the first one is the RHS)
+  kInner = 2,         // running inner Krylov passes
   kInnerDone = 3,     // inner solve finished: x64 += d, then a residual
-  kDone = 4,          // converged
+  kDone = 4,          // converged (waiting to be accumulated)
   kFailMaxIter = 5,   // stopped at max_iter (x64 holds the best iterate)
-  kFailBreakdown = 6, // p^T K p vanished or non-finite scalars
+  kFailBreakdown = 6, // non-finite scalars
+};
+
+// One problem (an initial state on a grid) of the launch.
+struct Inst {
+  int nx, ny, tiles_x, nblk;
+  double cx, cy;          // (nx/2)^2, (ny/2)^2
+  const double* eta0;     // [ny][nx]
+  const double* D0;       // div(u0, v0) or nullptr
+  const double* Z0;       // curl(u0, v0) or nullptr
+  double* A;              // accumulators [3][ny][nx]
+};
+
+// One shifted system (device table, read by the scheduler).
+struct SolveDev {
+  double2 zeta, a1, a2;   // shift and RHS coefficients
+  double2 c0, c1, c2;     // accumulation weights
+  double tol2;            // done when ||b - K x||^2 <= tol2 ||b||^2
+  int inst;
+  int pad;
+};
+
+// Per-solve outcome (for the report).
+struct SolveStat {
+  double rn2, bn2;
+  int it_total, rounds, status, stagnated;
 };
 
 struct Slot {
-  double2 zeta;     // Helmholtz shift of this pole
-  double2 a1, a2;   // RHS coefficients of div and curl of the initial velocity
-  double2 rr;       // r^T r of the inner iteration (bilinear, no conjugate)
+  double2 zeta, a1, a2;
+  double2 rr;        // r^T r of the current inner iterate
   double2 alpha, beta;
-  double bn2;       // ||b||^2
-  double rn2;       // latest FP64 true residual ||b - K x||^2
-  double in_tol2;   // inner stop: recursive ||r||^2 <= in_tol2
-  double tol2;      // done when rn2 <= tol2 * bn2
-  double inner_eta2;// relative reduction^2 of one inner solve
-  double prev_rn2;  // residual of the previous FP64 round (stagnation test)
+  double bn2;        // ||b||^2
+  double rn2;        // latest FP64 true residual ||b - K x||^2
+  double prev_rn2;   // residual of the previous FP64 round
+  double in_tol2;    // inner stop: recursive ||r||^2 <= in_tol2
+  double tol2;       // final relative tolerance^2 of this solve
   int status;
-  int parity;       // which search-direction buffer holds the current p
-  int it_total;     // inner iterations over all rounds
-  int it_inner;     // iterations of the current inner solve
-  int rounds;       // FP64 residual evaluations
+  int parity;        // which r/p buffers hold the current iterate
+  int prime;         // 1: next pass only forms p = r and its dots
+  int it_total;      // inner iterations over all rounds
+  int it_inner;
+  int rounds;        // FP64 residual evaluations
+  int solve;         // index into the SolveDev table
+  int inst;
+  int stagnated;
+  int pad;
+};
+
+// Everything the kernels of one engine need (passed by value).
+struct Eng {
+  int B;                 // slots
+  int S;                 // solves in the queue
+  int cap;               // points per slot vector (max over instances)
+  int cap_blk;           // partial-sum slots per slot (max tiles)
+  double inner_eta2;     // relative reduction^2 of one inner solve
   int max_iter;
-  int pole;         // index of the pole (or solve) in the problem
-  int stagnated;    // 1 if stopped at the FP64 rounding floor above tol
-};
-
-struct Geo {
-  int nx, ny;
-  int tiles_x, tiles_y, nblk;
-  double cx, cy;    // (nx/2)^2, (ny/2)^2: coefficients of dx dx and dy dy
-};
-
-// Buffers of one batch of B slots.  Vectors are [B][ny][nx].
-struct Batch {
-  int B;
-  Geo geo;
+  int pad;
   Slot* slots;           // [B]
-  double2* x64;          // FP64 solution
-  void* d;               // inner correction (T2)
-  void* r;               // inner residual (T2)
-  void* p0;              // search directions, ping-pong (T2)
+  const Inst* inst;      // [ninst]
+  const SolveDev* solves;// [S]
+  SolveStat* stats;      // [S]
+  int* next;             // [1] next solve to hand out
+  int* tile_start;       // [B + 1] exclusive prefix of tiles of working slots
+  int* counter;          // [4] host-visible counts
+  double* part;          // [B][cap_blk][kNDots]
+  double2* x64;          // [B][cap]
+  void* d;               // [B][cap] T2
+  void* r0;              // [B][cap] T2, ping-pong
+  void* r1;
+  void* p0;
   void* p1;
-  double2* part_a;       // [B][nblk] partial sums
-  double2* part_b;       // [B][nblk]
-  double* part_c;        // [B][nblk]
-  int* counter;          // [4] status counts read back by the host
+  double2* yout;         // nullptr: accumulate; else [S][cap] solutions
+  int* dbg;              // [16] consistency counters (debug builds only)
 };
 
-// Problem-wide inputs (device)
-struct Rhs {
-  const double* eta0;    // [ny][nx]
-  const double* D0;      // div(u0, v0) or nullptr
-  const double* Z0;      // curl(u0, v0) or nullptr
+// Per-pole bilinear dot of the depth derivative (adjoint): for a forward
+// Helmholtz solution y (pole with m1, m2, a1, a2, zeta, 1/sigma) and the
+// partner adjoint solution y',
+//   div = m1 D0 + m2 Z0 + t g m1 (r + zeta y) / sigma,  r = eta0 + a1 D0 + a2 Z0
+//   (the divergence of the pole's velocity: L eta = (r + zeta y) / sigma),
+//   dot = sum_points Y . div,  Y = (conj ? conj(y') : y') * ysc.
+struct AdjDot {
+  double2 m1, m2, a1, a2, zeta, isig, ysc;
+  int jf, ja;        // queue positions of the forward and adjoint solutions
+  int conj;
+  int pad;
 };
 
-// Launchers (kernels.hip).  T is float or double (inner precision).
 template <typename T>
-void launch_outer_update(const Batch& b, hipStream_t s);
+void launch_pass(const Eng& e, int grid, hipStream_t s);
 template <typename T>
-void launch_outer_residual(const Batch& b, const Rhs& rhs, hipStream_t s);
-void launch_scalars_outer(const Batch& b, hipStream_t s);
+void launch_outer_update(const Eng& e, int grid, hipStream_t s);
 template <typename T>
-void launch_inner_mv(const Batch& b, hipStream_t s);
-void launch_scalars_mv(const Batch& b, hipStream_t s);
-template <typename T>
-void launch_inner_up(const Batch& b, hipStream_t s);
-void launch_scalars_up(const Batch& b, hipStream_t s);
-void launch_count(const Batch& b, hipStream_t s);
+void launch_outer_residual(const Eng& e, int grid, hipStream_t s);
+void launch_pass_scalars(const Eng& e, hipStream_t s);
+void launch_outer_scalars(const Eng& e, hipStream_t s);
+void launch_retire(const Eng& e, hipStream_t s);
+void launch_assign(const Eng& e, hipStream_t s);
+void launch_count_finished(const Eng& e, hipStream_t s);
+int pass_occupancy(int mixed);
 void launch_fill_zero(double* p, size_t n, hipStream_t s);
 void launch_prep(const double* f, int nx, int ny, double* D0, double* Z0, int* flags, hipStream_t s);
-void launch_accumulate(const Batch& b, const double2* c0, const double2* c1, const double2* c2,
-                       int nslots, double* A, hipStream_t s);
 void launch_reconstruct(const double* f, const double* A, int nx, int ny, double S1, double S2,
                         double tg, int has_vel, double* u, hipStream_t s);
-void launch_expand(const Batch& b, const double* f, int nslots, const double2* inv_sigma,
-                   const double2* m1, const double2* m2, double tg, int has_vel,
-                   double2* out, hipStream_t s);
+void launch_expand(const double2* y, const double* f, int nx, int ny, double2 inv_sigma, double2 m1,
+                   double2 m2, double tg, int has_vel, double2* out, hipStream_t s);
 void launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
+void launch_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2, hipStream_t s);
+int adj_dot_blocks(size_t n);
+void launch_adj_dots(const AdjDot* d, int nd, const double2* yout, int cap, const double* eta0, const double* D0,
+                     const double* Z0, int nx, int ny, double tg, int has_vel, double2* part, int nblk,
+                     double2* out, hipStream_t s);
 
 }  // namespace rexii
 

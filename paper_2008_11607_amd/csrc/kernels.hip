@@ -1,7 +1,16 @@
 // gfx950 kernels of the REXII shifted-solve path (see kernels.h for the
-// mathematics).  All reductions are deterministic: every block writes one
-// partial in a fixed order, wavefront sums use xor-shuffles over the 64
-// lanes, and the per-slot scalar kernels add the partials in index order.
+// mathematics and the slot scheme).
+//
+// Determinism: every block writes its partial sums to a fixed place; the
+// last block of a slot adds them in index order; wavefront sums use a fixed
+// xor-shuffle tree over the 64 lanes.  Accumulation into the FP64 outputs
+// walks the slots in index order.  Results are therefore bitwise
+// reproducible for a given slot count and chunk length.
+//
+// Work mapping: the pass kernels are persistent (grid-stride) over work items
+// (slot, tile).  Work items are numbered so that each of the 8 XCDs (block b
+// runs on XCD b % 8) walks one contiguous range of tiles, keeping the halo
+// rows of neighbouring tiles in that XCD's L2.
 #include "kernels.h"
 
 namespace rexii {
@@ -36,10 +45,7 @@ __device__ __forceinline__ V csub(V a, V b) {
 }
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double den = b.x * b.x + b.y * b.y;
-  double2 r;
-  r.x = (a.x * b.x + a.y * b.y) / den;
-  r.y = (a.y * b.x - a.x * b.y) / den;
-  return r;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
 template <typename V>
 __device__ __forceinline__ V mk(double x, double y) {
@@ -48,14 +54,85 @@ __device__ __forceinline__ V mk(double x, double y) {
   r.y = static_cast<decltype(r.y)>(y);
   return r;
 }
+__device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+// streaming (non-temporal) access to complex values
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+#ifdef REXII_NO_NT
+__device__ __forceinline__ float2 nt_load(const float2* p) { return *p; }
+__device__ __forceinline__ double2 nt_load(const double2* p) { return *p; }
+__device__ __forceinline__ void nt_store(float2 a, float2* p) { *p = a; }
+__device__ __forceinline__ void nt_store(double2 a, double2* p) { *p = a; }
+#else
+__device__ __forceinline__ float2 nt_load(const float2* p) {
+  const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+  const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void nt_store(float2 a, float2* p) {
+  nf2 v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<nf2*>(p));
+}
+__device__ __forceinline__ void nt_store(double2 a, double2* p) {
+  nd2 v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<nd2*>(p));
+}
+#endif
+
+// Control data (slot state, tile table, counters, partial sums) is written
+// by one kernel and read by later ones.  Reads go through agent-scope
+// atomic loads: a plain uniform load may be served from the scalar cache,
+// which is not kept coherent with vector stores of earlier launches.
+__device__ __forceinline__ int ldc(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ double ldc(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ldc(const double2* p) { return make_double2(ldc(&p->x), ldc(&p->y)); }
+template <typename P>
+__device__ __forceinline__ P* ldc_ptr(P* const* p) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  return reinterpret_cast<P*>(v);
+}
+// Problem and solve tables are uploaded once per call into reused workspace
+// addresses: read them the same way.
+__device__ __forceinline__ Inst ld_inst(const Inst* p) {
+  Inst I;
+  I.nx = ldc(&p->nx);
+  I.ny = ldc(&p->ny);
+  I.tiles_x = ldc(&p->tiles_x);
+  I.nblk = ldc(&p->nblk);
+  I.cx = ldc(&p->cx);
+  I.cy = ldc(&p->cy);
+  I.eta0 = ldc_ptr(&p->eta0);
+  I.D0 = ldc_ptr(&p->D0);
+  I.Z0 = ldc_ptr(&p->Z0);
+  I.A = ldc_ptr(&p->A);
+  return I;
+}
 
 __device__ __forceinline__ int wrap(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
+// Periodic index for i in [-n, 2n): one conditional add or subtract.
+__device__ __forceinline__ int wrap1(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+// Either form, chosen once per tile (block-uniform): the single-step form
+// is exact when the tile with its halo is no larger than the grid.
+__device__ __forceinline__ int wrapc(int i, int n, bool big) { return big ? wrap1(i, n) : wrap(i, n); }
 
 // ---------------------------------------------------------------------------
-// deterministic block reductions (256 threads = 4 wavefronts of 64)
+// deterministic reductions (256 threads = 4 wavefronts of 64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -63,352 +140,541 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sums v over the block; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+// Reduces v[0..N) over the block into out[0..N) (valid in thread 0).
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh, double (&out)[N]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
   __syncthreads();
-  if (lane == 0) sh[wid] = v;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[wid * N + k] = v[k];
+  }
   __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  return s;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = (sh[k] + sh[N + k]) + (sh[2 * N + k] + sh[3 * N + k]);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// stencil tile in LDS: (kTY + 4) x (kTX + 4) complex values, periodic wrap
+// work items (slot, tile)
 // ---------------------------------------------------------------------------
-constexpr int kLW = kTX + 2 * kHalo;
-constexpr int kLH = kTY + 2 * kHalo;
+struct Item {
+  int slot, tile;
+};
 
-// (L - zeta) v at LDS position (ly, lx) (interior coordinates)
-template <typename V, typename S>
-__device__ __forceinline__ V helm(const V (*t)[kLW], int ly, int lx, S cx, S cy, V zeta, V* centre) {
-  const V c = t[ly + kHalo][lx + kHalo];
-  const V e = t[ly + kHalo][lx + kHalo + 2];
-  const V w = t[ly + kHalo][lx + kHalo - 2];
-  const V n = t[ly + kHalo + 2][lx + kHalo];
-  const V s = t[ly + kHalo - 2][lx + kHalo];
+// Position pos in [0, total) -> (slot, tile) by binary search in the
+// exclusive prefix sums ts[0..B].
+__device__ __forceinline__ Item item_of(const int* ts, int B, int pos) {
+  int lo = 0, hi = B;  // ts[lo] <= pos < ts[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ldc(&ts[mid]) <= pos) lo = mid;
+    else hi = mid;
+  }
+  Item it;
+  it.slot = lo;
+  it.tile = pos - ldc(&ts[lo]);
+  return it;
+}
+
+// XCD-major numbering: loop index w (block b handles w = b, b + G, ...)
+// runs on XCD w % 8 when G % 8 == 0; map it to position
+// (w % 8) * ceil(total / 8) + w / 8 so each XCD owns a contiguous range.
+#ifdef REXII_NO_XCD
+__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return w; }
+#else
+__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return (w & 7) * per_xcd + (w >> 3); }
+#endif
+
+// Stencil (L - zeta) v at LDS position (y, x) of a tile with row width W.
+template <typename V, typename S, int W>
+__device__ __forceinline__ V helm(const V* t, int y, int x, S cx, S cy, V zeta) {
+  const V c = t[y * W + x];
+  const V e = t[y * W + x + 2];
+  const V w = t[y * W + x - 2];
+  const V n = t[(y + 2) * W + x];
+  const V s = t[(y - 2) * W + x];
   V q;
   q.x = cx * (e.x + w.x - S(2) * c.x) + cy * (n.x + s.x - S(2) * c.x) - (zeta.x * c.x - zeta.y * c.y);
   q.y = cx * (e.y + w.y - S(2) * c.y) + cy * (n.y + s.y - S(2) * c.y) - (zeta.x * c.y + zeta.y * c.x);
-  *centre = c;
   return q;
 }
 
-struct TileIdx {
-  int x0, y0;
-};
-__device__ __forceinline__ TileIdx tile_of(const Geo& g) {
-  TileIdx t;
-  t.x0 = (blockIdx.x % g.tiles_x) * kTX;
-  t.y0 = (blockIdx.x / g.tiles_x) * kTY;
-  return t;
+// ---------------------------------------------------------------------------
+// The COCG pass.  Input (x_i = d, r_i, p_i) with alpha_i, beta_i known:
+//   q_i = (L - zeta) p_i                      (tile + halo 2, from p with halo 4)
+//   d  += alpha_i p_i,  r_{i+1} = r_i - alpha_i q_i,  p_{i+1} = r_{i+1} + beta_i p_i
+//   q_{i+1} = (L - zeta) p_{i+1}              (tile)
+//   partial sums: p_{i+1}^T q_{i+1}, q_{i+1}^T r_{i+1}, q_{i+1}^T q_{i+1},
+//                 r_{i+1}^T r_{i+1}, |r_{i+1}|^2
+// The last block of the slot then sets alpha_{i+1} = rr_{i+1} / pq_{i+1} and
+// beta_{i+1} = (rr_{i+1} - 2 alpha qr + alpha^2 qq) / rr_{i+1}.
+// A "prime" pass (after an FP64 residual) only sets p = r and its sums.
+// ---------------------------------------------------------------------------
+constexpr int kPW = kTX + 8, kPH = kTY + 8;   // p tile with halo 4
+constexpr int kNW = kTX + 4, kNH = kTY + 4;   // p_{i+1} tile with halo 2
+constexpr int kRing = kNW * kNH - kTX * kTY;  // halo-2 ring points
+
+__device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
+  // rows 0,1 and kNH-2, kNH-1 (full width), then columns 0,1,kNW-2,kNW-1
+  if (e < 2 * kNW) {
+    y = e / kNW;
+    x = e - y * kNW;
+  } else if (e < 4 * kNW) {
+    e -= 2 * kNW;
+    y = kNH - 2 + e / kNW;
+    x = e - (e / kNW) * kNW;
+  } else {
+    e -= 4 * kNW;
+    y = 2 + (e >> 2);
+    const int c = e & 3;
+    x = (c < 2) ? c : kNW - 4 + c;
+  }
 }
 
-// ---------------------------------------------------------------------------
-// inner COCG: p_new = r + beta p_old, partial sums of p_new^T (L - zeta) p_new
-// ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_inner_mv(Batch b) {
+__global__ __launch_bounds__(kNT) void k_pass(Eng e) {
   using V = typename C2<T>::t;
-  const int slot = blockIdx.y;
-  Slot* S = &b.slots[slot];
-  if (S->status != kInner) return;
-  const Geo g = b.geo;
-  const size_t n = size_t(g.nx) * g.ny;
-  const V* r = reinterpret_cast<const V*>(b.r) + slot * n;
-  const int parity = S->parity;
-  const V* pold = reinterpret_cast<const V*>(parity ? b.p1 : b.p0) + slot * n;
-  V* pnew = reinterpret_cast<V*>(parity ? b.p0 : b.p1) + slot * n;
-  const bool first = (S->it_inner == 0);
-  const V beta = mk<V>(S->beta.x, S->beta.y);
-  const V zeta = mk<V>(S->zeta.x, S->zeta.y);
+  __shared__ V PT[kPH * kPW];
+  __shared__ V PN[kNH * kNW];
+  __shared__ double red[4 * kNDots];
 
-  __shared__ V tile[kLH][kLW];
-  __shared__ double red[8];
-  const TileIdx ti = tile_of(g);
-  for (int e = threadIdx.x; e < kLH * kLW; e += kNT) {
-    const int ly = e / kLW, lx = e - ly * kLW;
-    const size_t gi = size_t(wrap(ti.y0 - kHalo + ly, g.ny)) * g.nx + wrap(ti.x0 - kHalo + lx, g.nx);
-    V v = r[gi];
-    if (!first) v = cadd(v, cmul(beta, pold[gi]));
-    tile[ly][lx] = v;
-  }
-  __syncthreads();
+  const int total = ldc(&e.tile_start[e.B]);
+  const int per = (total + 7) >> 3;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const T cx = T(g.cx), cy = T(g.cy);
-  T ar = 0, ai = 0;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e.tile_start, e.B, pos);
+    Slot* S = &e.slots[it.slot];
+#ifdef REXII_DEBUG_CHECKS
+    {
+      const int tot_fresh = __hip_atomic_load(&e.tile_start[e.B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0 && tot_fresh != total) atomicAdd(&e.dbg[4], 1);
+      if (threadIdx.x == 0 && it.tile >= e.inst[S->inst].nblk) atomicAdd(&e.dbg[5], 1);
+    }
+    if (it.tile >= e.inst[S->inst].nblk) continue;
+    {
+      __shared__ int seen[4];
+      __syncthreads();
+      if (threadIdx.x == 0) { seen[0] = S->status; seen[1] = S->parity; seen[2] = S->prime; }
+      __syncthreads();
+      if (S->status != seen[0] || S->parity != seen[1] || S->prime != seen[2]) atomicAdd(&e.dbg[0], 1);
+      __syncthreads();
+    }
+#endif
+    if (ldc(&S->status) != kInner) continue;
+    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
+    const size_t base = size_t(it.slot) * e.cap;
+    const int par = ldc(&S->parity);
+    const V* rs = reinterpret_cast<const V*>(par ? e.r1 : e.r0) + base;
+    V* rd = reinterpret_cast<V*>(par ? e.r0 : e.r1) + base;
+    const V* ps = reinterpret_cast<const V*>(par ? e.p1 : e.p0) + base;
+    V* pd = reinterpret_cast<V*>(par ? e.p0 : e.p1) + base;
+    V* d = reinterpret_cast<V*>(e.d) + base;
+    const bool prime = ldc(&S->prime) != 0;
+    const double2 al2 = ldc(&S->alpha), be2 = ldc(&S->beta), ze2 = ldc(&S->zeta);
+    const V alpha = mk<V>(al2.x, al2.y);
+    const V beta = mk<V>(be2.x, be2.y);
+    const V zeta = mk<V>(ze2.x, ze2.y);
+    const T cx = T(I.cx), cy = T(I.cy);
+    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
+    const bool big = (I.nx >= kPW) && (I.ny >= kPH);
+
+    // issue the interior and ring loads of r and d before the p tile
+    // barrier so their latency overlaps the tile load
+    size_t gi[kTY / 4];
+    V rv[kTY / 4], dv[kTY / 4];
 #pragma unroll
-  for (int k = 0; k < kTY / 4; ++k) {
-    const int ly = ty + 4 * k;
-    const int gx = ti.x0 + tx, gy = ti.y0 + ly;
-    if (gx < g.nx && gy < g.ny) {
-      V c;
-      const V q = helm<V, T>(tile, ly, tx, cx, cy, zeta, &c);
-      pnew[size_t(gy) * g.nx + gx] = c;
-      ar += c.x * q.x - c.y * q.y;
-      ai += c.x * q.y + c.y * q.x;
+    for (int j = 0; j < kTY / 4; ++j) {
+      gi[j] = size_t(wrapc(y0 + ty + 4 * j, I.ny, big)) * I.nx + wrapc(x0 + tx, I.nx, big);
+      rv[j] = rs[gi[j]];
+      if (!prime) dv[j] = nt_load(&d[gi[j]]);
     }
-  }
-  const double sr = block_sum(double(ar), red);
-  const double si = block_sum(double(ai), red + 4);
-  if (threadIdx.x == 0) b.part_a[size_t(slot) * g.nblk + blockIdx.x] = make_double2(sr, si);
-}
-
-// d += alpha p, r -= alpha (L - zeta) p; partial sums of r^T r and |r|^2
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_inner_up(Batch b) {
-  using V = typename C2<T>::t;
-  const int slot = blockIdx.y;
-  Slot* S = &b.slots[slot];
-  if (S->status != kInner) return;
-  const Geo g = b.geo;
-  const size_t n = size_t(g.nx) * g.ny;
-  const int parity = S->parity;
-  const V* p = reinterpret_cast<const V*>(parity ? b.p0 : b.p1) + slot * n;
-  V* r = reinterpret_cast<V*>(b.r) + slot * n;
-  V* d = reinterpret_cast<V*>(b.d) + slot * n;
-  const V alpha = mk<V>(S->alpha.x, S->alpha.y);
-  const V zeta = mk<V>(S->zeta.x, S->zeta.y);
-
-  __shared__ V tile[kLH][kLW];
-  __shared__ double red[12];
-  const TileIdx ti = tile_of(g);
-  for (int e = threadIdx.x; e < kLH * kLW; e += kNT) {
-    const int ly = e / kLW, lx = e - ly * kLW;
-    const size_t gi = size_t(wrap(ti.y0 - kHalo + ly, g.ny)) * g.nx + wrap(ti.x0 - kHalo + lx, g.nx);
-    tile[ly][lx] = p[gi];
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const T cx = T(g.cx), cy = T(g.cy);
-  T ar = 0, ai = 0, an = 0;
+    constexpr int kRingPerThread = (kRing + kNT - 1) / kNT;
+    V rr_[kRingPerThread];
+    int rly[kRingPerThread], rlx[kRingPerThread];
 #pragma unroll
-  for (int k = 0; k < kTY / 4; ++k) {
-    const int ly = ty + 4 * k;
-    const int gx = ti.x0 + tx, gy = ti.y0 + ly;
-    if (gx < g.nx && gy < g.ny) {
-      V c;
-      const V q = helm<V, T>(tile, ly, tx, cx, cy, zeta, &c);
-      const size_t gi = size_t(gy) * g.nx + gx;
-      d[gi] = cadd(d[gi], cmul(alpha, c));
-      const V rn = csub(r[gi], cmul(alpha, q));
-      r[gi] = rn;
-      ar += rn.x * rn.x - rn.y * rn.y;
-      ai += T(2) * rn.x * rn.y;
-      an += rn.x * rn.x + rn.y * rn.y;
-    }
-  }
-  const double sr = block_sum(double(ar), red);
-  const double si = block_sum(double(ai), red + 4);
-  const double sn = block_sum(double(an), red + 8);
-  if (threadIdx.x == 0) {
-    b.part_a[size_t(slot) * g.nblk + blockIdx.x] = make_double2(sr, si);
-    b.part_c[size_t(slot) * g.nblk + blockIdx.x] = sn;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 outer step: x64 += d (after an inner solve) ...
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_outer_update(Batch b) {
-  using V = typename C2<T>::t;
-  const int slot = blockIdx.y;
-  const Slot* S = &b.slots[slot];
-  if (S->status != kInnerDone) return;
-  const Geo g = b.geo;
-  const size_t n = size_t(g.nx) * g.ny;
-  const V* d = reinterpret_cast<const V*>(b.d) + slot * n;
-  double2* x = b.x64 + slot * n;
-  const TileIdx ti = tile_of(g);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int k = 0; k < kTY / 4; ++k) {
-    const int gx = ti.x0 + tx, gy = ti.y0 + ty + 4 * k;
-    if (gx < g.nx && gy < g.ny) {
-      const size_t gi = size_t(gy) * g.nx + gx;
-      const V dv = d[gi];
-      double2 xv = x[gi];
-      xv.x += double(dv.x);
-      xv.y += double(dv.y);
-      x[gi] = xv;
-    }
-  }
-}
-
-// ... then r64 = b - (L - zeta) x64 in FP64; r = (T) r64, d = 0;
-// partial sums |r64|^2 (part_c) and r^T r of the rounded r (part_a).
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_outer_residual(Batch b, Rhs rhs) {
-  using V = typename C2<T>::t;
-  const int slot = blockIdx.y;
-  const Slot* S = &b.slots[slot];
-  if (S->status != kInnerDone && S->status != kOuterPending) return;
-  const Geo g = b.geo;
-  const size_t n = size_t(g.nx) * g.ny;
-  const double2* x = b.x64 + slot * n;
-  V* r = reinterpret_cast<V*>(b.r) + slot * n;
-  V* d = reinterpret_cast<V*>(b.d) + slot * n;
-  const double2 zeta = S->zeta, a1 = S->a1, a2 = S->a2;
-  const bool zero_x = (S->rounds == 0);
-
-  __shared__ double2 tile[kLH][kLW];
-  __shared__ double red[12];
-  const TileIdx ti = tile_of(g);
-  if (!zero_x) {
-    for (int e = threadIdx.x; e < kLH * kLW; e += kNT) {
-      const int ly = e / kLW, lx = e - ly * kLW;
-      const size_t gi = size_t(wrap(ti.y0 - kHalo + ly, g.ny)) * g.nx + wrap(ti.x0 - kHalo + lx, g.nx);
-      tile[ly][lx] = x[gi];
-    }
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  double ar = 0, ai = 0, an = 0;
-#pragma unroll
-  for (int k = 0; k < kTY / 4; ++k) {
-    const int ly = ty + 4 * k;
-    const int gx = ti.x0 + tx, gy = ti.y0 + ly;
-    if (gx < g.nx && gy < g.ny) {
-      const size_t gi = size_t(gy) * g.nx + gx;
-      double2 bv = make_double2(rhs.eta0[gi], 0.0);
-      if (rhs.D0) {
-        const double dv = rhs.D0[gi], zv = rhs.Z0[gi];
-        bv.x += a1.x * dv + a2.x * zv;
-        bv.y += a1.y * dv + a2.y * zv;
+    for (int m = 0; m < kRingPerThread; ++m) {
+      const int k = threadIdx.x + m * kNT;
+      rly[m] = -1;
+      if (k < kRing) {
+        ring_pos(k, rly[m], rlx[m]);
+        rr_[m] = rs[size_t(wrapc(y0 - 2 + rly[m], I.ny, big)) * I.nx + wrapc(x0 - 2 + rlx[m], I.nx, big)];
       }
-      double2 rv = bv;
-      if (!zero_x) {
-        double2 c;
-        const double2 q = helm<double2, double>(tile, ly, tx, g.cx, g.cy, zeta, &c);
-        rv = csub(bv, q);
+    }
+    __syncthreads();  // LDS of the previous work item is free
+    if (!prime) {
+      for (int k = threadIdx.x; k < kPH * kPW; k += kNT) {
+        const int ly = k / kPW, lx = k - ly * kPW;
+        PT[k] = ps[size_t(wrapc(y0 - 4 + ly, I.ny, big)) * I.nx + wrapc(x0 - 4 + lx, I.nx, big)];
       }
-      const V rt = mk<V>(rv.x, rv.y);
-      r[gi] = rt;
-      d[gi] = mk<V>(0.0, 0.0);
-      an += rv.x * rv.x + rv.y * rv.y;
-      const double tr = double(rt.x), tim = double(rt.y);
-      ar += tr * tr - tim * tim;
-      ai += 2.0 * tr * tim;
+    }
+    __syncthreads();
+    // interior: rows ty + 4j, column tx
+    V rn[kTY / 4], pn[kTY / 4];
+#pragma unroll
+    for (int j = 0; j < kTY / 4; ++j) {
+      const int ly = ty + 4 * j;
+      const bool in = (x0 + tx < I.nx) && (y0 + ly < I.ny);
+      V r1 = rv[j], p1 = rv[j];
+      if (!prime) {
+        const V pc = PT[(ly + 4) * kPW + tx + 4];
+        const V q = helm<V, T, kPW>(PT, ly + 4, tx + 4, cx, cy, zeta);
+        r1 = csub(rv[j], cmul(alpha, q));
+        p1 = cadd(r1, cmul(beta, pc));
+        if (in) nt_store(cadd(dv[j], cmul(alpha, pc)), &d[gi[j]]);
+      }
+      PN[(ly + 2) * kNW + tx + 2] = p1;
+      if (in) {
+        rd[gi[j]] = r1;
+        pd[gi[j]] = p1;
+      }
+      rn[j] = r1;
+      pn[j] = p1;
+    }
+    // halo ring of p_{i+1}
+#pragma unroll
+    for (int m = 0; m < kRingPerThread; ++m) {
+      if (rly[m] < 0) continue;
+      const int ly = rly[m], lx = rlx[m];
+      V p1 = rr_[m];
+      if (!prime) {
+        const V pc = PT[(ly + 2) * kPW + lx + 2];
+        const V q = helm<V, T, kPW>(PT, ly + 2, lx + 2, cx, cy, zeta);
+        p1 = cadd(csub(rr_[m], cmul(alpha, q)), cmul(beta, pc));
+      }
+      PN[ly * kNW + lx] = p1;
+    }
+    __syncthreads();
+    double s[kNDots];
+#pragma unroll
+    for (int k = 0; k < kNDots; ++k) s[k] = 0.0;
+    // dot products accumulated in FP64 (the beta recurrence cancels)
+#pragma unroll
+    for (int j = 0; j < kTY / 4; ++j) {
+      const int ly = ty + 4 * j;
+      if (x0 + tx < I.nx && y0 + ly < I.ny) {
+        const V qv = helm<V, T, kNW>(PN, ly + 2, tx + 2, cx, cy, zeta);
+        const double px = pn[j].x, py = pn[j].y, rx = rn[j].x, ry = rn[j].y, qx = qv.x, qy = qv.y;
+        s[0] += px * qx - py * qy;
+        s[1] += px * qy + py * qx;
+        s[2] += qx * rx - qy * ry;
+        s[3] += qx * ry + qy * rx;
+        s[4] += qx * qx - qy * qy;
+        s[5] += 2.0 * qx * qy;
+        s[6] += rx * rx - ry * ry;
+        s[7] += 2.0 * rx * ry;
+        s[8] += rx * rx + ry * ry;
+      }
+    }
+    double tot[kNDots];
+    block_sum_n<kNDots>(s, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
+#pragma unroll
+      for (int k = 0; k < kNDots; ++k) pp[k] = tot[k];
     }
   }
-  const double sr = block_sum(ar, red);
-  const double si = block_sum(ai, red + 4);
-  const double sn = block_sum(an, red + 8);
-  if (threadIdx.x == 0) {
-    b.part_a[size_t(slot) * g.nblk + blockIdx.x] = make_double2(sr, si);
-    b.part_c[size_t(slot) * g.nblk + blockIdx.x] = sn;
+}
+
+// One block per slot after each pass: add the partial sums of the slot's
+// tiles in index order and set alpha_{i+1}, beta_{i+1} (or end the inner
+// solve).
+__global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
+  __shared__ double red[4 * kNDots];
+  Slot* S = &e.slots[blockIdx.x];
+  if (ldc(&S->status) != kInner) return;
+  const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
+  double v[kNDots], tot[kNDots];
+#pragma unroll
+  for (int k = 0; k < kNDots; ++k) v[k] = 0.0;
+  const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
+  for (int b = threadIdx.x; b < nblk; b += kNT) {
+#pragma unroll
+    for (int k = 0; k < kNDots; ++k) v[k] += ldc(&pp[size_t(b) * kNDots + k]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// per-slot scalar kernels: one block per slot, partials added in index order
-// ---------------------------------------------------------------------------
-__device__ double2 reduce_parts2(const double2* p, int m, double* sh) {
-  double sx = 0.0, sy = 0.0;
-  for (int i = threadIdx.x; i < m; i += kNT) {
-    sx += p[i].x;
-    sy += p[i].y;
-  }
-  const double rx = block_sum(sx, sh);
-  const double ry = block_sum(sy, sh + 4);
-  return make_double2(rx, ry);
-}
-__device__ double reduce_parts1(const double* p, int m, double* sh) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += kNT) s += p[i];
-  return block_sum(s, sh);
-}
-
-__device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
-
-__global__ __launch_bounds__(kNT) void k_scalars_outer(Batch b) {
-  const int slot = blockIdx.x;
-  Slot* S = &b.slots[slot];
-  const int st = S->status;
-  if (st != kInnerDone && st != kOuterPending) return;
-  __shared__ double sh[12];
-  const int m = b.geo.nblk;
-  const double2 rr = reduce_parts2(b.part_a + size_t(slot) * m, m, sh);
-  const double rn2 = reduce_parts1(b.part_c + size_t(slot) * m, m, sh + 8);
+  block_sum_n<kNDots>(v, red, tot);
   if (threadIdx.x != 0) return;
-  if (S->rounds == 0) S->bn2 = rn2;
-  S->rounds += 1;
-  const double prev = S->prev_rn2;
+  const double2 pq = make_double2(tot[0], tot[1]);
+  const double2 qr = make_double2(tot[2], tot[3]);
+  const double2 qq = make_double2(tot[4], tot[5]);
+  const double2 rr = make_double2(tot[6], tot[7]);
+  const double n2 = tot[8];
+  const bool prime = ldc(&S->prime) != 0;
+  S->parity = ldc(&S->parity) ^ 1;
+  int it_total = ldc(&S->it_total);
+  if (!prime) {
+    S->it_inner = ldc(&S->it_inner) + 1;
+    it_total += 1;
+    S->it_total = it_total;
+  }
+  S->prime = 0;
+  const bool ok = isfinite(n2) && finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) &&
+                  (fabs(pq.x) + fabs(pq.y) > 0.0) && (fabs(rr.x) + fabs(rr.y) > 0.0);
+  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
+    S->status = kInnerDone;
+  } else {
+    const double2 al = cdiv(rr, pq);
+    // rr_{i+2} = rr - 2 alpha qr + alpha^2 qq
+    const double2 a2 = make_double2(al.x * al.x - al.y * al.y, 2.0 * al.x * al.y);
+    const double2 aqr = make_double2(al.x * qr.x - al.y * qr.y, al.x * qr.y + al.y * qr.x);
+    const double2 aqq = make_double2(a2.x * qq.x - a2.y * qq.y, a2.x * qq.y + a2.y * qq.x);
+    const double2 rr2 = make_double2(rr.x - 2.0 * aqr.x + aqq.x, rr.y - 2.0 * aqr.y + aqq.y);
+    S->alpha = al;
+    S->beta = cdiv(rr2, rr);
+    S->rr = rr;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 outer steps
+// ---------------------------------------------------------------------------
+// x64 += d for slots whose inner solve finished
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_outer_update(Eng e) {
+  using V = typename C2<T>::t;
+  const int total = ldc(&e.tile_start[e.B]);
+  const int per = (total + 7) >> 3;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e.tile_start, e.B, pos);
+    const Slot* S = &e.slots[it.slot];
+    if (ldc(&S->status) != kInnerDone) continue;
+    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
+    const size_t base = size_t(it.slot) * e.cap;
+    const V* d = reinterpret_cast<const V*>(e.d) + base;
+    double2* x = e.x64 + base;
+    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
+    for (int j = 0; j < kTY / 4; ++j) {
+      const int gx = x0 + tx, gy = y0 + ty + 4 * j;
+      if (gx < I.nx && gy < I.ny) {
+        const size_t gi = size_t(gy) * I.nx + gx;
+        const V dv = d[gi];
+        double2 xv = x[gi];
+        xv.x += double(dv.x);
+        xv.y += double(dv.y);
+        x[gi] = xv;
+      }
+    }
+  }
+}
+
+// r64 = b - (L - zeta) x64 in FP64; r = (T) r64 into the current r buffer,
+// d = 0.  The last block of a slot decides: done, failed, or a new inner
+// solve (prime pass next).
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_outer_residual(Eng e) {
+  using V = typename C2<T>::t;
+  constexpr int W = kTX + 4, H = kTY + 4;
+  __shared__ double2 XT[H * W];
+  __shared__ double red[4 * 2];
+  const int total = ldc(&e.tile_start[e.B]);
+  const int per = (total + 7) >> 3;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e.tile_start, e.B, pos);
+    Slot* S = &e.slots[it.slot];
+    const int st = ldc(&S->status);
+    if (st != kInnerDone && st != kOuterPending) continue;
+    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
+    const size_t base = size_t(it.slot) * e.cap;
+    const double2* x = e.x64 + base;
+    V* r = reinterpret_cast<V*>(ldc(&S->parity) ? e.r1 : e.r0) + base;
+    V* d = reinterpret_cast<V*>(e.d) + base;
+    const double2 zeta = ldc(&S->zeta), a1 = ldc(&S->a1), a2 = ldc(&S->a2);
+    const bool zero_x = (ldc(&S->rounds) == 0);
+    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
+    const bool big = (I.nx >= W) && (I.ny >= H);
+    __syncthreads();
+    if (!zero_x) {
+      for (int k = threadIdx.x; k < H * W; k += kNT) {
+        const int ly = k / W, lx = k - ly * W;
+        XT[k] = x[size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big)];
+      }
+    }
+    __syncthreads();
+    double s[2] = {0.0, 0.0};
+    for (int j = 0; j < kTY / 4; ++j) {
+      const int ly = ty + 4 * j;
+      const int gx = x0 + tx, gy = y0 + ly;
+      if (gx < I.nx && gy < I.ny) {
+        const size_t gi = size_t(gy) * I.nx + gx;
+        double2 bv = make_double2(I.eta0[gi], 0.0);
+        if (I.D0) {
+          const double dv = I.D0[gi], zv = I.Z0[gi];
+          bv.x += a1.x * dv + a2.x * zv;
+          bv.y += a1.y * dv + a2.y * zv;
+        }
+        double2 rv = bv;
+#ifdef REXII_DEBUG_CHECKS
+        if (zero_x && (x[gi].x != 0.0 || x[gi].y != 0.0)) atomicAdd(&e.dbg[3], 1);
+#endif
+        if (!zero_x) rv = csub(bv, helm<double2, double, W>(XT, ly + 2, tx + 2, I.cx, I.cy, zeta));
+        r[gi] = mk<V>(rv.x, rv.y);
+        d[gi] = mk<V>(0.0, 0.0);
+        s[0] += rv.x * rv.x + rv.y * rv.y;
+      }
+    }
+    double tot[2];
+    block_sum_n<2>(s, red, tot);
+    if (threadIdx.x == 0) e.part[(size_t(it.slot) * e.cap_blk + it.tile) * kNDots] = tot[0];
+  }
+}
+
+// One block per slot after the FP64 residual: done, failed, or a new inner
+// solve (prime pass next).
+__global__ __launch_bounds__(kNT) void k_outer_scalars(Eng e) {
+  __shared__ double red[4 * 2];
+  Slot* S = &e.slots[blockIdx.x];
+  const int st = ldc(&S->status);
+  if (st != kInnerDone && st != kOuterPending) return;
+  const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
+  double v[2] = {0.0, 0.0}, tot[2];
+  const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
+  for (int b = threadIdx.x; b < nblk; b += kNT) v[0] += ldc(&pp[size_t(b) * kNDots]);
+  block_sum_n<2>(v, red, tot);
+  if (threadIdx.x != 0) return;
+  const double rn2 = tot[0];
+  const int rounds0 = ldc(&S->rounds);
+  double bn2 = ldc(&S->bn2);
+  if (rounds0 == 0) {
+    bn2 = rn2;
+    S->bn2 = rn2;
+  }
+  const int rounds = rounds0 + 1;
+  S->rounds = rounds;
+  const double prev = ldc(&S->prev_rn2);
+  const double tol2 = ldc(&S->tol2);
   S->rn2 = rn2;
   S->prev_rn2 = rn2;
-  if (!isfinite(rn2) || !finite2(rr)) {
+  if (!isfinite(rn2)) {
     S->status = kFailBreakdown;
-  } else if (rn2 <= S->tol2 * S->bn2) {
+  } else if (rn2 <= tol2 * bn2) {
     S->status = kDone;
-  } else if (S->rounds >= 3 && rn2 > 0.25 * prev) {
-    // a whole inner solve did not halve the true residual: the FP64
-    // rounding floor of the residual is above the requested tolerance
+  } else if (rounds >= 3 && rn2 > 0.25 * prev) {
+    // a whole inner solve did not halve the FP64 residual: it sits at its
+    // rounding floor, above the requested tolerance
     S->status = kDone;
     S->stagnated = 1;
-  } else if (S->it_total >= S->max_iter) {
+  } else if (ldc(&S->it_total) >= e.max_iter) {
     S->status = kFailMaxIter;
   } else {
     S->status = kInner;
-    S->rr = rr;
+    S->prime = 1;
     S->it_inner = 0;
+    S->alpha = make_double2(0.0, 0.0);
     S->beta = make_double2(0.0, 0.0);
-    // inner target: the requested reduction of this residual, but never
-    // below a quarter of the final tolerance
-    S->in_tol2 = fmax(S->inner_eta2 * rn2, 0.0625 * S->tol2 * S->bn2);
+    // the requested reduction of this residual, never below a quarter of
+    // the final tolerance
+    S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
   }
 }
 
-__global__ __launch_bounds__(kNT) void k_scalars_mv(Batch b) {
-  const int slot = blockIdx.x;
-  Slot* S = &b.slots[slot];
-  if (S->status != kInner) return;
-  __shared__ double sh[8];
-  const int m = b.geo.nblk;
-  const double2 pq = reduce_parts2(b.part_a + size_t(slot) * m, m, sh);
-  if (threadIdx.x != 0) return;
-  const double mag = fabs(pq.x) + fabs(pq.y);
-  if (!(mag > 0.0) || !finite2(pq)) {
-    // breakdown of the bilinear form: hand the slot back to the FP64
-    // residual step, which restarts the iteration from the true residual
-    S->status = (S->it_inner == 0) ? kFailBreakdown : kInnerDone;
-    return;
-  }
-  S->alpha = cdiv(S->rr, pq);
+// ---------------------------------------------------------------------------
+// scheduler
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool finished(int st) {
+  return st == kDone || st == kFailMaxIter || st == kFailBreakdown;
 }
 
-__global__ __launch_bounds__(kNT) void k_scalars_up(Batch b) {
-  const int slot = blockIdx.x;
-  Slot* S = &b.slots[slot];
-  if (S->status != kInner) return;
-  __shared__ double sh[12];
-  const int m = b.geo.nblk;
-  const double2 rr = reduce_parts2(b.part_a + size_t(slot) * m, m, sh);
-  const double rn2 = reduce_parts1(b.part_c + size_t(slot) * m, m, sh + 8);
-  if (threadIdx.x != 0) return;
-  S->parity ^= 1;
-  S->it_inner += 1;
-  S->it_total += 1;
-  const bool ok = isfinite(rn2) && finite2(rr) && (fabs(S->rr.x) + fabs(S->rr.y) > 0.0);
-  if (ok) S->beta = cdiv(rr, S->rr);
-  S->rr = rr;
-  if (!ok || rn2 <= S->in_tol2 || S->it_total >= S->max_iter) S->status = kInnerDone;
+// Finished slots: A[inst] += Re(c_j x64) (or copy x64 out), then x64 = 0.
+// Each point walks the slots in index order.
+__global__ void k_retire(Eng e) {
+  if (ldc(&e.counter[3]) == 0) return;  // nothing finished in the previous chunk
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < e.cap; i += gridDim.x * blockDim.x) {
+    for (int s = 0; s < e.B; ++s) {
+      const Slot* S = &e.slots[s];
+      if (!finished(ldc(&S->status))) continue;
+      const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
+      const int n = I.nx * I.ny;
+      if (i >= n) continue;
+      double2* xp = e.x64 + size_t(s) * e.cap + i;
+      const double2 x = *xp;
+      const int sv = ldc(&S->solve);
+      if (e.yout) e.yout[size_t(sv) * e.cap + i] = x;
+      const double2 c0 = ldc(&e.solves[sv].c0), c1 = ldc(&e.solves[sv].c1), c2 = ldc(&e.solves[sv].c2);
+      I.A[i] += c0.x * x.x - c0.y * x.y;
+      I.A[n + i] += c1.x * x.x - c1.y * x.y;
+      I.A[2 * n + i] += c2.x * x.x - c2.y * x.y;
+      *xp = make_double2(0.0, 0.0);
+    }
+  }
 }
 
-__global__ void k_count(Batch b) {
-  // counter[0]: slots still working; [1]: done; [2]: failed
-  __shared__ int c[3];
-  if (threadIdx.x < 3) c[threadIdx.x] = 0;
-  __syncthreads();
-  for (int s = threadIdx.x; s < b.B; s += blockDim.x) {
-    const int st = b.slots[s].status;
-    if (st == kOuterPending || st == kInner || st == kInnerDone) atomicAdd(&c[0], 1);
-    else if (st == kDone) atomicAdd(&c[1], 1);
-    else if (st == kFailMaxIter || st == kFailBreakdown) atomicAdd(&c[2], 1);
+// One thread: record finished solves, hand out the next ones in queue order,
+// rebuild the tile table of working slots and the host-visible counts.
+__global__ void k_assign(Eng e) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int next = ldc(e.next);
+  int working = 0;
+  int acc = 0;
+#ifdef REXII_DEBUG_CHECKS
+  {
+    int fin = 0;
+    for (int s = 0; s < e.B; ++s) fin += finished(ldc(&e.slots[s].status)) ? 1 : 0;
+    if (fin != ldc(&e.counter[3])) atomicAdd(&e.dbg[1], 1);
+    if (fin > 0 && ldc(&e.counter[3]) == 0) atomicAdd(&e.dbg[2], 1);
   }
-  __syncthreads();
-  if (threadIdx.x < 3) b.counter[threadIdx.x] = c[threadIdx.x];
+#endif
+  for (int s = 0; s < e.B; ++s) {
+    Slot* S = &e.slots[s];
+    int status = ldc(&S->status);
+    if (finished(status)) {
+      SolveStat& st = e.stats[ldc(&S->solve)];
+      st.rn2 = ldc(&S->rn2);
+      st.bn2 = ldc(&S->bn2);
+      st.it_total = ldc(&S->it_total);
+      st.rounds = ldc(&S->rounds);
+      st.status = status;
+      st.stagnated = ldc(&S->stagnated);
+      status = kIdle;
+      S->status = kIdle;
+    }
+    if (status == kIdle && next < e.S) {
+      const SolveDev* D = &e.solves[next];
+      const int dinst = ldc(&D->inst);
+      S->zeta = ldc(&D->zeta);
+      S->a1 = ldc(&D->a1);
+      S->a2 = ldc(&D->a2);
+      S->tol2 = ldc(&D->tol2);
+      S->rr = S->alpha = S->beta = make_double2(0.0, 0.0);
+      S->bn2 = S->rn2 = S->prev_rn2 = S->in_tol2 = 0.0;
+      S->status = kOuterPending;
+      S->parity = 0;
+      S->prime = 0;
+      S->it_total = S->it_inner = S->rounds = 0;
+      S->solve = next;
+      S->inst = dinst;
+      S->stagnated = 0;
+      status = kOuterPending;
+      ++next;
+    }
+    e.tile_start[s] = acc;
+    if (status != kIdle) {
+      acc += ldc(&e.inst[ldc(&S->inst)].nblk);
+      ++working;
+    }
+  }
+  e.tile_start[e.B] = acc;
+  *e.next = next;
+  e.counter[0] = working + (next < e.S ? 1 : 0);
+  e.counter[1] = next;
+}
+
+// Count of slots that finished during the chunk (read by the next retire).
+__global__ void k_count_finished(Eng e) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int fin = 0;
+  for (int s = 0; s < e.B; ++s) fin += finished(ldc(&e.slots[s].status)) ? 1 : 0;
+  e.counter[3] = fin;
 }
 
 // ---------------------------------------------------------------------------
@@ -450,23 +716,6 @@ __global__ void k_prep(const double* f, int nx, int ny, double* D0, double* Z0, 
   if (fl) atomicOr(flags, fl);
 }
 
-// A[j] += Re(c_j[s] * x64[s]) for j = 0, 1, 2, slots in index order
-__global__ void k_accumulate(Batch b, const double2* c0, const double2* c1, const double2* c2, int ns, double* A) {
-  const size_t n = size_t(b.geo.nx) * b.geo.ny;
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
-    double s0 = A[i], s1 = A[n + i], s2 = A[2 * n + i];
-    for (int s = 0; s < ns; ++s) {
-      const double2 x = b.x64[size_t(s) * n + i];
-      s0 += c0[s].x * x.x - c0[s].y * x.y;
-      s1 += c1[s].x * x.x - c1[s].y * x.y;
-      s2 += c2[s].x * x.x - c2[s].y * x.y;
-    }
-    A[i] = s0;
-    A[n + i] = s1;
-    A[2 * n + i] = s2;
-  }
-}
-
 // u_eta = A0;  (u, v) = S1 (u0, v0) + S2 J(u0, v0) + t g (grad A1 + J grad A2),
 // J(a, b) = (b, -a)
 __global__ void k_reconstruct(const double* f, const double* A, int nx, int ny, double S1, double S2,
@@ -495,17 +744,11 @@ __global__ void k_reconstruct(const double* f, const double* A, int nx, int ny, 
   }
 }
 
-// Full per-pole solution x_k = (eta_k, u_k, v_k) from y_k:
+// Full per-pole solution x = (eta, u, v) from the Helmholtz solution y:
 // eta = y / sigma, (u, v) = M ((u0, v0) + t g grad eta), M = m1 I + m2 J.
-__global__ void k_expand(Batch b, const double* f, int ns, const double2* inv_sigma, const double2* m1,
-                         const double2* m2, double tg, int has_vel, double2* out) {
-  const int nx = b.geo.nx, ny = b.geo.ny;
+__global__ void k_expand(const double2* y, const double* f, int nx, int ny, double2 is, double2 M1, double2 M2,
+                         double tg, int has_vel, double2* o) {
   const size_t n = size_t(nx) * ny;
-  const int s = blockIdx.y;
-  if (s >= ns) return;
-  const double2* y = b.x64 + size_t(s) * n;
-  const double2 is = inv_sigma[s], M1 = m1[s], M2 = m2[s];
-  double2* o = out + size_t(s) * 3 * n;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
     const int yy = int(i / nx), x = int(i - size_t(yy) * nx);
     const size_t xp = size_t(yy) * nx + (x + 1 == nx ? 0 : x + 1);
@@ -526,41 +769,112 @@ __global__ void k_expand(Batch b, const double* f, int ns, const double2* inv_si
   }
 }
 
+__global__ void k_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    dst[i] = s0 * src[i];
+    dst[n + i] = s1 * src[n + i];
+    dst[2 * n + i] = s2 * src[2 * n + i];
+  }
+}
+
+// partial sums of the adjoint dots: block b of dot k covers points
+// b, b + nblk*256, ... (fixed assignment), then a fixed-order reduction
+__global__ __launch_bounds__(256) void k_adj_dots(const AdjDot* dd, const double2* yout, int cap, const double* eta0,
+                                                  const double* D0, const double* Z0, int nx, int ny, double tg,
+                                                  int has_vel, double2* part, int nblk) {
+  __shared__ double red[8];
+  const AdjDot a = dd[blockIdx.y];
+  const size_t n = size_t(nx) * ny;
+  const double2* y = yout + size_t(a.jf) * cap;
+  const double2* ya = yout + size_t(a.ja) * cap;
+  double sr = 0.0, si = 0.0;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(nblk) * 256) {
+    double2 r = make_double2(eta0[i], 0.0);
+    double2 div = make_double2(0.0, 0.0);
+    if (has_vel) {
+      const double dv = D0[i], zv = Z0[i];
+      r.x += a.a1.x * dv + a.a2.x * zv;
+      r.y += a.a1.y * dv + a.a2.y * zv;
+      div.x = a.m1.x * dv + a.m2.x * zv;
+      div.y = a.m1.y * dv + a.m2.y * zv;
+    }
+    const double2 ly = cmul(cadd(r, cmul(a.zeta, y[i])), a.isig);   // L eta
+    const double2 t = cmul(a.m1, ly);
+    div.x += tg * t.x;
+    div.y += tg * t.y;
+    double2 yy = ya[i];
+    if (a.conj) yy.y = -yy.y;
+    const double2 Y = cmul(yy, a.ysc);
+    sr += Y.x * div.x - Y.y * div.y;
+    si += Y.x * div.y + Y.y * div.x;
+  }
+  double v[2] = {sr, si}, tot[2];
+  block_sum_n<2>(v, red, tot);
+  if (threadIdx.x == 0) part[size_t(blockIdx.y) * nblk + blockIdx.x] = make_double2(tot[0], tot[1]);
+}
+
+__global__ __launch_bounds__(256) void k_adj_reduce(const double2* part, int nblk, double2* out) {
+  __shared__ double red[8];
+  double v[2] = {0.0, 0.0}, tot[2];
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    v[0] += part[size_t(blockIdx.x) * nblk + b].x;
+    v[1] += part[size_t(blockIdx.x) * nblk + b].y;
+  }
+  block_sum_n<2>(v, red, tot);
+  if (threadIdx.x == 0) out[blockIdx.x] = make_double2(tot[0], tot[1]);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline dim3 slot_grid(const Batch& b) { return dim3(b.geo.nblk, b.B); }
+void launch_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2, hipStream_t s) {
+  size_t bl = (n + 255) / 256;
+  hipLaunchKernelGGL(k_scale3, dim3(unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl))), dim3(256), 0, s, src, dst, n,
+                     s0, s1, s2);
+}
+int adj_dot_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  return int(b > 64 ? 64 : (b < 1 ? 1 : b));
+}
+void launch_adj_dots(const AdjDot* d, int nd, const double2* yout, int cap, const double* eta0, const double* D0,
+                     const double* Z0, int nx, int ny, double tg, int has_vel, double2* part, int nblk, double2* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_dots, dim3(nblk, nd), dim3(256), 0, s, d, yout, cap, eta0, D0, Z0, nx, ny, tg, has_vel,
+                     part, nblk);
+  hipLaunchKernelGGL(k_adj_reduce, dim3(nd), dim3(256), 0, s, part, nblk, out);
+}
 static inline unsigned flat_blocks(size_t n) {
   size_t bl = (n + 255) / 256;
   return unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl));
 }
 
 template <typename T>
-void launch_outer_update(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update<T>, slot_grid(b), dim3(kNT), 0, s, b);
+void launch_pass(const Eng& e, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass<T>, dim3(grid), dim3(kNT), 0, s, e);
 }
 template <typename T>
-void launch_outer_residual(const Batch& b, const Rhs& rhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_residual<T>, slot_grid(b), dim3(kNT), 0, s, b, rhs);
-}
-void launch_scalars_outer(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalars_outer, dim3(b.B), dim3(kNT), 0, s, b);
+void launch_outer_update(const Eng& e, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update<T>, dim3(grid), dim3(kNT), 0, s, e);
 }
 template <typename T>
-void launch_inner_mv(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_inner_mv<T>, slot_grid(b), dim3(kNT), 0, s, b);
+void launch_outer_residual(const Eng& e, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_residual<T>, dim3(grid), dim3(kNT), 0, s, e);
 }
-void launch_scalars_mv(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalars_mv, dim3(b.B), dim3(kNT), 0, s, b);
+void launch_pass_scalars(const Eng& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_scalars, dim3(e.B), dim3(kNT), 0, s, e);
 }
-template <typename T>
-void launch_inner_up(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_inner_up<T>, slot_grid(b), dim3(kNT), 0, s, b);
+void launch_outer_scalars(const Eng& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_scalars, dim3(e.B), dim3(kNT), 0, s, e);
 }
-void launch_scalars_up(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalars_up, dim3(b.B), dim3(kNT), 0, s, b);
+void launch_retire(const Eng& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(256), 0, s, e);
 }
-void launch_count(const Batch& b, hipStream_t s) { hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, b); }
+void launch_assign(const Eng& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_assign, dim3(1), dim3(64), 0, s, e);
+}
+void launch_count_finished(const Eng& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_finished, dim3(1), dim3(64), 0, s, e);
+}
 void launch_fill_zero(double* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(flat_blocks(n)), dim3(256), 0, s, p, n);
 }
@@ -570,30 +884,29 @@ void launch_copy(const double* src, double* dst, size_t n, hipStream_t s) {
 void launch_prep(const double* f, int nx, int ny, double* D0, double* Z0, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(flat_blocks(size_t(nx) * ny)), dim3(256), 0, s, f, nx, ny, D0, Z0, flags);
 }
-void launch_accumulate(const Batch& b, const double2* c0, const double2* c1, const double2* c2, int ns, double* A,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_accumulate, dim3(flat_blocks(size_t(b.geo.nx) * b.geo.ny)), dim3(256), 0, s, b, c0, c1, c2,
-                     ns, A);
-}
 void launch_reconstruct(const double* f, const double* A, int nx, int ny, double S1, double S2, double tg,
                         int has_vel, double* u, hipStream_t s) {
   hipLaunchKernelGGL(k_reconstruct, dim3(flat_blocks(size_t(nx) * ny)), dim3(256), 0, s, f, A, nx, ny, S1, S2, tg,
                      has_vel, u);
 }
-void launch_expand(const Batch& b, const double* f, int ns, const double2* inv_sigma, const double2* m1,
-                   const double2* m2, double tg, int has_vel, double2* out, hipStream_t s) {
-  size_t n = size_t(b.geo.nx) * b.geo.ny;
-  unsigned bx = unsigned(n / 256 + 1 > 1024 ? 1024 : n / 256 + 1);
-  hipLaunchKernelGGL(k_expand, dim3(bx, ns), dim3(256), 0, s, b, f, ns, inv_sigma, m1, m2, tg, has_vel, out);
+void launch_expand(const double2* y, const double* f, int nx, int ny, double2 is, double2 m1, double2 m2,
+                   double tg, int has_vel, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3(flat_blocks(size_t(nx) * ny)), dim3(256), 0, s, y, f, nx, ny, is, m1, m2, tg,
+                     has_vel, out);
 }
 
-template void launch_outer_update<float>(const Batch&, hipStream_t);
-template void launch_outer_update<double>(const Batch&, hipStream_t);
-template void launch_outer_residual<float>(const Batch&, const Rhs&, hipStream_t);
-template void launch_outer_residual<double>(const Batch&, const Rhs&, hipStream_t);
-template void launch_inner_mv<float>(const Batch&, hipStream_t);
-template void launch_inner_mv<double>(const Batch&, hipStream_t);
-template void launch_inner_up<float>(const Batch&, hipStream_t);
-template void launch_inner_up<double>(const Batch&, hipStream_t);
+int pass_occupancy(int mixed) {
+  int occ = 0;
+  hipError_t err = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass<float>, kNT, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass<double>, kNT, 0);
+  return err == hipSuccess ? occ : 1;
+}
+
+template void launch_pass<float>(const Eng&, int, hipStream_t);
+template void launch_pass<double>(const Eng&, int, hipStream_t);
+template void launch_outer_update<float>(const Eng&, int, hipStream_t);
+template void launch_outer_update<double>(const Eng&, int, hipStream_t);
+template void launch_outer_residual<float>(const Eng&, int, hipStream_t);
+template void launch_outer_residual<double>(const Eng&, int, hipStream_t);
 
 }  // namespace rexii

@@ -113,19 +113,19 @@ struct Plan {
   int chunk;           // inner iterations per graph replay
   bool profile = false;
   std::vector<cd> z, w;
+  std::vector<cd> w_fwd;   // forward weights (w holds the adjoint ones in adjoint plans)
   std::vector<SolveDesc> solves;
   double S1 = 0, S2 = 0;
 };
 
-static Geo make_geo(int nx, int ny) {
-  Geo g;
-  g.nx = nx;
-  g.ny = ny;
+struct GridGeo {
+  int tiles_x, tiles_y, nblk;
+};
+static GridGeo make_geo(int nx, int ny) {
+  GridGeo g;
   g.tiles_x = (nx + kTX - 1) / kTX;
   g.tiles_y = (ny + kTY - 1) / kTY;
   g.nblk = g.tiles_x * g.tiles_y;
-  g.cx = 0.25 * double(nx) * nx;
-  g.cy = 0.25 * double(ny) * ny;
   return g;
 }
 
@@ -166,7 +166,7 @@ static rexii_opts resolve_opts(const rexii_opts* o) {
 
 // Pole set, shifts, weights and scheduling (host, FP64).
 static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opts& o, bool has_vel,
-                               bool div_free, Plan& pl) {
+                               bool div_free, Plan& pl, bool adjoint = false) {
   pl.nx = op->nx;
   pl.ny = op->ny;
   pl.g = op->g;
@@ -202,6 +202,18 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   }
   pl.kappa = kappa_sum(w, pl.h);
   pl.pole_tol = pl.tol / pl.kappa;
+  pl.w_fwd = pl.w;
+  if (adjoint) {
+    // r(tA)^T = W Re sum_k w'_k (tA - z_k)^{-1} W^{-1}: with A^T = -W A W^{-1}
+    // the transposed resolvent at z_k is -W (tA + z_k)^{-1} W^{-1}, and
+    // -z_{n,1} = conj(z_{n,2}), so the same poles serve with
+    // w'_{n,1} = -conj(w_{n,2}), w'_{n,2} = -conj(w_{n,1}).
+    for (int k = 0; k + 1 < pl.P; k += 2) {
+      const cd a = pl.w[k], b = pl.w[k + 1];
+      pl.w[k] = -std::conj(b);
+      pl.w[k + 1] = -std::conj(a);
+    }
+  }
 
   const double g = op->g, H = op->H0, fc = op->f_cor;
   const double lmax = max_s2(op->nx) + max_s2(op->ny);  // max(s_x^2 + s_y^2)
@@ -253,160 +265,228 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
       pl.solves.push_back(s);
     }
   }
-  // most expensive first: batches of similar cost
+  // most expensive first (longest-processing-time order for the slot queue)
   std::stable_sort(pl.solves.begin(), pl.solves.end(),
                    [](const SolveDesc& a, const SolveDesc& b) { return a.cost > b.cost; });
-  const Geo geo = make_geo(op->nx, op->ny);
-  int B = o.pole_batch;
-  if (B <= 0) {
-    B = (8192 + geo.nblk - 1) / geo.nblk;
-    B = std::max(8, std::min(B, 512));
-  }
-  // keep a batch within 16 GiB
-  const size_t per_slot = size_t(op->nx) * op->ny * (16 + 4 * inner_elem_bytes(o.precision));
-  const size_t cap = size_t(16) << 30;
-  B = int(std::max<size_t>(1, std::min<size_t>(size_t(B), cap / per_slot)));
-  B = std::min<int>(B, int(pl.solves.size()));
-  pl.B = std::max(1, B);
+  pl.B = o.pole_batch;
   pl.chunk = 16;
   return REXII_OK;
 }
 
-static size_t plan_bytes(const Plan& pl) {
-  const size_t n = size_t(pl.nx) * pl.ny;
-  const Geo geo = make_geo(pl.nx, pl.ny);
-  const size_t eb = inner_elem_bytes(pl.precision);
-  size_t b = 0;
-  b += al256(2 * n * sizeof(double));      // D0, Z0
-  b += al256(3 * n * sizeof(double));      // A
-  b += al256(64 * sizeof(int));            // flags, counters
-  b += al256(pl.B * sizeof(Slot));
-  b += al256(pl.B * n * 16);               // x64
-  b += 4 * al256(pl.B * n * eb);           // d, r, p0, p1
-  b += 2 * al256(size_t(pl.B) * geo.nblk * 16) + al256(size_t(pl.B) * geo.nblk * 8);
-  b += 6 * al256(pl.B * 16);               // c0..c2, inv_sigma, m1, m2
-  return b;
+// Slots for a set of problems: enough tiles to fill the chip several times
+// over, within a memory budget, never more than the number of solves.
+static int choose_slots(int requested, size_t max_points, int max_nblk, size_t nsolves, int precision) {
+  int B = requested;
+  if (B <= 0) {
+    B = (16384 + max_nblk - 1) / max_nblk;
+    B = std::max(8, std::min(B, 1024));
+  }
+  const size_t per_slot = max_points * (16 + 5 * inner_elem_bytes(precision));
+  const size_t budget = size_t(24) << 30;
+  B = int(std::max<size_t>(1, std::min<size_t>(size_t(B), budget / per_slot)));
+  B = int(std::min<size_t>(size_t(B), std::max<size_t>(1, nsolves)));
+  return B;
 }
 
 // ---------------------------------------------------------------------------
-// the batched solve engine
+// the slot engine (one or several problems)
 // ---------------------------------------------------------------------------
+struct Problem {
+  Plan pl;
+  const double* f = nullptr;   // device [3][ny][nx]
+  double* DZ = nullptr;        // device div / curl of the initial velocity
+  double* A = nullptr;         // device accumulators [3][ny][nx]
+  size_t n() const { return size_t(pl.nx) * pl.ny; }
+};
+
+struct EngineSize {
+  int B = 1, cap = 0, cap_blk = 0, S = 0, ninst = 0;
+  size_t eb = 16;
+};
+
+static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_B, int precision) {
+  EngineSize z;
+  size_t maxp = 0;
+  for (Problem* p : probs) {
+    maxp = std::max(maxp, p->n());
+    z.cap_blk = std::max(z.cap_blk, make_geo(p->pl.nx, p->pl.ny).nblk);
+    z.S += int(p->pl.solves.size());
+  }
+  z.cap = int(maxp);
+  z.ninst = int(probs.size());
+  z.eb = inner_elem_bytes(precision);
+  z.B = choose_slots(requested_B, maxp, z.cap_blk, size_t(z.S), precision);
+  return z;
+}
+
+// device bytes of the engine (problem arrays D0/Z0 and A are counted by
+// the caller)
+static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
+  size_t b = 0;
+  b += al256(z.B * sizeof(Slot)) + al256(z.ninst * sizeof(Inst));
+  b += al256(z.S * sizeof(SolveDev)) + al256(z.S * sizeof(SolveStat));
+  b += al256(sizeof(int)) + al256((z.B + 1) * sizeof(int)) + al256(4 * sizeof(int));
+  b += al256(size_t(z.B) * z.cap_blk * kNDots * sizeof(double));
+  b += al256(size_t(z.B) * z.cap * 16);
+  b += 5 * al256(size_t(z.B) * z.cap * z.eb);
+  if (keep_solutions) b += al256(size_t(z.S) * z.cap * 16);
+  b += al256(16 * sizeof(int));
+  return b;
+}
+
+static size_t problem_bytes(const Problem& p) { return al256(2 * p.n() * 8) + al256(3 * p.n() * 8) + al256(64); }
+
 struct Engine {
-  Plan& pl;
   hipStream_t st;
-  Batch bt{};
-  Rhs rhs{};
-  double* A = nullptr;
-  double2 *c0 = nullptr, *c1 = nullptr, *c2 = nullptr, *isg = nullptr, *dm1 = nullptr, *dm2 = nullptr;
+  EngineSize z;
+  int precision = 0, chunk = 16, grid = 0;
+  bool profile = false;
+  Eng e{};
   int* hcount = nullptr;   // pinned host mirror of the counters
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  // report
-  int max_iters = 0, max_rounds = 0, not_conv = 0, breakdowns = 0;
-  int64_t total_iters = 0;
-  double max_rel_res = 0.0;
-  int stagnated = 0;
+  std::vector<SolveStat> stats;
+  std::vector<int> solve_inst;    // instance of each queued solve
+  std::vector<int> solve_index;   // index of the solve within its instance
   // profiling (opts.profile)
   std::vector<hipEvent_t> evs;
-  int64_t mv_launches = 0, up_launches = 0;
-  double mv_ms = 0.0, up_ms = 0.0;
+  int64_t launches = 0;
+  double kernel_ms = 0.0;
+  double pass_bytes = 0.0;
+  std::vector<size_t> inst_points;
 
-  Engine(Plan& p, hipStream_t s) : pl(p), st(s) {}
+  explicit Engine(hipStream_t s) : st(s) {}
   ~Engine() {
-    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (hcount) (void)hipHostFree(hcount);
   }
 
-  void setup(Arena& ar, const double* f, double* DZ, int* small) {
-    const size_t n = size_t(pl.nx) * pl.ny;
-    const Geo geo = make_geo(pl.nx, pl.ny);
-    const size_t eb = inner_elem_bytes(pl.precision);
-    A = ar.take<double>(3 * n);
-    bt.B = pl.B;
-    bt.geo = geo;
-    bt.slots = ar.take<Slot>(pl.B);
-    bt.x64 = ar.take<double2>(size_t(pl.B) * n);
-    bt.d = ar.take<char>(size_t(pl.B) * n * eb);
-    bt.r = ar.take<char>(size_t(pl.B) * n * eb);
-    bt.p0 = ar.take<char>(size_t(pl.B) * n * eb);
-    bt.p1 = ar.take<char>(size_t(pl.B) * n * eb);
-    bt.part_a = ar.take<double2>(size_t(pl.B) * geo.nblk);
-    bt.part_b = ar.take<double2>(size_t(pl.B) * geo.nblk);
-    bt.part_c = ar.take<double>(size_t(pl.B) * geo.nblk);
-    bt.counter = small + 16;
-    c0 = ar.take<double2>(pl.B);
-    c1 = ar.take<double2>(pl.B);
-    c2 = ar.take<double2>(pl.B);
-    isg = ar.take<double2>(pl.B);
-    dm1 = ar.take<double2>(pl.B);
-    dm2 = ar.take<double2>(pl.B);
-    rhs.eta0 = f;
-    rhs.D0 = pl.has_vel ? DZ : nullptr;
-    rhs.Z0 = pl.has_vel ? DZ + n : nullptr;
+  void setup(Arena& ar, const std::vector<Problem*>& probs, const EngineSize& zs, int prec, int max_iter,
+             double inner_eta, bool prof, bool keep_solutions) {
+    z = zs;
+    precision = prec;
+    profile = prof;
+    e.B = z.B;
+    e.S = z.S;
+    e.cap = z.cap;
+    e.cap_blk = z.cap_blk;
+    e.max_iter = max_iter;
+    e.inner_eta2 = inner_eta * inner_eta;
+    e.slots = ar.take<Slot>(z.B);
+    Inst* dinst = ar.take<Inst>(z.ninst);
+    SolveDev* dsol = ar.take<SolveDev>(z.S);
+    e.inst = dinst;
+    e.solves = dsol;
+    e.stats = ar.take<SolveStat>(z.S);
+    e.next = ar.take<int>(1);
+    e.tile_start = ar.take<int>(z.B + 1);
+    e.counter = ar.take<int>(4);
+    e.part = ar.take<double>(size_t(z.B) * z.cap_blk * kNDots);
+    e.x64 = ar.take<double2>(size_t(z.B) * z.cap);
+    e.d = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    e.r0 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    e.r1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    e.p0 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    e.p1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    e.yout = keep_solutions ? ar.take<double2>(size_t(z.S) * z.cap) : nullptr;
+    e.dbg = ar.take<int>(16);
+
+    // problem table
+    std::vector<Inst> hinst(z.ninst);
+    inst_points.resize(z.ninst);
+    for (int i = 0; i < z.ninst; ++i) inst_points[i] = probs[i]->n();
+    for (int i = 0; i < z.ninst; ++i) {
+      const Plan& pl = probs[i]->pl;
+      const GridGeo g = make_geo(pl.nx, pl.ny);
+      Inst I;
+      I.nx = pl.nx;
+      I.ny = pl.ny;
+      I.tiles_x = g.tiles_x;
+      I.nblk = g.nblk;
+      I.cx = 0.25 * double(pl.nx) * pl.nx;
+      I.cy = 0.25 * double(pl.ny) * pl.ny;
+      I.eta0 = probs[i]->f;
+      I.D0 = pl.has_vel ? probs[i]->DZ : nullptr;
+      I.Z0 = pl.has_vel ? probs[i]->DZ + probs[i]->n() : nullptr;
+      I.A = probs[i]->A;
+      hinst[i] = I;
+    }
+    // solve queue: all problems' solves, most expensive first
+    struct Q {
+      double cost;
+      int inst, idx;
+    };
+    std::vector<Q> q;
+    for (int i = 0; i < z.ninst; ++i)
+      for (size_t k = 0; k < probs[i]->pl.solves.size(); ++k) q.push_back({probs[i]->pl.solves[k].cost, i, int(k)});
+    std::stable_sort(q.begin(), q.end(), [](const Q& a, const Q& b) { return a.cost > b.cost; });
+    std::vector<SolveDev> hs(z.S);
+    solve_inst.resize(z.S);
+    solve_index.resize(z.S);
+    for (int j = 0; j < z.S; ++j) {
+      const Plan& pl = probs[q[j].inst]->pl;
+      const SolveDesc& d = pl.solves[q[j].idx];
+      SolveDev D;
+      D.zeta = to_d2(d.zeta);
+      D.a1 = to_d2(d.a1);
+      D.a2 = to_d2(d.a2);
+      D.c0 = to_d2(d.c0);
+      D.c1 = to_d2(d.c1);
+      D.c2 = to_d2(d.c2);
+      D.tol2 = pl.pole_tol * pl.pole_tol;
+      D.inst = q[j].inst;
+      hs[j] = D;
+      solve_inst[j] = q[j].inst;
+      solve_index[j] = q[j].idx;
+    }
+    HIPCHK(hipMemcpyAsync(dinst, hinst.data(), z.ninst * sizeof(Inst), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dsol, hs.data(), z.S * sizeof(SolveDev), hipMemcpyHostToDevice, st));
+    // zero: slots (all idle), queue head, tile table, counters, x64
+    launch_fill_zero(reinterpret_cast<double*>(e.slots), z.B * sizeof(Slot) / 8, st);
+    launch_fill_zero(reinterpret_cast<double*>(e.next), 1, st);  // 8 bytes inside its 256-byte block
+    launch_fill_zero(reinterpret_cast<double*>(e.tile_start), (size_t(z.B + 1) * 4 + 7) / 8, st);
+    launch_fill_zero(reinterpret_cast<double*>(e.counter), 2, st);
+    launch_fill_zero(reinterpret_cast<double*>(e.dbg), 8, st);
+    launch_fill_zero(reinterpret_cast<double*>(e.x64), size_t(z.B) * z.cap * 2, st);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hcount), 64 * sizeof(int), hipHostMallocDefault));
-    launch_fill_zero(A, 3 * n, st);
+    // persistent grid: every CU filled with as many blocks as fit
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int occ = pass_occupancy(precision == REXII_PREC_MIXED ? 1 : 0);
+    // one work item (slot, tile) per block when every slot is live; never
+    // fewer blocks than fill the chip
+    const size_t items = size_t(z.B) * z.cap_blk;
+    grid = int(std::max<size_t>(size_t(cus) * std::max(1, occ), items));
+    grid = ((grid + 7) / 8) * 8;
   }
 
   template <typename T>
-  void enqueue_chunk() {
-    launch_outer_update<T>(bt, st);
-    launch_outer_residual<T>(bt, rhs, st);
-    launch_scalars_outer(bt, st);
-    for (int i = 0; i < pl.chunk; ++i) {
-      launch_inner_mv<T>(bt, st);
-      launch_scalars_mv(bt, st);
-      launch_inner_up<T>(bt, st);
-      launch_scalars_up(bt, st);
+  void enqueue_chunk(bool with_events) {
+    launch_retire(e, st);
+    launch_assign(e, st);
+    launch_outer_update<T>(e, grid, st);
+    launch_outer_residual<T>(e, grid, st);
+    launch_outer_scalars(e, st);
+    for (int i = 0; i < chunk; ++i) {
+      if (with_events) HIPCHK(hipEventRecord(evs[2 * i], st));
+      launch_pass<T>(e, grid, st);
+      if (with_events) HIPCHK(hipEventRecord(evs[2 * i + 1], st));
+      launch_pass_scalars(e, st);
     }
-    launch_count(bt, st);
-    HIPCHK(hipMemcpyAsync(hcount, bt.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  }
-
-  // The same chunk, launched directly, with an event pair around every inner
-  // kernel; elapsed times are collected after the chunk's host sync.
-  template <typename T>
-  void enqueue_chunk_profiled() {
-    if (evs.empty()) {
-      evs.resize(4 * pl.chunk);
-      for (hipEvent_t& e : evs) HIPCHK(hipEventCreate(&e));
-    }
-    launch_outer_update<T>(bt, st);
-    launch_outer_residual<T>(bt, rhs, st);
-    launch_scalars_outer(bt, st);
-    for (int i = 0; i < pl.chunk; ++i) {
-      HIPCHK(hipEventRecord(evs[4 * i], st));
-      launch_inner_mv<T>(bt, st);
-      HIPCHK(hipEventRecord(evs[4 * i + 1], st));
-      launch_scalars_mv(bt, st);
-      HIPCHK(hipEventRecord(evs[4 * i + 2], st));
-      launch_inner_up<T>(bt, st);
-      HIPCHK(hipEventRecord(evs[4 * i + 3], st));
-      launch_scalars_up(bt, st);
-    }
-    launch_count(bt, st);
-    HIPCHK(hipMemcpyAsync(hcount, bt.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  }
-  void collect_profile() {
-    for (int i = 0; i < pl.chunk; ++i) {
-      float a = 0.f, b = 0.f;
-      HIPCHK(hipEventElapsedTime(&a, evs[4 * i], evs[4 * i + 1]));
-      HIPCHK(hipEventElapsedTime(&b, evs[4 * i + 2], evs[4 * i + 3]));
-      mv_ms += a;
-      up_ms += b;
-    }
-    mv_launches += pl.chunk;
-    up_launches += pl.chunk;
+    launch_count_finished(e, st);
+    HIPCHK(hipMemcpyAsync(hcount, e.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   }
 
   template <typename T>
   void build_graph() {
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_chunk<T>();
+      enqueue_chunk<T>(false);
     } catch (...) {
-      hipGraph_t g2;
+      hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(st, &g2);
       if (g2) (void)hipGraphDestroy(g2);
       throw;
@@ -415,88 +495,75 @@ struct Engine {
     HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
 
-  // Run all solves in batches; accumulate into A.  If xout != nullptr the
-  // per-solve solutions are expanded into xout instead (shifted_solve).
   template <typename T>
-  void run(const double* f, double2* xout) {
-    const size_t n = size_t(pl.nx) * pl.ny;
-    const int S = int(pl.solves.size());
-    if (!pl.profile) build_graph<T>();
-    std::vector<Slot> hs(pl.B);
-    std::vector<double2> hc0(pl.B), hc1(pl.B), hc2(pl.B), his(pl.B), hm1(pl.B), hm2(pl.B);
-    for (int s0 = 0; s0 < S; s0 += pl.B) {
-      const int ns = std::min(pl.B, S - s0);
-      for (int j = 0; j < pl.B; ++j) {
-        Slot sl;
-        std::memset(&sl, 0, sizeof(sl));
-        if (j < ns) {
-          const SolveDesc& d = pl.solves[s0 + j];
-          sl.zeta = to_d2(d.zeta);
-          sl.a1 = to_d2(d.a1);
-          sl.a2 = to_d2(d.a2);
-          sl.tol2 = pl.pole_tol * pl.pole_tol;
-          sl.inner_eta2 = pl.inner_eta * pl.inner_eta;
-          sl.status = kOuterPending;
-          sl.max_iter = pl.max_iter;
-          sl.pole = d.pole;
-          hc0[j] = to_d2(d.c0);
-          hc1[j] = to_d2(d.c1);
-          hc2[j] = to_d2(d.c2);
-          his[j] = to_d2(d.inv_sigma);
-          hm1[j] = to_d2(d.m1);
-          hm2[j] = to_d2(d.m2);
-        } else {
-          sl.status = kIdle;
-          hc0[j] = hc1[j] = hc2[j] = his[j] = hm1[j] = hm2[j] = make_double2(0, 0);
+  void run(int max_iter) {
+    if (profile) {
+      evs.resize(2 * chunk);
+      for (hipEvent_t& ev : evs) HIPCHK(hipEventCreate(&ev));
+    } else {
+      build_graph<T>();
+    }
+    // enough replays for every solve to run max_iter iterations in turn
+    const int64_t per_slot = (int64_t(z.S) + z.B - 1) / z.B;
+    const int64_t max_replays = per_slot * (int64_t(max_iter) / chunk + 8) + 8;
+    for (int64_t rep = 0; rep < max_replays; ++rep) {
+      if (profile) {
+        enqueue_chunk<T>(true);
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < chunk; ++i) {
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+          kernel_ms += ms;
         }
-        hs[j] = sl;
-      }
-      HIPCHK(hipMemcpyAsync(bt.slots, hs.data(), pl.B * sizeof(Slot), hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(c0, hc0.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(c1, hc1.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(c2, hc2.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(isg, his.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dm1, hm1.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dm2, hm2.data(), pl.B * 16, hipMemcpyHostToDevice, st));
-      launch_fill_zero(reinterpret_cast<double*>(bt.x64), size_t(pl.B) * n * 2, st);
-      // replay the chunk until no slot is working
-      const int max_replays = pl.max_iter / pl.chunk + 64;
-      for (int rep = 0; rep < max_replays; ++rep) {
-        if (pl.profile) {
-          enqueue_chunk_profiled<T>();
-          HIPCHK(hipStreamSynchronize(st));
-          collect_profile();
-        } else {
-          HIPCHK(hipGraphLaunch(gexec, st));
-          HIPCHK(hipStreamSynchronize(st));
-        }
-        if (hcount[0] == 0) break;
-      }
-      if (xout) {
-        launch_expand(bt, f, ns, isg, dm1, dm2, pl.t * pl.g, pl.has_vel ? 1 : 0,
-                      xout + size_t(s0) * 3 * n, st);
+        launches += chunk;
       } else {
-        launch_accumulate(bt, c0, c1, c2, ns, A, st);
+        HIPCHK(hipGraphLaunch(gexec, st));
+        HIPCHK(hipStreamSynchronize(st));
       }
-      HIPCHK(hipMemcpyAsync(hs.data(), bt.slots, pl.B * sizeof(Slot), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      for (int j = 0; j < ns; ++j) {
-        const Slot& sl = hs[j];
-        max_iters = std::max(max_iters, sl.it_total);
-        max_rounds = std::max(max_rounds, sl.rounds);
-        total_iters += sl.it_total;
-        if (sl.status == kFailMaxIter) not_conv++;
-        if (sl.status == kFailBreakdown) breakdowns++;
-        if (sl.status != kDone && sl.status != kFailMaxIter && sl.status != kFailBreakdown) not_conv++;
-        stagnated += sl.stagnated;
-        const double rel = sl.bn2 > 0 ? std::sqrt(sl.rn2 / sl.bn2) : 0.0;
-        max_rel_res = std::max(max_rel_res, rel);
-      }
+      if (hcount[0] == 0) break;
+    }
+    stats.resize(z.S);
+    HIPCHK(hipMemcpyAsync(stats.data(), e.stats, z.S * sizeof(SolveStat), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+#ifdef REXII_DEBUG_CHECKS
+    int dbg[16];
+    HIPCHK(hipMemcpy(dbg, e.dbg, sizeof(dbg), hipMemcpyDeviceToHost));
+    fprintf(stderr, "rexii debug: nonuniform=%d fin_mismatch=%d missed_retire=%d nonzero_x0=%d stale_total=%d bad_tile=%d\n",
+            dbg[0], dbg[1], dbg[2], dbg[3], dbg[4], dbg[5]);
+#endif
+    // algorithmic bytes of all pass launches: a pass reads d, r, p and writes
+    // them (6 complex values per point); a prime pass reads r and writes r, p
+    pass_bytes = 0.0;
+    for (int j = 0; j < z.S; ++j) {
+      const double pts = double(inst_points[solve_inst[j]]);
+      pass_bytes += pts * double(z.eb) * (6.0 * stats[j].it_total + 3.0 * std::max(0, stats[j].rounds - 1));
     }
   }
 };
 
-static void fill_report(rexii_report* rep, const Plan& pl, const Engine* e, double secs) {
+struct RunSummary {
+  int max_iters = 0, max_rounds = 0, not_conv = 0, breakdowns = 0, stagnated = 0;
+  int64_t total_iters = 0;
+  double max_rel_res = 0.0;
+};
+
+static RunSummary summarize(const Engine& en, int inst) {
+  RunSummary r;
+  for (size_t j = 0; j < en.stats.size(); ++j) {
+    if (inst >= 0 && en.solve_inst[j] != inst) continue;
+    const SolveStat& s = en.stats[j];
+    r.max_iters = std::max(r.max_iters, s.it_total);
+    r.max_rounds = std::max(r.max_rounds, s.rounds);
+    r.total_iters += s.it_total;
+    if (s.status == kFailBreakdown) r.breakdowns++;
+    else if (s.status != kDone) r.not_conv++;
+    r.stagnated += s.stagnated;
+    r.max_rel_res = std::max(r.max_rel_res, s.bn2 > 0 ? std::sqrt(s.rn2 / s.bn2) : 0.0);
+  }
+  return r;
+}
+
+static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int inst, double secs) {
   if (!rep) return;
   std::memset(rep, 0, sizeof(*rep));
   rep->P = pl.P;
@@ -510,166 +577,382 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* e, doub
   rep->kappa_sum = pl.kappa;
   rep->pole_tol = pl.pole_tol;
   rep->seconds = secs;
-  if (e) {
-    rep->max_iters = e->max_iters;
-    rep->max_refine = e->max_rounds;
-    rep->not_converged = e->not_conv;
-    rep->total_iters = e->total_iters;
-    rep->max_rel_residual = e->max_rel_res;
+  if (en) {
+    const RunSummary r = summarize(*en, inst);
+    rep->max_iters = r.max_iters;
+    rep->max_refine = r.max_rounds;
+    rep->not_converged = r.not_conv + r.breakdowns;
+    rep->total_iters = r.total_iters;
+    rep->max_rel_residual = r.max_rel_res;
+    rep->stagnated = r.stagnated;
     const double eb = double(inner_elem_bytes(pl.precision));
-    // inner iteration: mv reads r, p and writes p; up reads p, d, r and writes d, r
-    rep->alg_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 8.0 * eb;
-    rep->mv_launches = e->mv_launches;
-    rep->up_launches = e->up_launches;
-    rep->mv_ms = e->mv_ms;
-    rep->up_ms = e->up_ms;
-    rep->mv_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 3.0 * eb;
-    rep->up_bytes = double(e->total_iters) * double(pl.nx) * pl.ny * 5.0 * eb;
+    // one pass reads x, r, p and writes them back: 6 complex values per point
+    rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * 6.0 * eb;
+    rep->kernel_launches = en->launches;
+    rep->kernel_ms = en->kernel_ms;
+    rep->kernel_bytes = en->pass_bytes;
   }
 }
 
-// Shared front end of apply / shifted_solve.
-static rexii_status run_problem_on(const rexii_swe_op* op, const double* f, double* u, double t,
-                                   const rexii_opts* opts_in, void* ws, size_t ws_bytes,
-                                   hipStream_t stream, rexii_report* rep, const std::vector<cd>* shifts,
-                                   double2* xout);
-
-// The work runs on a private stream (graph capture needs a capturable
-// stream; the caller's may be the null stream), ordered after the work
-// already enqueued on the caller's stream and before anything enqueued on it
-// later: the call returns only when its result is complete.
-static rexii_status run_problem(const rexii_swe_op* op, const double* f, double* u, double t,
-                                const rexii_opts* opts_in, void* ws, size_t ws_bytes,
-                                hipStream_t stream, rexii_report* rep, const std::vector<cd>* shifts,
-                                double2* xout) {
-  {
-    // argument checks that need no device
-    rexii_status v = validate_op(op);
-    if (v != REXII_OK) return v;
-    if (!f || (!u && !xout)) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
-    if (!(t >= 0.0) || !std::isfinite(t)) return set_error(REXII_ERR_INVALID_ARG, "t must be finite and >= 0");
-    if (op->H_field) return set_error(REXII_ERR_INVALID_ARG, "variable depth is not supported by this entry point");
+// explicit shifts: one solve per shift, no weights
+static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>& shifts, double tol, Plan& pl) {
+  pl.paired = false;
+  pl.solves.clear();
+  const double g = op->g, H = op->H0, fc = op->f_cor;
+  for (size_t k = 0; k < shifts.size(); ++k) {
+    const cd zk = shifts[k];
+    const cd den = zk * zk + t * t * fc * fc;
+    SolveDesc s;
+    s.m1 = -zk / den;
+    s.m2 = -t * fc / den;
+    const cd sig = t * t * g * H * zk / den;
+    s.zeta = den / (t * t * g * H);
+    s.a1 = t * H * s.m1;
+    s.a2 = t * H * s.m2;
+    s.inv_sigma = 1.0 / sig;
+    s.c0 = s.c1 = s.c2 = 0.0;
+    s.cost = 0.0;
+    s.pole = int(k);
+    pl.solves.push_back(s);
   }
+  pl.pole_tol = tol;
+}
+
+// ---------------------------------------------------------------------------
+// jobs: the problems of one call, run through one slot engine
+// ---------------------------------------------------------------------------
+struct JobItem {
+  const rexii_swe_op* op = nullptr;
+  const double* f = nullptr;              // device right-hand state
+  double t = 0.0;
+  double* u = nullptr;                    // device output (nullptr: none)
+  bool adjoint = false;                   // transposed-operator weights
+  const std::vector<cd>* shifts = nullptr;// explicit shifts (resolvents)
+  double2* xout = nullptr;                // resolvent output
+  rexii_report* rep = nullptr;
+  bool skip = false;                      // t == 0: u = f
+};
+
+// Sizing plans: unpaired with velocity, an upper bound of every variant.
+static rexii_status sizing_plan(const JobItem& it, const rexii_opts& o, Problem& pb) {
+  rexii_status st = build_plan(it.op, it.t, o, true, false, pb.pl, it.adjoint);
+  if (st != REXII_OK) return st;
+  if (it.shifts) shift_solves(it.op, it.t, *it.shifts, o.tol, pb.pl);
+  return REXII_OK;
+}
+
+static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opts& o, bool keep, size_t extra,
+                              size_t* bytes) {
+  std::vector<Problem> pbs(items.size());
+  std::vector<Problem*> ptrs;
+  size_t b = extra;
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (items[i].skip) continue;
+    rexii_status st = sizing_plan(items[i], o, pbs[i]);
+    if (st != REXII_OK) return st;
+    ptrs.push_back(&pbs[i]);
+    b += problem_bytes(pbs[i]);
+  }
+  if (!ptrs.empty()) b += engine_bytes(engine_size(ptrs, o.pole_batch, o.precision), keep);
+  *bytes = b;
+  return REXII_OK;
+}
+
+struct Job {
+  hipStream_t st;
+  rexii_opts o;
+  std::vector<JobItem> items;
+  std::vector<Problem> pbs;
+  std::vector<Problem*> ptrs;    // problems in the engine
+  std::vector<int> engine_index; // item -> problem index in the engine (-1: skipped)
+  Engine* en = nullptr;
+  bool keep = false;
+  bool force_unpaired = false;
+  bool pair_all = false;         // pairing decided jointly (adjoint)
+  ~Job() { delete en; }
+};
+
+// Prepares every problem (input checks, div/curl, plans) and runs the engine.
+static void run_job(Job& jb, Arena& ar) {
+  const size_t ni = jb.items.size();
+  jb.pbs.resize(ni);
+  jb.engine_index.assign(ni, -1);
+  int* flags = nullptr;
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&flags), std::max<size_t>(1, ni) * sizeof(int), hipHostMallocDefault));
+  struct FreeHost {
+    int* p;
+    ~FreeHost() { (void)hipHostFree(p); }
+  } fh{flags};
+  int* dflags = ar.take<int>(std::max<size_t>(1, ni));
+  launch_fill_zero(reinterpret_cast<double*>(dflags), (std::max<size_t>(1, ni) + 1) / 2, jb.st);
+  for (size_t i = 0; i < ni; ++i) {
+    JobItem& it = jb.items[i];
+    if (it.skip) continue;
+    Problem& pb = jb.pbs[i];
+    const size_t n = size_t(it.op->nx) * it.op->ny;
+    pb.f = it.f;
+    pb.DZ = ar.take<double>(2 * n);
+    pb.A = ar.take<double>(3 * n);
+    (void)ar.take<char>(64);
+    launch_fill_zero(pb.A, 3 * n, jb.st);
+    launch_prep(it.f, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, jb.st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(flags, dflags, ni * sizeof(int), hipMemcpyDeviceToHost, jb.st));
+  HIPCHK(hipStreamSynchronize(jb.st));
+  bool all_div_free = true;
+  for (size_t i = 0; i < ni; ++i) {
+    if (jb.items[i].skip) continue;
+    if (flags[i] & 1) throw HipError{REXII_ERR_NONFINITE, "non-finite value in an input state"};
+    if (flags[i] & 4) all_div_free = false;
+  }
+  for (size_t i = 0; i < ni; ++i) {
+    JobItem& it = jb.items[i];
+    if (it.skip) continue;
+    const bool has_vel = (flags[i] & 2) != 0;
+    bool div_free = (flags[i] & 4) == 0;
+    if (jb.pair_all) div_free = all_div_free;
+    if (jb.force_unpaired || it.shifts) div_free = false;
+    rexii_status st = build_plan(it.op, it.t, jb.o, has_vel, div_free, jb.pbs[i].pl, it.adjoint);
+    if (st != REXII_OK) throw HipError{st, g_err};
+    if (it.shifts) shift_solves(it.op, it.t, *it.shifts, jb.o.tol, jb.pbs[i].pl);
+    jb.engine_index[i] = int(jb.ptrs.size());
+    jb.ptrs.push_back(&jb.pbs[i]);
+  }
+  if (jb.ptrs.empty()) return;
+  const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision);
+  jb.en = new Engine(jb.st);
+  jb.en->setup(ar, jb.ptrs, z, jb.o.precision, jb.o.max_iter,
+               (jb.o.precision == REXII_PREC_MIXED) ? jb.o.inner_tol : 0.0, jb.o.profile != 0, jb.keep);
+  if (jb.o.precision == REXII_PREC_MIXED)
+    jb.en->run<float>(jb.o.max_iter);
+  else
+    jb.en->run<double>(jb.o.max_iter);
+}
+
+// Reports and status of every item after the run.
+static rexii_status finish_job(Job& jb, double secs) {
+  int bad_breakdown = 0, bad_conv = 0;
+  for (size_t i = 0; i < jb.items.size(); ++i) {
+    JobItem& it = jb.items[i];
+    if (it.skip) {
+      if (it.rep) {
+        std::memset(it.rep, 0, sizeof(*it.rep));
+        it.rep->t = 0.0;
+      }
+      continue;
+    }
+    const int ei = jb.engine_index[i];
+    fill_report(it.rep, jb.pbs[i].pl, jb.en, ei, secs);
+    const RunSummary sm = summarize(*jb.en, ei);
+    bad_breakdown += sm.breakdowns;
+    bad_conv += sm.not_conv;
+  }
+  if (bad_breakdown > 0) return set_error(REXII_ERR_BREAKDOWN, "Krylov breakdown in a shifted solve");
+  if (bad_conv > 0) return set_error(REXII_ERR_NOT_CONVERGED, "a shifted solve reached max_iter");
+  return clear_error();
+}
+
+static rexii_status check_op_and_t(const rexii_swe_op* op, double t, bool allow_zero) {
+  rexii_status v = validate_op(op);
+  if (v != REXII_OK) return v;
+  if (!std::isfinite(t) || t < 0.0 || (!allow_zero && t == 0.0))
+    return set_error(REXII_ERR_INVALID_ARG, allow_zero ? "t must be finite and >= 0" : "t must be > 0");
+  if (op->H_field) return set_error(REXII_ERR_INVALID_ARG, "variable depth is not supported by this entry point");
+  return REXII_OK;
+}
+
+static bool overlaps(const double* a, size_t na, const double* b, size_t nb) { return a < b + nb && b < a + na; }
+
+// Runs `body(stream)` on a private stream ordered after the caller's stream
+// (graph capture needs a capturable stream; the caller's may be the null
+// stream).  The call returns only when the work is complete, so later work
+// on the caller's stream sees the results.
+template <typename F>
+static rexii_status on_private_stream(hipStream_t caller, F&& body) {
   hipStream_t own = nullptr;
   hipEvent_t ev = nullptr;
   if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
     return set_error(REXII_ERR_HIP, "hipStreamCreateWithFlags failed");
-  rexii_status st = REXII_OK;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, stream) != hipSuccess ||
+  rexii_status st;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, caller) != hipSuccess ||
       hipStreamWaitEvent(own, ev, 0) != hipSuccess) {
     st = set_error(REXII_ERR_HIP, "could not order the private stream after the caller's stream");
   } else {
-    st = run_problem_on(op, f, u, t, opts_in, ws, ws_bytes, own, rep, shifts, xout);
+    try {
+      st = body(own);
+    } catch (const HipError& he) {
+      st = set_error(he.st, he.msg);
+    } catch (const std::bad_alloc&) {
+      st = set_error(REXII_ERR_OOM, "host allocation failed");
+    }
   }
   const std::string msg = g_err;
   if (hipStreamSynchronize(own) != hipSuccess && st == REXII_OK) st = set_error(REXII_ERR_HIP, "stream sync failed");
   if (ev) (void)hipEventDestroy(ev);
   (void)hipStreamDestroy(own);
-  if (st != REXII_OK) g_err = msg.empty() ? g_err : msg;
+  g_err = msg;
   return st;
 }
 
-static rexii_status run_problem_on(const rexii_swe_op* op, const double* f, double* u, double t,
-                                   const rexii_opts* opts_in, void* ws, size_t ws_bytes,
-                                   hipStream_t stream, rexii_report* rep, const std::vector<cd>* shifts,
-                                   double2* xout) {
+// Common driver of apply / batched / shifted_solve.
+static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts_in, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
   const auto t0 = std::chrono::steady_clock::now();
-  rexii_status st = validate_op(op);
-  if (st != REXII_OK) return st;
-  if (op->H_field) return set_error(REXII_ERR_INVALID_ARG, "variable depth is not supported by this entry point");
-  if (!f || (!u && !xout)) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
-  if (!(t >= 0.0) || !std::isfinite(t)) return set_error(REXII_ERR_INVALID_ARG, "t must be finite and >= 0");
-  const size_t n = size_t(op->nx) * op->ny;
-  if (u && (u < f + 3 * n && f < u + 3 * n)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
-  rexii_opts o = resolve_opts(opts_in);
-  try {
-    if (t == 0.0 && !shifts) {
-      launch_copy(f, u, 3 * n, stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(stream));
-      if (rep) {
-        std::memset(rep, 0, sizeof(*rep));
-        rep->t = 0.0;
+  return on_private_stream(stream, [&](hipStream_t st) -> rexii_status {
+    Job jb;
+    jb.st = st;
+    jb.o = resolve_opts(opts_in);
+    jb.items = items;
+    for (JobItem& it : jb.items) {
+      if (it.t == 0.0 && !it.shifts) {
+        it.skip = true;
+        launch_copy(it.f, it.u, 3 * size_t(it.op->nx) * it.op->ny, st);
       }
-      return clear_error();
     }
-    // workspace: sized for the unpaired plan, an upper bound of every variant
-    Plan pl;
-    st = build_plan(op, t, o, true, false, pl);
-    if (st != REXII_OK) return st;
-    if (shifts) pl.B = std::max(1, std::min<int>(pl.B, int(shifts->size())));
-    const size_t need = plan_bytes(pl);
+    jb.keep = false;
+    for (const JobItem& it : jb.items) jb.keep = jb.keep || (it.shifts != nullptr);
+    size_t need = 0;
+    rexii_status s0 = job_bytes(jb.items, jb.o, jb.keep, 0, &need);
+    if (s0 != REXII_OK) return s0;
     Arena ar(ws, ws_bytes);
     if (!ws) {
-      ar.reserve_own(need);
+      ar.reserve_own(need + 4096);
     } else if (ws_bytes < need) {
       return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_workspace_size()");
     }
-    double* DZ = ar.take<double>(2 * n);
-    int* small = ar.take<int>(64);
-    // input checks and velocity derivatives
-    int* flags = nullptr;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&flags), 4 * sizeof(int), hipHostMallocDefault));
-    struct FreeHost {
-      int* p;
-      ~FreeHost() { (void)hipHostFree(p); }
-    } fh{flags};
-    launch_fill_zero(reinterpret_cast<double*>(small), 8, stream);
-    launch_prep(f, op->nx, op->ny, DZ, DZ + n, small, stream);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(flags, small, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    if (flags[0] & 1) return set_error(REXII_ERR_NONFINITE, "non-finite value in f");
-    const bool has_vel = (flags[0] & 2) != 0;
-    const bool div_free = (flags[0] & 4) == 0;
-
-    st = build_plan(op, t, o, has_vel, div_free && !shifts, pl);
-    if (st != REXII_OK) return st;
-    if (shifts) {
-      // explicit shifts: one solve per shift, no weights
-      pl.paired = false;
-      pl.solves.clear();
-      const double g = op->g, H = op->H0, fc = op->f_cor;
-      for (size_t k = 0; k < shifts->size(); ++k) {
-        const cd zk = (*shifts)[k];
-        const cd den = zk * zk + t * t * fc * fc;
-        SolveDesc s;
-        s.m1 = -zk / den;
-        s.m2 = -t * fc / den;
-        const cd sig = t * t * g * H * zk / den;
-        s.zeta = den / (t * t * g * H);
-        s.a1 = t * H * s.m1;
-        s.a2 = t * H * s.m2;
-        s.inv_sigma = 1.0 / sig;
-        s.c0 = s.c1 = s.c2 = 0.0;
-        s.cost = 0.0;
-        s.pole = int(k);
-        pl.solves.push_back(s);
+    run_job(jb, ar);
+    for (size_t i = 0; i < jb.items.size(); ++i) {
+      const JobItem& it = jb.items[i];
+      if (it.skip) continue;
+      const Problem& pb = jb.pbs[i];
+      const size_t n = size_t(it.op->nx) * it.op->ny;
+      if (it.shifts) {
+        for (int j = 0; j < jb.en->z.S; ++j) {
+          if (jb.en->solve_inst[j] != jb.engine_index[i]) continue;
+          const SolveDesc& d = pb.pl.solves[jb.en->solve_index[j]];
+          launch_expand(jb.en->e.yout + size_t(j) * jb.en->z.cap, it.f, it.op->nx, it.op->ny, to_d2(d.inv_sigma),
+                        to_d2(d.m1), to_d2(d.m2), it.t * it.op->g, pb.pl.has_vel ? 1 : 0,
+                        it.xout + size_t(d.pole) * 3 * n, st);
+        }
+      } else if (it.u) {
+        launch_reconstruct(it.f, pb.A, it.op->nx, it.op->ny, pb.pl.S1, pb.pl.S2, it.t * it.op->g,
+                           pb.pl.has_vel ? 1 : 0, it.u, st);
       }
-      pl.B = std::max(1, std::min<int>(pl.B, int(pl.solves.size())));
-      pl.pole_tol = o.tol;
-    }
-    Engine e(pl, stream);
-    e.setup(ar, f, DZ, small);
-    if (o.precision == REXII_PREC_MIXED)
-      e.run<float>(f, xout);
-    else
-      e.run<double>(f, xout);
-    if (!xout) {
-      launch_reconstruct(f, e.A, op->nx, op->ny, pl.S1, pl.S2, t * op->g, pl.has_vel ? 1 : 0, u, stream);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_report(rep, pl, &e, secs);
-    if (e.breakdowns > 0) return set_error(REXII_ERR_BREAKDOWN, "Krylov breakdown in a shifted solve");
-    if (e.not_conv > 0) return set_error(REXII_ERR_NOT_CONVERGED, "a shifted solve reached max_iter");
-    return clear_error();
-  } catch (const HipError& he) {
-    return set_error(he.st, he.msg);
-  } catch (const std::bad_alloc&) {
-    return set_error(REXII_ERR_OOM, "host allocation failed");
-  }
+    return finish_job(jb, secs);
+  });
+}
+
+// Adjoint: dJdf = r(tA)^T gbar = W Re sum_k w'_k (tA - z_k)^{-1} W^{-1} gbar,
+// dJdH = -t g Re sum_k w_k <conj(eta-part of (tA - z_{pi(k)})^{-1} W^{-1} gbar),
+//                            div of the velocity of (tA - z_k)^{-1} f>,
+// pi swapping the two poles of a term.
+static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const double* gbar, double* dJdf,
+                                double* dJdH, double t, const rexii_opts* opts_in, void* ws, size_t ws_bytes,
+                                hipStream_t stream, rexii_report* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  return on_private_stream(stream, [&](hipStream_t st) -> rexii_status {
+    const size_t n = size_t(op->nx) * op->ny;
+    Job jb;
+    jb.st = st;
+    jb.o = resolve_opts(opts_in);
+    jb.pair_all = true;
+    const bool want_H = (dJdH != nullptr);
+    jb.keep = want_H;
+    JobItem G;
+    G.op = op;
+    G.t = t;
+    G.adjoint = true;
+    G.u = dJdf;
+    G.rep = rep;
+    jb.items.push_back(G);
+    if (want_H) {
+      JobItem F;
+      F.op = op;
+      F.f = f;
+      F.t = t;
+      jb.items.push_back(F);
+    }
+    size_t need = 0;
+    rexii_status s0 = job_bytes(jb.items, jb.o, jb.keep, al256(3 * n * 8) + 4096, &need);
+    if (s0 != REXII_OK) return s0;
+    Arena ar(ws, ws_bytes);
+    if (!ws) {
+      ar.reserve_own(need + 4096);
+    } else if (ws_bytes < need) {
+      return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_workspace_size()");
+    }
+    // b' = W^{-1} gbar, W = diag(g, H, H)
+    double* bprime = ar.take<double>(3 * n);
+    launch_scale3(gbar, bprime, n, 1.0 / op->g, 1.0 / op->H0, 1.0 / op->H0, st);
+    jb.items[0].f = bprime;
+    run_job(jb, ar);
+    const Problem& pg = jb.pbs[0];
+    if (dJdf) {
+      launch_reconstruct(bprime, pg.A, op->nx, op->ny, pg.pl.S1, pg.pl.S2, t * op->g, pg.pl.has_vel ? 1 : 0, dJdf,
+                         st);
+      launch_scale3(dJdf, dJdf, n, op->g, op->H0, op->H0, st);
+    }
+    if (want_H) {
+      const Problem& pf = jb.pbs[1];
+      const Engine& en = *jb.en;
+      // queue positions of every (instance, solve) pair
+      std::vector<int> qpos_g(pg.pl.solves.size(), -1), qpos_f(pf.pl.solves.size(), -1);
+      for (int j = 0; j < en.z.S; ++j) {
+        if (en.solve_inst[j] == 0) qpos_g[en.solve_index[j]] = j;
+        else qpos_f[en.solve_index[j]] = j;
+      }
+      // adjoint solve by pole index
+      std::vector<int> g_by_pole(pg.pl.P, -1);
+      for (size_t k = 0; k < pg.pl.solves.size(); ++k) g_by_pole[pg.pl.solves[k].pole] = int(k);
+      std::vector<AdjDot> dots;
+      std::vector<cd> coef;
+      const bool paired = pf.pl.paired;
+      for (size_t k = 0; k < pf.pl.solves.size(); ++k) {
+        const SolveDesc& d = pf.pl.solves[k];
+        const int pole = d.pole;
+        const int partner = paired ? pole : (pole ^ 1);
+        const int gk = g_by_pole[partner];
+        if (gk < 0) throw HipError{REXII_ERR_INVALID_ARG, "adjoint: partner solve missing"};
+        const SolveDesc& dg = pg.pl.solves[gk];
+        AdjDot a;
+        a.m1 = to_d2(d.m1);
+        a.m2 = to_d2(d.m2);
+        a.a1 = to_d2(d.a1);
+        a.a2 = to_d2(d.a2);
+        a.zeta = to_d2(d.zeta);
+        a.isig = to_d2(d.inv_sigma);
+        a.ysc = to_d2(paired ? dg.inv_sigma : std::conj(dg.inv_sigma));
+        a.conj = paired ? 0 : 1;
+        a.jf = qpos_f[k];
+        a.ja = qpos_g[gk];
+        dots.push_back(a);
+        coef.push_back(paired ? (std::conj(pf.pl.w_fwd[pole + 1]) - pf.pl.w_fwd[pole]) : pf.pl.w_fwd[pole]);
+      }
+      const int nd = int(dots.size());
+      AdjDot* ddots = ar.take<AdjDot>(nd);
+      const int nblk = adj_dot_blocks(n);
+      double2* part = ar.take<double2>(size_t(nd) * nblk);
+      double2* out = ar.take<double2>(nd);
+      HIPCHK(hipMemcpyAsync(ddots, dots.data(), nd * sizeof(AdjDot), hipMemcpyHostToDevice, st));
+      launch_adj_dots(ddots, nd, en.e.yout, en.z.cap, f, pf.DZ, pf.pl.has_vel ? pf.DZ + n : nullptr, op->nx, op->ny,
+                      t * op->g, pf.pl.has_vel ? 1 : 0, part, nblk, out, st);
+      std::vector<double2> hout(nd);
+      HIPCHK(hipMemcpyAsync(hout.data(), out, nd * sizeof(double2), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double acc = 0.0;
+      for (int k = 0; k < nd; ++k) acc += (coef[k] * cd(hout[k].x, hout[k].y)).real();
+      *dJdH = -t * op->g * acc;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return finish_job(jb, secs);
+  });
 }
 
 }  // namespace rexii
@@ -713,42 +996,95 @@ rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts
     return clear_error();
   }
   rexii_opts o = resolve_opts(opts);
-  Plan pl;
-  // sized for the unpaired case (an upper bound)
-  st = build_plan(op, t, o, true, false, pl);
+  // the adjoint with dJ/dH is the largest user of one operator: two
+  // problems, every solution kept, plus W^{-1} gbar and the dot buffers
+  const size_t n = size_t(op->nx) * op->ny;
+  JobItem G, F;
+  G.op = F.op = op;
+  G.t = F.t = t;
+  G.adjoint = true;
+  size_t b = 0;
+  st = job_bytes({G, F}, o, true, al256(3 * n * 8) + 4096, &b);
   if (st != REXII_OK) return st;
-  *bytes = plan_bytes(pl);
+  Problem pb;
+  st = build_plan(op, t, o, true, false, pb.pl);
+  if (st != REXII_OK) return st;
+  const size_t nd = pb.pl.solves.size();
+  b += al256(nd * sizeof(AdjDot)) + al256(nd * size_t(adj_dot_blocks(n)) * 16) + al256(nd * 16) + 4096;
+  *bytes = b;
   return clear_error();
 }
 
 rexii_status rexii_apply(const rexii_swe_op* op, const double* f, double* u, double t, const rexii_opts* opts,
                          void* workspace, size_t ws_bytes, hipStream_t stream, rexii_report* rep) {
-  return run_problem(op, f, u, t, opts, workspace, ws_bytes, stream, rep, nullptr, nullptr);
+  rexii_status v = check_op_and_t(op, t, true);
+  if (v != REXII_OK) return v;
+  if (!f || !u) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
+  const size_t n3 = 3 * size_t(op->nx) * op->ny;
+  if (overlaps(f, n3, u, n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
+  JobItem it;
+  it.op = op;
+  it.f = f;
+  it.u = u;
+  it.t = t;
+  it.rep = rep;
+  return run_items({it}, opts, workspace, ws_bytes, stream);
 }
 
 rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double t, int32_t npoles, const double* z,
                                  double* x, const rexii_opts* opts, void* workspace, size_t ws_bytes,
                                  hipStream_t stream, rexii_report* rep) {
-  if (npoles <= 0 || !z || !x) return set_error(REXII_ERR_INVALID_ARG, "need npoles > 0, z and x");
-  if (!(t > 0.0)) return set_error(REXII_ERR_INVALID_ARG, "t must be > 0");
+  rexii_status v = check_op_and_t(op, t, false);
+  if (v != REXII_OK) return v;
+  if (npoles <= 0 || !z || !x || !f) return set_error(REXII_ERR_INVALID_ARG, "need f, npoles > 0, z and x");
   std::vector<cd> sh(npoles);
   for (int k = 0; k < npoles; ++k) {
     sh[k] = cd(z[2 * k], z[2 * k + 1]);
     if (!(sh[k].real() != 0.0) || !std::isfinite(sh[k].real()) || !std::isfinite(sh[k].imag()))
       return set_error(REXII_ERR_INVALID_ARG, "shifts need a finite, non-zero real part");
   }
-  return run_problem(op, f, nullptr, t, opts, workspace, ws_bytes, stream, rep, &sh,
-                     reinterpret_cast<double2*>(x));
+  JobItem it;
+  it.op = op;
+  it.f = f;
+  it.t = t;
+  it.shifts = &sh;
+  it.xout = reinterpret_cast<double2*>(x);
+  it.rep = rep;
+  return run_items({it}, opts, workspace, ws_bytes, stream);
 }
 
-rexii_status rexii_apply_adjoint(const rexii_swe_op*, const double*, const double*, double*, double*, double,
-                                 const rexii_opts*, void*, size_t, hipStream_t, rexii_report*) {
-  return set_error(REXII_ERR_INVALID_ARG, "rexii_apply_adjoint: not implemented yet");
+rexii_status rexii_apply_adjoint(const rexii_swe_op* op, const double* f, const double* gbar, double* dJdf,
+                                 double* dJdH, double t, const rexii_opts* opts, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream, rexii_report* rep) {
+  rexii_status v = check_op_and_t(op, t, false);
+  if (v != REXII_OK) return v;
+  if (!gbar) return set_error(REXII_ERR_INVALID_ARG, "gbar is NULL");
+  if (!dJdf && !dJdH) return set_error(REXII_ERR_INVALID_ARG, "nothing to compute (dJdf and dJdH are NULL)");
+  if (dJdH && !f) return set_error(REXII_ERR_INVALID_ARG, "dJdH needs f");
+  const size_t n3 = 3 * size_t(op->nx) * op->ny;
+  if (dJdf && (overlaps(dJdf, n3, gbar, n3) || (f && overlaps(dJdf, n3, f, n3))))
+    return set_error(REXII_ERR_INVALID_ARG, "dJdf overlaps an input");
+  return run_adjoint(op, f, gbar, dJdf, dJdH, t, opts, workspace, ws_bytes, stream, rep);
 }
 
-rexii_status rexii_apply_batched(int32_t, const rexii_swe_op*, const double* const*, double* const*, const double*,
-                                 const rexii_opts*, void*, size_t, hipStream_t, rexii_report*) {
-  return set_error(REXII_ERR_INVALID_ARG, "rexii_apply_batched: not implemented yet");
+rexii_status rexii_apply_batched(int32_t count, const rexii_swe_op* ops, const double* const* f, double* const* u,
+                                 const double* t, const rexii_opts* opts, void* workspace, size_t ws_bytes,
+                                 hipStream_t stream, rexii_report* reps) {
+  if (count <= 0 || !ops || !f || !u || !t) return set_error(REXII_ERR_INVALID_ARG, "need count > 0 and arrays");
+  std::vector<JobItem> items(count);
+  for (int i = 0; i < count; ++i) {
+    rexii_status v = check_op_and_t(&ops[i], t[i], true);
+    if (v != REXII_OK) return v;
+    if (!f[i] || !u[i]) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer in batch");
+    const size_t n3 = 3 * size_t(ops[i].nx) * ops[i].ny;
+    if (overlaps(f[i], n3, u[i], n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f in batch");
+    items[i].op = &ops[i];
+    items[i].f = f[i];
+    items[i].u = u[i];
+    items[i].t = t[i];
+    items[i].rep = reps ? &reps[i] : nullptr;
+  }
+  return run_items(items, opts, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

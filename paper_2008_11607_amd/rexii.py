@@ -50,9 +50,9 @@ class Report(ctypes.Structure):
                 ("rho", ctypes.c_double), ("kappa_sum", ctypes.c_double),
                 ("pole_tol", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double),
-                ("mv_launches", ctypes.c_int64), ("up_launches", ctypes.c_int64),
-                ("mv_ms", ctypes.c_double), ("up_ms", ctypes.c_double),
-                ("mv_bytes", ctypes.c_double), ("up_bytes", ctypes.c_double)]
+                ("stagnated", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+                ("kernel_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -226,3 +226,96 @@ def workspace_size(nx, ny, t, g=1.0, fc=10.0, H=1.0, **opts):
     out = ctypes.c_size_t()
     _check(lib.rexii_workspace_size(ctypes.byref(op), ctypes.byref(o), float(t), ctypes.byref(out)))
     return out.value
+
+
+def apply_adjoint(f, gbar, t, g=1.0, fc=10.0, H=1.0, want_dJdf=True, want_dJdH=True, **opts):
+    """Reverse mode of apply for a loss J(u): gbar = dJ/du (float64 CUDA
+    [3, ny, nx]).  Returns (dJdf tensor or None, dJdH float or None, report).
+    The pole set is the one apply uses for (t, H) and is held fixed."""
+    import torch
+    lib = load()
+    _dev_f64(gbar)
+    ny, nx = gbar.shape[1], gbar.shape[2]
+    if f is not None:
+        _dev_f64(f, gbar.shape)
+    dJdf = torch.empty_like(gbar) if want_dJdf else None
+    dJdH = ctypes.c_double(0.0)
+    op = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_apply_adjoint(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()) if f is not None else None,
+                                 ctypes.c_void_p(gbar.data_ptr()),
+                                 ctypes.c_void_p(dJdf.data_ptr()) if dJdf is not None else None,
+                                 ctypes.byref(dJdH) if want_dJdH else None, float(t), ctypes.byref(o), None, 0,
+                                 _stream(), ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return dJdf, (dJdH.value if want_dJdH else None), rep.as_dict()
+
+
+def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, **opts):
+    """u_i = exp(t_i A_i) f_i for a list of states (grids may differ) in one
+    call: all problems' solves share one slot scheduler.  g, fc, H may be
+    scalars or per-problem lists.  Returns (list of u, list of reports)."""
+    import torch
+    lib = load()
+    cnt = len(fs)
+
+    def per(v, i):
+        return v[i] if isinstance(v, (list, tuple)) else v
+
+    ops = (SweOp * cnt)()
+    us = [torch.empty_like(_dev_f64(f)) for f in fs]
+    for i, f in enumerate(fs):
+        ops[i] = make_op(f.shape[2], f.shape[1], per(g, i), per(fc, i), per(H, i), None)
+    fptr = (ctypes.c_void_p * cnt)(*[ctypes.c_void_p(f.data_ptr()) for f in fs])
+    uptr = (ctypes.c_void_p * cnt)(*[ctypes.c_void_p(u.data_ptr()) for u in us])
+    tarr = (ctypes.c_double * cnt)(*[float(t) for t in ts])
+    reps = (Report * cnt)()
+    o = make_opts(**opts)
+    st = lib.rexii_apply_batched(cnt, ops, fptr, uptr, tarr, ctypes.byref(o), None, 0, _stream(), reps)
+    _check(st, [r.as_dict() for r in reps])
+    return us, [r.as_dict() for r in reps]
+
+
+def _autograd_fn():
+    import torch
+
+    class RexiiExp(torch.autograd.Function):
+        """u = exp(tA(H)) f with gradients w.r.t. f and the constant depth H
+        (a 0-d float64 tensor).  The pole set is frozen at the forward call
+        (its rho is taken at the given H), so the gradient is that of the
+        fixed rational approximation."""
+
+        @staticmethod
+        def forward(ctx, f, H, t, g, fc, opts):
+            Hv = float(H)
+            rho = opts.get("rho") or globals()["rho"](f.shape[2], f.shape[1], g=g, fc=fc, H=Hv)
+            o = dict(opts)
+            o["rho"] = rho
+            u, _ = apply(f.contiguous(), t, g=g, fc=fc, H=Hv, **o)
+            ctx.save_for_backward(f)
+            ctx.args = (Hv, t, g, fc, o)
+            return u
+
+        @staticmethod
+        def backward(ctx, gu):
+            (f,) = ctx.saved_tensors
+            Hv, t, g, fc, o = ctx.args
+            need_f, need_H = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            dJdf, dJdH, _ = apply_adjoint(f.contiguous(), gu.contiguous(), t, g=g, fc=fc, H=Hv,
+                                          want_dJdf=need_f, want_dJdH=need_H, **o)
+            gH = torch.tensor(dJdH, dtype=torch.float64, device=f.device) if need_H else None
+            return dJdf, gH, None, None, None, None
+
+    return RexiiExp
+
+
+_RexiiExp = None
+
+
+def rexii_exp(f, H, t, g=1.0, fc=10.0, **opts):
+    """Differentiable u = exp(t A(H)) f (see RexiiExp)."""
+    global _RexiiExp
+    if _RexiiExp is None:
+        _RexiiExp = _autograd_fn()
+    return _RexiiExp.apply(f, H, t, g, fc, opts)

@@ -1,0 +1,55 @@
+"""Batched calls: problems of different grid size and time step in one slot
+engine, against the oracle and against one call per problem."""
+import numpy as np
+import pytest
+
+from oracle import expm_modes as em
+from oracle import lrsw
+from paper_2008_11607_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2008_11607_amd import rexii
+    rexii.load()
+    return rexii
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_batched_heterogeneous(rx, precision, bar):
+    shapes = [(64, 64, 80.0), (96, 64, 150.0), (128, 128, 300.0), (48, 40, 40.0), (128, 128, 60.0)]
+    fs, ts, ops = [], [], []
+    for i, (nx, ny, trho) in enumerate(shapes):
+        op = lrsw.LRSW(nx, ny, fc=10.0)
+        fs.append(inputs.gaussian_bumps(nx, ny, nbumps=16, seed=300 + i, velocity=(i == 3)))
+        ts.append(trho / lrsw.rho(op))
+        ops.append(op)
+    us, reps = rx.apply_batched([_dev(f) for f in fs], ts, fc=10.0, precision=precision)
+    for f, t, op, u, rep in zip(fs, ts, ops, us, reps):
+        assert rep["not_converged"] == 0
+        assert em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t)) <= bar
+    # the same problems one at a time agree to the solver tolerance
+    for f, t, u in zip(fs[:2], ts[:2], us[:2]):
+        u1, _ = rx.apply(_dev(f), t, fc=10.0, precision=precision)
+        assert em.rel_l2(u.cpu().numpy(), u1.cpu().numpy()) <= 10 * bar
+
+
+def test_batched_with_t_zero_and_single(rx):
+    f0 = inputs.gaussian_bumps(32, nbumps=2, seed=1)
+    f1 = inputs.gaussian_bumps(40, nbumps=2, seed=2)
+    op1 = lrsw.LRSW(40, 40, fc=10.0)
+    t1 = 30.0 / lrsw.rho(op1)
+    us, reps = rx.apply_batched([_dev(f0), _dev(f1)], [0.0, t1], fc=10.0)
+    assert np.array_equal(us[0].cpu().numpy(), f0)
+    assert em.rel_l2(us[1].cpu().numpy(), em.expm_closed_real(op1, f1, t1)) <= 1e-10
+    us, reps = rx.apply_batched([_dev(f1)], [t1], fc=10.0)
+    assert em.rel_l2(us[0].cpu().numpy(), em.expm_closed_real(op1, f1, t1)) <= 1e-10

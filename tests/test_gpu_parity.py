@@ -118,7 +118,7 @@ def test_profile_mode_same_result(rx):
     a, _ = rx.apply(fd, t, fc=10.0)
     b, rep = rx.apply(fd, t, fc=10.0, profile=1)
     assert bool((a == b).all())
-    assert rep["up_launches"] > 0 and rep["up_ms"] > 0 and rep["up_bytes"] > 0
+    assert rep["kernel_launches"] > 0 and rep["kernel_ms"] > 0 and rep["kernel_bytes"] > 0
 
 
 def test_t_zero_copies(rx):

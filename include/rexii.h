@@ -84,12 +84,21 @@ typedef struct rexii_opts {
     int32_t m0;             /* safety term of the M rule; < 0 -> from tol   */
     double rho;             /* bound on the spectral radius of A; <= 0 ->
                                computed (exact for constant depth)          */
-    int32_t pole_batch;     /* concurrent solves per batch; 0 -> automatic  */
+    int32_t pole_batch;     /* concurrent solves (slots); 0 -> heuristic;
+                               < 0 -> autotuned: candidate slot counts are
+                               timed on the problem itself and the best is
+                               cached per grid, precision, method and CU
+                               count in $REXII_TUNE_CACHE (default
+                               $HOME/.cache/rexii_tune.txt)                 */
     int32_t pair_conjugate; /* 1: when div(u0, v0) == 0 the two poles of a
                                term share one Krylov solve (exact identity);
                                0: one solve per pole.  Default 1            */
     double inner_tol;       /* MIXED: relative residual reduction of one FP32
                                inner solve; 0 -> 1e-4                      */
+    int32_t method;         /* 0: automatic (COCG on the constant-depth
+                               Helmholtz, BiCGStab for a depth field);
+                               1: BiCGStab on the flux form also for
+                               constant depth                              */
     int32_t profile;        /* 1: launch the inner kernels one by one with
                                HIP events around each (fills the kernel
                                timing fields of the report); 0: replay them
@@ -113,7 +122,7 @@ typedef struct rexii_report {
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
     int32_t stagnated;       /* solves stopped at their FP64 residual floor
                                (above pole_tol; counted as converged)       */
-    int32_t pad_;
+    int32_t slots;           /* concurrent solves the engine ran with        */
     /* with opts.profile = 1: launches and summed HIP-event time of the COCG
      * pass kernel, and the algorithmic bytes of those launches (a pass reads
      * x, r, p and writes them once: 6 complex values per grid point and
@@ -142,7 +151,8 @@ rexii_status rexii_coeffs(double t, double rho, double h, double tol, int32_t m0
 /* Spectral radius bound of A (eq. matrixAccuracyBound needs an upper bound).
  * Constant depth: exact, sqrt(f_c^2 + g H0 max(s_x^2 + s_y^2)) with
  * s_x = nx sin(2 pi k / nx).  Variable depth: the guaranteed
- * sqrt(g max H) sqrt(nx^2 + ny^2) + |f_c| (reads H_field on `stream`). */
+ * sqrt(g max H) sqrt(nx^2 + ny^2) + |f_c| (reads H_field on `stream`;
+ * REXII_ERR_NONFINITE if a depth is not finite and positive). */
 rexii_status rexii_rho(const rexii_swe_op* op, hipStream_t stream, double* rho);
 
 /* Device workspace rexii_apply / rexii_apply_adjoint need for these

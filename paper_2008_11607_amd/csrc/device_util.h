@@ -1,0 +1,202 @@
+// Device helpers shared by the REXII kernel sources: complex arithmetic,
+// coherent loads of control data, periodic indexing, deterministic block
+// reductions and the (slot, tile) work mapping.
+#ifndef REXII_DEVICE_UTIL_H
+#define REXII_DEVICE_UTIL_H
+
+#include "kernels.h"
+
+namespace rexii {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+template <typename T> struct C2;
+template <> struct C2<float> { using t = float2; };
+template <> struct C2<double> { using t = double2; };
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) {
+  V r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) {
+  V r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+template <typename V>
+__device__ __forceinline__ V mk(double x, double y) {
+  V r;
+  r.x = static_cast<decltype(r.x)>(x);
+  r.y = static_cast<decltype(r.y)>(y);
+  return r;
+}
+__device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+// streaming (non-temporal) access to complex values
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+#ifdef REXII_NO_NT
+__device__ __forceinline__ float2 nt_load(const float2* p) { return *p; }
+__device__ __forceinline__ double2 nt_load(const double2* p) { return *p; }
+__device__ __forceinline__ void nt_store(float2 a, float2* p) { *p = a; }
+__device__ __forceinline__ void nt_store(double2 a, double2* p) { *p = a; }
+#else
+__device__ __forceinline__ float2 nt_load(const float2* p) {
+  const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+  const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void nt_store(float2 a, float2* p) {
+  nf2 v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<nf2*>(p));
+}
+__device__ __forceinline__ void nt_store(double2 a, double2* p) {
+  nd2 v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<nd2*>(p));
+}
+#endif
+
+// Control data (slot state, tile table, counters, partial sums) is written
+// by one kernel and read by later ones.  Reads go through agent-scope
+// atomic loads: a plain uniform load may be served from the scalar cache,
+// which is not kept coherent with vector stores of earlier launches.
+__device__ __forceinline__ int ldc(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ double ldc(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ldc(const double2* p) { return make_double2(ldc(&p->x), ldc(&p->y)); }
+template <typename P>
+__device__ __forceinline__ P* ldc_ptr(P* const* p) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  return reinterpret_cast<P*>(v);
+}
+// Problem and solve tables are uploaded once per call into reused workspace
+// addresses: read them the same way.
+__device__ __forceinline__ Inst ld_inst(const Inst* p) {
+  Inst I;
+  I.nx = ldc(&p->nx);
+  I.ny = ldc(&p->ny);
+  I.tiles_x = ldc(&p->tiles_x);
+  I.nblk = ldc(&p->nblk);
+  I.cx = ldc(&p->cx);
+  I.cy = ldc(&p->cy);
+  I.cxy = ldc(&p->cxy);
+  I.H = ldc_ptr(&p->H);
+  I.eta0 = ldc_ptr(&p->eta0);
+  I.D0 = ldc_ptr(&p->D0);
+  I.Z0 = ldc_ptr(&p->Z0);
+  I.A = ldc_ptr(&p->A);
+  return I;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+// Periodic index for i in [-n, 2n): one conditional add or subtract.
+__device__ __forceinline__ int wrap1(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+// Either form, chosen once per tile (block-uniform): the single-step form
+// is exact when the tile with its halo is no larger than the grid.
+__device__ __forceinline__ int wrapc(int i, int n, bool big) { return big ? wrap1(i, n) : wrap(i, n); }
+
+// ---------------------------------------------------------------------------
+// deterministic reductions (256 threads = 4 wavefronts of 64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduces v[0..N) over the block into out[0..N) (valid in thread 0).
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh, double (&out)[N]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[wid * N + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = (sh[k] + sh[N + k]) + (sh[2 * N + k] + sh[3 * N + k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// work items (slot, tile)
+// ---------------------------------------------------------------------------
+struct Item {
+  int slot, tile;
+};
+
+// Position pos in [0, total) -> (slot, tile) by binary search in the
+// exclusive prefix sums ts[0..B].
+__device__ __forceinline__ Item item_of_search(const int* ts, int B, int pos) {
+  int lo = 0, hi = B;  // ts[lo] <= pos < ts[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ldc(&ts[mid]) <= pos) lo = mid;
+    else hi = mid;
+  }
+  Item it;
+  it.slot = lo;
+  it.tile = pos - ldc(&ts[lo]);
+  return it;
+}
+
+// (slot, tile) of position pos: one load from the compact list of working
+// slots when they all have the same tile count, else a binary search.
+__device__ __forceinline__ Item item_of(const Eng& e, int pos, int uniform_nblk) {
+  if (uniform_nblk > 0) {
+    const int k = pos / uniform_nblk;
+    Item it;
+    it.slot = ldc(&e.work[2 + k]);
+    it.tile = pos - k * uniform_nblk;
+    return it;
+  }
+  return item_of_search(e.tile_start, e.B, pos);
+}
+
+// XCD-major numbering: loop index w (block b handles w = b, b + G, ...)
+// runs on XCD w % 8 when G % 8 == 0; map it to position
+// (w % 8) * ceil(total / 8) + w / 8 so each XCD owns a contiguous range.
+#ifdef REXII_NO_XCD
+__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return w; }
+#else
+__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return (w & 7) * per_xcd + (w >> 3); }
+#endif
+
+}  // namespace rexii
+
+#endif

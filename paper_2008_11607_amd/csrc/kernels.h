@@ -55,6 +55,8 @@ enum SlotStatus : int {
 struct Inst {
   int nx, ny, tiles_x, nblk;
   double cx, cy;          // (nx/2)^2, (ny/2)^2
+  double cxy;             // nx ny / 4 (cross term of the variable-depth operator)
+  const double* H;        // depth field [ny][nx] (BiCGStab path) or nullptr
   const double* eta0;     // [ny][nx]
   const double* D0;       // div(u0, v0) or nullptr
   const double* Z0;       // curl(u0, v0) or nullptr
@@ -64,6 +66,7 @@ struct Inst {
 // One shifted system (device table, read by the scheduler).
 struct SolveDev {
   double2 zeta, a1, a2;   // shift and RHS coefficients
+  double2 gamma, sc;      // BiCGStab path: cross-term factor, RHS scale
   double2 c0, c1, c2;     // accumulation weights
   double tol2;            // done when ||b - K x||^2 <= tol2 ||b||^2
   int inst;
@@ -78,8 +81,10 @@ struct SolveStat {
 
 struct Slot {
   double2 zeta, a1, a2;
-  double2 rr;        // r^T r of the current inner iterate
+  double2 gamma, sc; // BiCGStab path (see SolveDev)
+  double2 rr;        // COCG: r^T r; BiCGStab: rho = <r_hat, r>
   double2 alpha, beta;
+  double2 omega;     // BiCGStab
   double bn2;        // ||b||^2
   double rn2;        // latest FP64 true residual ||b - K x||^2
   double prev_rn2;   // residual of the previous FP64 round
@@ -105,13 +110,15 @@ struct Eng {
   int cap_blk;           // partial-sum slots per slot (max tiles)
   double inner_eta2;     // relative reduction^2 of one inner solve
   int max_iter;
-  int pad;
+  int method;            // 0: COCG on the constant-depth Helmholtz; 1: BiCGStab (flux form)
   Slot* slots;           // [B]
   const Inst* inst;      // [ninst]
   const SolveDev* solves;// [S]
   SolveStat* stats;      // [S]
   int* next;             // [1] next solve to hand out
   int* tile_start;       // [B + 1] exclusive prefix of tiles of working slots
+  int* work;             // [B + 2]: [0] working slots, [1] their common tile
+                         // count (0 if they differ), [2..] slot indices
   int* counter;          // [4] host-visible counts
   double* part;          // [B][cap_blk][kNDots]
   double2* x64;          // [B][cap]
@@ -120,6 +127,9 @@ struct Eng {
   void* r1;
   void* p0;
   void* p1;
+  void* v0;              // BiCGStab: v = K p (ping-pong) and the shadow residual
+  void* v1;
+  void* rh;
   double2* yout;         // nullptr: accumulate; else [S][cap] solutions
   int* dbg;              // [16] consistency counters (debug builds only)
 };
@@ -139,6 +149,23 @@ struct AdjDot {
 
 template <typename T>
 void launch_pass(const Eng& e, int grid, hipStream_t s);
+// Variable-depth (flux form) shifted systems, per pole:
+//   K eta = (L_H + gamma C_H - zeta) eta = sc (eta0 + a1 D_H + a2 Z_H),
+//   L_H = dx(H dx .) + dy(H dy .),  C_H = dx(H dy .) - dy(H dx .),
+//   gamma = t f_c / z,  zeta = (z^2 + t^2 f_c^2) / (t^2 g),  sc = zeta / z,
+//   a1 = t m1, a2 = t m2, D_H = div(H (u0, v0)), Z_H = dx(H v0) - dy(H u0),
+// solved by BiCGStab (K is not complex-symmetric: C_H is antisymmetric).
+template <typename T>
+void launch_bcg(const Eng& e, int grid, hipStream_t s);   // passes A, B, C with their scalar kernels
+template <typename T>
+void launch_outer_residual_vh(const Eng& e, int grid, hipStream_t s);
+void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
+                    double* hmax_part, hipStream_t s);
+int prep_vh_blocks();
+void launch_hmax(const double* H, size_t n, int* flags, double* part, hipStream_t s);
+void launch_fill_value(double* p, size_t n, double v, hipStream_t s);
+int bcg_occupancy(int mixed);
+
 template <typename T>
 void launch_outer_update(const Eng& e, int grid, hipStream_t s);
 template <typename T>
@@ -157,6 +184,7 @@ void launch_expand(const double2* y, const double* f, int nx, int ny, double2 in
                    double2 m2, double tg, int has_vel, double2* out, hipStream_t s);
 void launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 void launch_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2, hipStream_t s);
+void launch_scale1(double* p, size_t n, double s, hipStream_t st);
 int adj_dot_blocks(size_t n);
 void launch_adj_dots(const AdjDot* d, int nd, const double2* yout, int cap, const double* eta0, const double* D0,
                      const double* Z0, int nx, int ny, double tg, int has_vel, double2* part, int nblk,

@@ -12,182 +12,10 @@
 // runs on XCD b % 8) walks one contiguous range of tiles, keeping the halo
 // rows of neighbouring tiles in that XCD's L2.
 #include "kernels.h"
+#include "device_util.h"
 
 namespace rexii {
 
-// ---------------------------------------------------------------------------
-// complex helpers
-// ---------------------------------------------------------------------------
-template <typename T> struct C2;
-template <> struct C2<float> { using t = float2; };
-template <> struct C2<double> { using t = double2; };
-
-template <typename V>
-__device__ __forceinline__ V cmul(V a, V b) {
-  V r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
-template <typename V>
-__device__ __forceinline__ V cadd(V a, V b) {
-  V r;
-  r.x = a.x + b.x;
-  r.y = a.y + b.y;
-  return r;
-}
-template <typename V>
-__device__ __forceinline__ V csub(V a, V b) {
-  V r;
-  r.x = a.x - b.x;
-  r.y = a.y - b.y;
-  return r;
-}
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  const double den = b.x * b.x + b.y * b.y;
-  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
-}
-template <typename V>
-__device__ __forceinline__ V mk(double x, double y) {
-  V r;
-  r.x = static_cast<decltype(r.x)>(x);
-  r.y = static_cast<decltype(r.y)>(y);
-  return r;
-}
-__device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
-
-// streaming (non-temporal) access to complex values
-typedef float nf2 __attribute__((ext_vector_type(2)));
-typedef double nd2 __attribute__((ext_vector_type(2)));
-#ifdef REXII_NO_NT
-__device__ __forceinline__ float2 nt_load(const float2* p) { return *p; }
-__device__ __forceinline__ double2 nt_load(const double2* p) { return *p; }
-__device__ __forceinline__ void nt_store(float2 a, float2* p) { *p = a; }
-__device__ __forceinline__ void nt_store(double2 a, double2* p) { *p = a; }
-#else
-__device__ __forceinline__ float2 nt_load(const float2* p) {
-  const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p));
-  return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ double2 nt_load(const double2* p) {
-  const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
-  return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void nt_store(float2 a, float2* p) {
-  nf2 v;
-  v.x = a.x;
-  v.y = a.y;
-  __builtin_nontemporal_store(v, reinterpret_cast<nf2*>(p));
-}
-__device__ __forceinline__ void nt_store(double2 a, double2* p) {
-  nd2 v;
-  v.x = a.x;
-  v.y = a.y;
-  __builtin_nontemporal_store(v, reinterpret_cast<nd2*>(p));
-}
-#endif
-
-// Control data (slot state, tile table, counters, partial sums) is written
-// by one kernel and read by later ones.  Reads go through agent-scope
-// atomic loads: a plain uniform load may be served from the scalar cache,
-// which is not kept coherent with vector stores of earlier launches.
-__device__ __forceinline__ int ldc(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ __forceinline__ double ldc(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double2 ldc(const double2* p) { return make_double2(ldc(&p->x), ldc(&p->y)); }
-template <typename P>
-__device__ __forceinline__ P* ldc_ptr(P* const* p) {
-  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-  return reinterpret_cast<P*>(v);
-}
-// Problem and solve tables are uploaded once per call into reused workspace
-// addresses: read them the same way.
-__device__ __forceinline__ Inst ld_inst(const Inst* p) {
-  Inst I;
-  I.nx = ldc(&p->nx);
-  I.ny = ldc(&p->ny);
-  I.tiles_x = ldc(&p->tiles_x);
-  I.nblk = ldc(&p->nblk);
-  I.cx = ldc(&p->cx);
-  I.cy = ldc(&p->cy);
-  I.eta0 = ldc_ptr(&p->eta0);
-  I.D0 = ldc_ptr(&p->D0);
-  I.Z0 = ldc_ptr(&p->Z0);
-  I.A = ldc_ptr(&p->A);
-  return I;
-}
-
-__device__ __forceinline__ int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
-}
-// Periodic index for i in [-n, 2n): one conditional add or subtract.
-__device__ __forceinline__ int wrap1(int i, int n) {
-  return i < 0 ? i + n : (i >= n ? i - n : i);
-}
-// Either form, chosen once per tile (block-uniform): the single-step form
-// is exact when the tile with its halo is no larger than the grid.
-__device__ __forceinline__ int wrapc(int i, int n, bool big) { return big ? wrap1(i, n) : wrap(i, n); }
-
-// ---------------------------------------------------------------------------
-// deterministic reductions (256 threads = 4 wavefronts of 64)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Reduces v[0..N) over the block into out[0..N) (valid in thread 0).
-template <int N>
-__device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh, double (&out)[N]) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) sh[wid * N + k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) out[k] = (sh[k] + sh[N + k]) + (sh[2 * N + k] + sh[3 * N + k]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// work items (slot, tile)
-// ---------------------------------------------------------------------------
-struct Item {
-  int slot, tile;
-};
-
-// Position pos in [0, total) -> (slot, tile) by binary search in the
-// exclusive prefix sums ts[0..B].
-__device__ __forceinline__ Item item_of(const int* ts, int B, int pos) {
-  int lo = 0, hi = B;  // ts[lo] <= pos < ts[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (ldc(&ts[mid]) <= pos) lo = mid;
-    else hi = mid;
-  }
-  Item it;
-  it.slot = lo;
-  it.tile = pos - ldc(&ts[lo]);
-  return it;
-}
-
-// XCD-major numbering: loop index w (block b handles w = b, b + G, ...)
-// runs on XCD w % 8 when G % 8 == 0; map it to position
-// (w % 8) * ceil(total / 8) + w / 8 so each XCD owns a contiguous range.
-#ifdef REXII_NO_XCD
-__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return w; }
-#else
-__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return (w & 7) * per_xcd + (w >> 3); }
-#endif
 
 // Stencil (L - zeta) v at LDS position (y, x) of a tile with row width W.
 template <typename V, typename S, int W>
@@ -243,12 +71,13 @@ __global__ __launch_bounds__(kNT) void k_pass(Eng e) {
   __shared__ double red[4 * kNDots];
 
   const int total = ldc(&e.tile_start[e.B]);
+  const int un = ldc(&e.work[1]);
   const int per = (total + 7) >> 3;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e.tile_start, e.B, pos);
+    const Item it = item_of(e, pos, un);
     Slot* S = &e.slots[it.slot];
 #ifdef REXII_DEBUG_CHECKS
     {
@@ -438,12 +267,13 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_outer_update(Eng e) {
   using V = typename C2<T>::t;
   const int total = ldc(&e.tile_start[e.B]);
+  const int un = ldc(&e.work[1]);
   const int per = (total + 7) >> 3;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e.tile_start, e.B, pos);
+    const Item it = item_of(e, pos, un);
     const Slot* S = &e.slots[it.slot];
     if (ldc(&S->status) != kInnerDone) continue;
     const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
@@ -475,12 +305,13 @@ __global__ __launch_bounds__(kNT) void k_outer_residual(Eng e) {
   __shared__ double2 XT[H * W];
   __shared__ double red[4 * 2];
   const int total = ldc(&e.tile_start[e.B]);
+  const int un = ldc(&e.work[1]);
   const int per = (total + 7) >> 3;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e.tile_start, e.B, pos);
+    const Item it = item_of(e, pos, un);
     Slot* S = &e.slots[it.slot];
     const int st = ldc(&S->status);
     if (st != kInnerDone && st != kOuterPending) continue;
@@ -539,7 +370,10 @@ __global__ __launch_bounds__(kNT) void k_outer_scalars(Eng e) {
   const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
   double v[2] = {0.0, 0.0}, tot[2];
   const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
-  for (int b = threadIdx.x; b < nblk; b += kNT) v[0] += ldc(&pp[size_t(b) * kNDots]);
+  for (int b = threadIdx.x; b < nblk; b += kNT) {
+    v[0] += ldc(&pp[size_t(b) * kNDots]);
+    if (e.method == 1) v[1] += ldc(&pp[size_t(b) * kNDots + 1]);
+  }
   block_sum_n<2>(v, red, tot);
   if (threadIdx.x != 0) return;
   const double rn2 = tot[0];
@@ -572,6 +406,9 @@ __global__ __launch_bounds__(kNT) void k_outer_scalars(Eng e) {
     S->it_inner = 0;
     S->alpha = make_double2(0.0, 0.0);
     S->beta = make_double2(0.0, 0.0);
+    S->omega = make_double2(0.0, 0.0);
+    // BiCGStab starts from rho = <r_hat, r> = |r|^2 of the rounded residual
+    if (e.method == 1) S->rr = make_double2(tot[1], 0.0);
     // the requested reduction of this residual, never below a quarter of
     // the final tolerance
     S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
@@ -616,6 +453,7 @@ __global__ void k_assign(Eng e) {
   int next = ldc(e.next);
   int working = 0;
   int acc = 0;
+  int uniform = 0;
 #ifdef REXII_DEBUG_CHECKS
   {
     int fin = 0;
@@ -644,6 +482,9 @@ __global__ void k_assign(Eng e) {
       S->zeta = ldc(&D->zeta);
       S->a1 = ldc(&D->a1);
       S->a2 = ldc(&D->a2);
+      S->gamma = ldc(&D->gamma);
+      S->sc = ldc(&D->sc);
+      S->omega = make_double2(0.0, 0.0);
       S->tol2 = ldc(&D->tol2);
       S->rr = S->alpha = S->beta = make_double2(0.0, 0.0);
       S->bn2 = S->rn2 = S->prev_rn2 = S->in_tol2 = 0.0;
@@ -659,11 +500,16 @@ __global__ void k_assign(Eng e) {
     }
     e.tile_start[s] = acc;
     if (status != kIdle) {
-      acc += ldc(&e.inst[ldc(&S->inst)].nblk);
+      const int nb = ldc(&e.inst[ldc(&S->inst)].nblk);
+      acc += nb;
+      e.work[2 + working] = s;
+      uniform = (working == 0) ? nb : (uniform == nb ? nb : 0);
       ++working;
     }
   }
   e.tile_start[e.B] = acc;
+  e.work[0] = working;
+  e.work[1] = uniform;
   *e.next = next;
   e.counter[0] = working + (next < e.S ? 1 : 0);
   e.counter[1] = next;
@@ -827,6 +673,13 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const double2* part, int nbl
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+__global__ void k_scale1(double* p, size_t n, double v) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] *= v;
+}
+void launch_scale1(double* p, size_t n, double v, hipStream_t s) {
+  size_t bl = (n + 255) / 256;
+  hipLaunchKernelGGL(k_scale1, dim3(unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl))), dim3(256), 0, s, p, n, v);
+}
 void launch_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2, hipStream_t s) {
   size_t bl = (n + 255) / 256;
   hipLaunchKernelGGL(k_scale3, dim3(unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl))), dim3(256), 0, s, src, dst, n,

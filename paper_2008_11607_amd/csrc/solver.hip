@@ -16,6 +16,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -93,6 +94,7 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // ---------------------------------------------------------------------------
 struct SolveDesc {
   cd zeta, a1, a2;     // Helmholtz shift and RHS coefficients
+  cd gamma = 0.0, sc = 1.0;  // flux-form (BiCGStab) path: cross-term factor, RHS scale
   cd c0, c1, c2;       // accumulation weights (A_j += Re(c_j y))
   cd inv_sigma, m1, m2;
   double cost;         // expected relative Krylov cost (for scheduling)
@@ -109,6 +111,8 @@ struct Plan {
   double inner_eta;
   bool paired;
   bool has_vel;
+  bool bicg = false;   // flux-form operator solved by BiCGStab
+  double hmax = 0.0;   // max depth (variable depth)
   int B;               // slots per batch
   int chunk;           // inner iterations per graph replay
   bool profile = false;
@@ -166,7 +170,7 @@ static rexii_opts resolve_opts(const rexii_opts* o) {
 
 // Pole set, shifts, weights and scheduling (host, FP64).
 static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opts& o, bool has_vel,
-                               bool div_free, Plan& pl, bool adjoint = false) {
+                               bool div_free, Plan& pl, bool adjoint = false, double hmax = 0.0) {
   pl.nx = op->nx;
   pl.ny = op->ny;
   pl.g = op->g;
@@ -180,12 +184,19 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   pl.inner_eta = (o.precision == REXII_PREC_MIXED) ? o.inner_tol : 0.0;
   pl.has_vel = has_vel;
   pl.profile = (o.profile != 0);
-  pl.paired = (o.pair_conjugate != 0) && div_free;
+  pl.bicg = (op->H_field != nullptr) || (o.method == 1);
+  pl.hmax = op->H_field ? hmax : op->H0;
+  // the two poles of a term give conjugate systems only for the symmetric
+  // constant-depth operator
+  pl.paired = (o.pair_conjugate != 0) && div_free && !pl.bicg;
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
   if (o.precision != REXII_PREC_FP64 && o.precision != REXII_PREC_MIXED)
     return set_error(REXII_ERR_INVALID_ARG, "unknown precision");
-  pl.rho = (o.rho > 0.0) ? o.rho : rho_const(op->nx, op->ny, op->g, op->H0, op->f_cor);
+  if (op->H_field && !(hmax > 0.0)) return set_error(REXII_ERR_INVALID_ARG, "variable depth needs max H > 0");
+  pl.rho = (o.rho > 0.0) ? o.rho
+           : (op->H_field ? rho_bound_var(op->nx, op->ny, op->g, hmax, op->f_cor)
+                          : rho_const(op->nx, op->ny, op->g, op->H0, op->f_cor));
   pl.m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
   const double Md = std::ceil(t * pl.rho / pl.h) + pl.m0;
   if (Md > 2.0e6) return set_error(REXII_ERR_INVALID_ARG, "t*rho/h too large for this library");
@@ -230,7 +241,29 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
     pl.S2 += (pl.w[k] * m2[k]).real();
   }
   pl.solves.clear();
-  if (pl.paired) {
+  if (pl.bicg) {
+    // flux form: (L_H + gamma C_H - zeta) eta = sc (eta0 + t m1 D_H + t m2 Z_H),
+    // solved for eta itself (no 1/sigma scaling)
+    for (int k = 0; k < pl.P; ++k) {
+      const cd zk = pl.z[k];
+      const cd den = zk * zk + t * t * fc * fc;
+      SolveDesc s;
+      s.zeta = den / (t * t * g);
+      s.gamma = t * fc / zk;
+      s.sc = s.zeta / zk;
+      s.a1 = t * m1[k];
+      s.a2 = t * m2[k];
+      s.inv_sigma = 1.0;
+      s.m1 = m1[k];
+      s.m2 = m2[k];
+      s.c0 = pl.w[k];
+      s.c1 = pl.w[k] * m1[k];
+      s.c2 = pl.w[k] * m2[k];
+      s.cost = cheb_cost(s.zeta / pl.hmax, lmax, pl.pole_tol);
+      s.pole = k;
+      pl.solves.push_back(s);
+    }
+  } else if (pl.paired) {
     for (int n = 0; 2 * n < pl.P; ++n) {
       const int k = 2 * n;
       SolveDesc s;
@@ -275,13 +308,13 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
 
 // Slots for a set of problems: enough tiles to fill the chip several times
 // over, within a memory budget, never more than the number of solves.
-static int choose_slots(int requested, size_t max_points, int max_nblk, size_t nsolves, int precision) {
+static int choose_slots(int requested, size_t max_points, int max_nblk, size_t nsolves, int precision, int nvec) {
   int B = requested;
   if (B <= 0) {
     B = (16384 + max_nblk - 1) / max_nblk;
     B = std::max(8, std::min(B, 1024));
   }
-  const size_t per_slot = max_points * (16 + 5 * inner_elem_bytes(precision));
+  const size_t per_slot = max_points * (16 + nvec * inner_elem_bytes(precision));
   const size_t budget = size_t(24) << 30;
   B = int(std::max<size_t>(1, std::min<size_t>(size_t(B), budget / per_slot)));
   B = int(std::min<size_t>(size_t(B), std::max<size_t>(1, nsolves)));
@@ -296,11 +329,14 @@ struct Problem {
   const double* f = nullptr;   // device [3][ny][nx]
   double* DZ = nullptr;        // device div / curl of the initial velocity
   double* A = nullptr;         // device accumulators [3][ny][nx]
+  const double* H = nullptr;   // device depth field (flux-form path)
   size_t n() const { return size_t(pl.nx) * pl.ny; }
 };
 
 struct EngineSize {
   int B = 1, cap = 0, cap_blk = 0, S = 0, ninst = 0;
+  int method = 0;   // 0 COCG, 1 BiCGStab
+  int nvec = 5;     // inner-precision vectors per slot
   size_t eb = 16;
 };
 
@@ -315,7 +351,10 @@ static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_
   z.cap = int(maxp);
   z.ninst = int(probs.size());
   z.eb = inner_elem_bytes(precision);
-  z.B = choose_slots(requested_B, maxp, z.cap_blk, size_t(z.S), precision);
+  z.method = 0;
+  for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
+  z.nvec = z.method ? 8 : 5;
+  z.B = choose_slots(requested_B, maxp, z.cap_blk, size_t(z.S), precision, z.nvec);
   return z;
 }
 
@@ -325,16 +364,20 @@ static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
   size_t b = 0;
   b += al256(z.B * sizeof(Slot)) + al256(z.ninst * sizeof(Inst));
   b += al256(z.S * sizeof(SolveDev)) + al256(z.S * sizeof(SolveStat));
-  b += al256(sizeof(int)) + al256((z.B + 1) * sizeof(int)) + al256(4 * sizeof(int));
+  b += al256(sizeof(int)) + al256((z.B + 1) * sizeof(int)) + al256((z.B + 2) * sizeof(int)) + al256(4 * sizeof(int));
   b += al256(size_t(z.B) * z.cap_blk * kNDots * sizeof(double));
   b += al256(size_t(z.B) * z.cap * 16);
-  b += 5 * al256(size_t(z.B) * z.cap * z.eb);
+  b += size_t(z.nvec) * al256(size_t(z.B) * z.cap * z.eb);
   if (keep_solutions) b += al256(size_t(z.S) * z.cap * 16);
   b += al256(16 * sizeof(int));
   return b;
 }
 
-static size_t problem_bytes(const Problem& p) { return al256(2 * p.n() * 8) + al256(3 * p.n() * 8) + al256(64); }
+// D/Z, A, a small block, and a constant depth field when a constant-depth
+// problem runs through the flux-form path
+static size_t problem_bytes(const Problem& p) {
+  return al256(2 * p.n() * 8) + al256(3 * p.n() * 8) + al256((8 + 256) * 8) + al256(p.n() * 8);
+}
 
 struct Engine {
   hipStream_t st;
@@ -370,6 +413,7 @@ struct Engine {
     profile = prof;
     e.B = z.B;
     e.S = z.S;
+    e.method = z.method;
     e.cap = z.cap;
     e.cap_blk = z.cap_blk;
     e.max_iter = max_iter;
@@ -382,6 +426,7 @@ struct Engine {
     e.stats = ar.take<SolveStat>(z.S);
     e.next = ar.take<int>(1);
     e.tile_start = ar.take<int>(z.B + 1);
+    e.work = ar.take<int>(z.B + 2);
     e.counter = ar.take<int>(4);
     e.part = ar.take<double>(size_t(z.B) * z.cap_blk * kNDots);
     e.x64 = ar.take<double2>(size_t(z.B) * z.cap);
@@ -390,6 +435,11 @@ struct Engine {
     e.r1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
     e.p0 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
     e.p1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    if (z.method == 1) {
+      e.v0 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+      e.v1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+      e.rh = ar.take<char>(size_t(z.B) * z.cap * z.eb);
+    }
     e.yout = keep_solutions ? ar.take<double2>(size_t(z.S) * z.cap) : nullptr;
     e.dbg = ar.take<int>(16);
 
@@ -407,6 +457,8 @@ struct Engine {
       I.nblk = g.nblk;
       I.cx = 0.25 * double(pl.nx) * pl.nx;
       I.cy = 0.25 * double(pl.ny) * pl.ny;
+      I.cxy = 0.25 * double(pl.nx) * pl.ny;
+      I.H = probs[i]->H;
       I.eta0 = probs[i]->f;
       I.D0 = pl.has_vel ? probs[i]->DZ : nullptr;
       I.Z0 = pl.has_vel ? probs[i]->DZ + probs[i]->n() : nullptr;
@@ -435,6 +487,8 @@ struct Engine {
       D.c0 = to_d2(d.c0);
       D.c1 = to_d2(d.c1);
       D.c2 = to_d2(d.c2);
+      D.gamma = to_d2(d.gamma);
+      D.sc = to_d2(d.sc);
       D.tol2 = pl.pole_tol * pl.pole_tol;
       D.inst = q[j].inst;
       hs[j] = D;
@@ -447,6 +501,7 @@ struct Engine {
     launch_fill_zero(reinterpret_cast<double*>(e.slots), z.B * sizeof(Slot) / 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.next), 1, st);  // 8 bytes inside its 256-byte block
     launch_fill_zero(reinterpret_cast<double*>(e.tile_start), (size_t(z.B + 1) * 4 + 7) / 8, st);
+    launch_fill_zero(reinterpret_cast<double*>(e.work), (size_t(z.B + 2) * 4 + 7) / 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.counter), 2, st);
     launch_fill_zero(reinterpret_cast<double*>(e.dbg), 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.x64), size_t(z.B) * z.cap * 2, st);
@@ -455,7 +510,8 @@ struct Engine {
     int dev = 0, cus = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int occ = pass_occupancy(precision == REXII_PREC_MIXED ? 1 : 0);
+    const int occ = (z.method == 1) ? bcg_occupancy(precision == REXII_PREC_MIXED ? 1 : 0)
+                                    : pass_occupancy(precision == REXII_PREC_MIXED ? 1 : 0);
     // one work item (slot, tile) per block when every slot is live; never
     // fewer blocks than fill the chip
     const size_t items = size_t(z.B) * z.cap_blk;
@@ -468,13 +524,20 @@ struct Engine {
     launch_retire(e, st);
     launch_assign(e, st);
     launch_outer_update<T>(e, grid, st);
-    launch_outer_residual<T>(e, grid, st);
+    if (z.method == 1)
+      launch_outer_residual_vh<T>(e, grid, st);
+    else
+      launch_outer_residual<T>(e, grid, st);
     launch_outer_scalars(e, st);
     for (int i = 0; i < chunk; ++i) {
       if (with_events) HIPCHK(hipEventRecord(evs[2 * i], st));
-      launch_pass<T>(e, grid, st);
+      if (z.method == 1) {
+        launch_bcg<T>(e, grid, st);
+      } else {
+        launch_pass<T>(e, grid, st);
+      }
       if (with_events) HIPCHK(hipEventRecord(evs[2 * i + 1], st));
-      launch_pass_scalars(e, st);
+      if (z.method == 0) launch_pass_scalars(e, st);
     }
     launch_count_finished(e, st);
     HIPCHK(hipMemcpyAsync(hcount, e.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -495,8 +558,27 @@ struct Engine {
     HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
 
+  // Runs the chunks until the queue drains (or max_chunks > 0 chunks have
+  // run).  With max_chunks > 0 the time of chunks 2..max_chunks is returned
+  // (ms, HIP events on the engine's stream) and no statistics are read.
   template <typename T>
-  void run(int max_iter) {
+  double run(int max_iter, int max_chunks = 0) {
+    if (max_chunks > 0) {
+      build_graph<T>();
+      hipEvent_t a = nullptr, b = nullptr;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      HIPCHK(hipGraphLaunch(gexec, st));
+      HIPCHK(hipEventRecord(a, st));
+      for (int c = 1; c < max_chunks; ++c) HIPCHK(hipGraphLaunch(gexec, st));
+      HIPCHK(hipEventRecord(b, st));
+      HIPCHK(hipStreamSynchronize(st));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, b));
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      return double(ms);
+    }
     if (profile) {
       evs.resize(2 * chunk);
       for (hipEvent_t& ev : evs) HIPCHK(hipEventCreate(&ev));
@@ -536,8 +618,16 @@ struct Engine {
     pass_bytes = 0.0;
     for (int j = 0; j < z.S; ++j) {
       const double pts = double(inst_points[solve_inst[j]]);
-      pass_bytes += pts * double(z.eb) * (6.0 * stats[j].it_total + 3.0 * std::max(0, stats[j].rounds - 1));
+      if (z.method == 1) {
+        // BiCGStab iteration: A reads r, p, v, r_hat, writes p, v; B reads
+        // r, v; C reads x, r, v, p, r_hat, writes x, r (15 complex values)
+        // plus the depth field once per pass
+        pass_bytes += pts * stats[j].it_total * (15.0 * double(z.eb) + 3.0 * 0.5 * double(z.eb));
+      } else {
+        pass_bytes += pts * double(z.eb) * (6.0 * stats[j].it_total + 3.0 * std::max(0, stats[j].rounds - 1));
+      }
     }
+    return 0.0;
   }
 };
 
@@ -588,6 +678,7 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     const double eb = double(inner_elem_bytes(pl.precision));
     // one pass reads x, r, p and writes them back: 6 complex values per point
     rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * 6.0 * eb;
+    rep->slots = en->z.B;
     rep->kernel_launches = en->launches;
     rep->kernel_ms = en->kernel_ms;
     rep->kernel_bytes = en->pass_bytes;
@@ -605,6 +696,19 @@ static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>
     SolveDesc s;
     s.m1 = -zk / den;
     s.m2 = -t * fc / den;
+    if (pl.bicg) {
+      s.zeta = den / (t * t * g);
+      s.gamma = t * fc / zk;
+      s.sc = s.zeta / zk;
+      s.a1 = t * s.m1;
+      s.a2 = t * s.m2;
+      s.inv_sigma = 1.0;
+      s.c0 = s.c1 = s.c2 = 0.0;
+      s.cost = 0.0;
+      s.pole = int(k);
+      pl.solves.push_back(s);
+      continue;
+    }
     const cd sig = t * t * g * H * zk / den;
     s.zeta = den / (t * t * g * H);
     s.a1 = t * H * s.m1;
@@ -631,11 +735,37 @@ struct JobItem {
   double2* xout = nullptr;                // resolvent output
   rexii_report* rep = nullptr;
   bool skip = false;                      // t == 0: u = f
+  double hmax = 0.0;                      // max of the depth field (variable depth)
 };
+
+// max of a device depth field (and its validity), synchronous on `st`
+static double device_hmax(const double* H, size_t n, hipStream_t st) {
+  const int nb = prep_vh_blocks();
+  char* buf = nullptr;
+  HIPCHK(hipMalloc(reinterpret_cast<void**>(&buf), 256 + nb * sizeof(double)));
+  struct FreeDev {
+    char* p;
+    ~FreeDev() { (void)hipFree(p); }
+  } fd{buf};
+  int* dfl = reinterpret_cast<int*>(buf);
+  double* part = reinterpret_cast<double*>(buf + 256);
+  launch_fill_zero(reinterpret_cast<double*>(dfl), 1, st);
+  launch_hmax(H, n, dfl, part, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> hp(nb);
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&fl, dfl, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (fl & 8) throw HipError{REXII_ERR_NONFINITE, "depth field has a non-finite or non-positive value"};
+  double m = 0.0;
+  for (double v : hp) m = std::max(m, v);
+  return m;
+}
 
 // Sizing plans: unpaired with velocity, an upper bound of every variant.
 static rexii_status sizing_plan(const JobItem& it, const rexii_opts& o, Problem& pb) {
-  rexii_status st = build_plan(it.op, it.t, o, true, false, pb.pl, it.adjoint);
+  rexii_status st = build_plan(it.op, it.t, o, true, false, pb.pl, it.adjoint, it.hmax);
   if (st != REXII_OK) return st;
   if (it.shifts) shift_solves(it.op, it.t, *it.shifts, o.tol, pb.pl);
   return REXII_OK;
@@ -645,7 +775,7 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
                               size_t* bytes) {
   std::vector<Problem> pbs(items.size());
   std::vector<Problem*> ptrs;
-  size_t b = extra;
+  size_t b = extra + al256(std::max<size_t>(1, items.size()) * sizeof(int)) + 4096;
   for (size_t i = 0; i < items.size(); ++i) {
     if (items[i].skip) continue;
     rexii_status st = sizing_plan(items[i], o, pbs[i]);
@@ -672,8 +802,9 @@ struct Job {
   ~Job() { delete en; }
 };
 
-// Prepares every problem (input checks, div/curl, plans) and runs the engine.
-static void run_job(Job& jb, Arena& ar) {
+// Prepares every problem (input checks, div/curl, plans) and runs the engine
+// (only max_chunks chunks if > 0; returns their time in ms).
+static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
   const size_t ni = jb.items.size();
   jb.pbs.resize(ni);
   jb.engine_index.assign(ni, -1);
@@ -685,6 +816,12 @@ static void run_job(Job& jb, Arena& ar) {
   } fh{flags};
   int* dflags = ar.take<int>(std::max<size_t>(1, ni));
   launch_fill_zero(reinterpret_cast<double*>(dflags), (std::max<size_t>(1, ni) + 1) / 2, jb.st);
+  bool any_depth_field = false;
+  for (const JobItem& it : jb.items) any_depth_field = any_depth_field || (!it.skip && it.op->H_field);
+  // one engine runs one method: a depth field anywhere puts every problem
+  // of the call on the flux-form path
+  if (any_depth_field) jb.o.method = 1;
+  std::vector<double> hpart(size_t(prep_vh_blocks()));
   for (size_t i = 0; i < ni; ++i) {
     JobItem& it = jb.items[i];
     if (it.skip) continue;
@@ -693,9 +830,23 @@ static void run_job(Job& jb, Arena& ar) {
     pb.f = it.f;
     pb.DZ = ar.take<double>(2 * n);
     pb.A = ar.take<double>(3 * n);
-    (void)ar.take<char>(64);
+    double* hp = ar.take<double>(8 + prep_vh_blocks());
+    double* hconst = ar.take<double>(n);
     launch_fill_zero(pb.A, 3 * n, jb.st);
-    launch_prep(it.f, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, jb.st);
+    if (it.op->H_field) {
+      pb.H = it.op->H_field;
+      launch_prep_vh(it.f, it.op->H_field, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, hp, jb.st);
+    } else {
+      if (jb.o.method == 1) {
+        launch_fill_value(hconst, n, it.op->H0, jb.st);
+        pb.H = hconst;
+      }
+      launch_prep(it.f, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, jb.st);
+      if (jb.o.method == 1) {
+        // flux form: D_H = H0 div, Z_H = H0 curl
+        launch_scale1(pb.DZ, 2 * n, it.op->H0, jb.st);
+      }
+    }
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(flags, dflags, ni * sizeof(int), hipMemcpyDeviceToHost, jb.st));
@@ -704,6 +855,7 @@ static void run_job(Job& jb, Arena& ar) {
   for (size_t i = 0; i < ni; ++i) {
     if (jb.items[i].skip) continue;
     if (flags[i] & 1) throw HipError{REXII_ERR_NONFINITE, "non-finite value in an input state"};
+    if (flags[i] & 8) throw HipError{REXII_ERR_NONFINITE, "depth field has a non-finite or non-positive value"};
     if (flags[i] & 4) all_div_free = false;
   }
   for (size_t i = 0; i < ni; ++i) {
@@ -713,21 +865,136 @@ static void run_job(Job& jb, Arena& ar) {
     bool div_free = (flags[i] & 4) == 0;
     if (jb.pair_all) div_free = all_div_free;
     if (jb.force_unpaired || it.shifts) div_free = false;
-    rexii_status st = build_plan(it.op, it.t, jb.o, has_vel, div_free, jb.pbs[i].pl, it.adjoint);
+    rexii_status st = build_plan(it.op, it.t, jb.o, has_vel, div_free, jb.pbs[i].pl, it.adjoint, it.hmax);
     if (st != REXII_OK) throw HipError{st, g_err};
     if (it.shifts) shift_solves(it.op, it.t, *it.shifts, jb.o.tol, jb.pbs[i].pl);
     jb.engine_index[i] = int(jb.ptrs.size());
     jb.ptrs.push_back(&jb.pbs[i]);
   }
-  if (jb.ptrs.empty()) return;
+  if (jb.ptrs.empty()) return 0.0;
   const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision);
   jb.en = new Engine(jb.st);
   jb.en->setup(ar, jb.ptrs, z, jb.o.precision, jb.o.max_iter,
-               (jb.o.precision == REXII_PREC_MIXED) ? jb.o.inner_tol : 0.0, jb.o.profile != 0, jb.keep);
-  if (jb.o.precision == REXII_PREC_MIXED)
-    jb.en->run<float>(jb.o.max_iter);
-  else
-    jb.en->run<double>(jb.o.max_iter);
+               (jb.o.precision == REXII_PREC_MIXED) ? jb.o.inner_tol : 0.0,
+               jb.o.profile != 0 && max_chunks == 0, jb.keep);
+  if (jb.o.precision == REXII_PREC_MIXED) return jb.en->run<float>(jb.o.max_iter, max_chunks);
+  return jb.en->run<double>(jb.o.max_iter, max_chunks);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: slots per engine (opts.pole_batch < 0)
+// ---------------------------------------------------------------------------
+// For each candidate slot count the real problems run for a few HIP-graph
+// chunks (all slots busy: the queue is longer than the slot count); the
+// rate of (slot x point x pass) per second decides.  Results are cached in a
+// text file keyed by grid, precision, method and CU count:
+// $REXII_TUNE_CACHE, else $HOME/.cache/rexii_tune.txt, else /tmp/rexii_tune.txt.
+static std::string tune_cache_path() {
+  if (const char* p = std::getenv("REXII_TUNE_CACHE")) return p;
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/rexii_tune.txt";
+  return "/tmp/rexii_tune.txt";
+}
+
+static std::string tune_key(const std::vector<JobItem>& items, const rexii_opts& o, int cus) {
+  size_t maxp = 0;
+  int nx = 0, ny = 0;
+  bool depth = false;
+  for (const JobItem& it : items) {
+    if (it.skip) continue;
+    const size_t n = size_t(it.op->nx) * it.op->ny;
+    if (n > maxp) {
+      maxp = n;
+      nx = it.op->nx;
+      ny = it.op->ny;
+    }
+    depth = depth || it.op->H_field != nullptr;
+  }
+  const int method = (depth || o.method == 1) ? 1 : 0;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "nx=%d ny=%d prec=%d method=%d cus=%d", nx, ny, o.precision, method, cus);
+  return buf;
+}
+
+static int tune_lookup(const std::string& key) {
+  FILE* fp = std::fopen(tune_cache_path().c_str(), "r");
+  if (!fp) return 0;
+  char line[256];
+  int best = 0;
+  while (std::fgets(line, sizeof(line), fp)) {
+    std::string l(line);
+    const size_t bar = l.find(" | B=");
+    if (bar != std::string::npos && l.substr(0, bar) == key) best = std::atoi(l.c_str() + bar + 5);
+  }
+  std::fclose(fp);
+  return best;
+}
+
+static void tune_store(const std::string& key, int B, double rate) {
+  const std::string path = tune_cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    const std::string dir = path.substr(0, slash);
+    (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+  }
+  FILE* fp = std::fopen(path.c_str(), "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s | B=%d rate=%.4e\n", key.c_str(), B, rate);
+  std::fclose(fp);
+}
+
+static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o, hipStream_t st) {
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const std::string key = tune_key(items, o, cus);
+  const int cached = tune_lookup(key);
+  if (cached > 0) return cached;
+  size_t nsolves = 0, maxp = 0;
+  {
+    std::vector<JobItem> its = items;
+    for (JobItem& it : its) {
+      if (it.skip) continue;
+      Problem pb;
+      if (sizing_plan(it, o, pb) != REXII_OK) return 0;
+      nsolves += pb.pl.solves.size();
+      maxp = std::max(maxp, pb.n());
+    }
+  }
+  const int cands[] = {8, 16, 24, 32, 48, 64, 96, 128};
+  int best = 0;
+  double best_rate = 0.0;
+  for (int B : cands) {
+    if (size_t(B) * 2 > nsolves && B != cands[0]) break;  // keep the queue longer than the slots
+    Job jb;
+    jb.st = st;
+    jb.o = o;
+    jb.o.pole_batch = B;
+    jb.o.profile = 0;
+    jb.items = items;
+    for (JobItem& it : jb.items) {
+      it.u = nullptr;
+      it.rep = nullptr;
+    }
+    size_t need = 0;
+    if (job_bytes(jb.items, jb.o, false, 0, &need) != REXII_OK) break;
+    Arena ar(nullptr, 0);
+    try {
+      ar.reserve_own(need + 4096);
+    } catch (const HipError&) {
+      break;  // out of memory: larger counts will not fit either
+    }
+    const int chunks = 4;
+    const double ms = run_job(jb, ar, chunks);
+    if (!(ms > 0.0)) continue;
+    const int chunk = jb.en ? jb.en->chunk : 16;
+    const double rate = double(B) * double(maxp) * chunk * (chunks - 1) / (ms * 1e-3);
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = B;
+    }
+  }
+  if (best > 0) tune_store(key, best, best_rate);
+  return best;
 }
 
 // Reports and status of every item after the run.
@@ -753,12 +1020,13 @@ static rexii_status finish_job(Job& jb, double secs) {
   return clear_error();
 }
 
-static rexii_status check_op_and_t(const rexii_swe_op* op, double t, bool allow_zero) {
+static rexii_status check_op_and_t(const rexii_swe_op* op, double t, bool allow_zero, bool allow_depth_field = true) {
   rexii_status v = validate_op(op);
   if (v != REXII_OK) return v;
   if (!std::isfinite(t) || t < 0.0 || (!allow_zero && t == 0.0))
     return set_error(REXII_ERR_INVALID_ARG, allow_zero ? "t must be finite and >= 0" : "t must be > 0");
-  if (op->H_field) return set_error(REXII_ERR_INVALID_ARG, "variable depth is not supported by this entry point");
+  if (op->H_field && !allow_depth_field)
+    return set_error(REXII_ERR_INVALID_ARG, "variable depth is not supported by this entry point");
   return REXII_OK;
 }
 
@@ -812,8 +1080,21 @@ static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts
     }
     jb.keep = false;
     for (const JobItem& it : jb.items) jb.keep = jb.keep || (it.shifts != nullptr);
+    bool any_depth_field = false;
+    for (JobItem& it : jb.items) {
+      if (it.skip || !it.op->H_field) continue;
+      it.hmax = device_hmax(it.op->H_field, size_t(it.op->nx) * it.op->ny, st);
+      any_depth_field = true;
+    }
+    rexii_opts osz = jb.o;
+    if (any_depth_field) osz.method = 1;
+    if (jb.o.pole_batch < 0) {
+      const int B = autotune_slots(jb.items, osz, st);
+      jb.o.pole_batch = (B > 0) ? B : 0;
+      osz.pole_batch = jb.o.pole_batch;
+    }
     size_t need = 0;
-    rexii_status s0 = job_bytes(jb.items, jb.o, jb.keep, 0, &need);
+    rexii_status s0 = job_bytes(jb.items, osz, jb.keep, 0, &need);
     if (s0 != REXII_OK) return s0;
     Arena ar(ws, ws_bytes);
     if (!ws) {
@@ -860,6 +1141,7 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
     Job jb;
     jb.st = st;
     jb.o = resolve_opts(opts_in);
+    jb.o.method = 0;  // the dJ/dH dots use the constant-depth Helmholtz form
     jb.pair_all = true;
     const bool want_H = (dJdH != nullptr);
     jb.keep = want_H;
@@ -878,7 +1160,16 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
       jb.items.push_back(F);
     }
     size_t need = 0;
-    rexii_status s0 = job_bytes(jb.items, jb.o, jb.keep, al256(3 * n * 8) + 4096, &need);
+    size_t dots_bytes = 0;
+    {
+      // per-pole dot buffers of dJ/dH (one per pole in the unpaired case)
+      Problem pz;
+      rexii_status sp = build_plan(op, t, jb.o, true, false, pz.pl);
+      if (sp != REXII_OK) return sp;
+      const size_t nd = pz.pl.solves.size();
+      dots_bytes = al256(nd * sizeof(AdjDot)) + al256(nd * size_t(adj_dot_blocks(n)) * 16) + al256(nd * 16);
+    }
+    rexii_status s0 = job_bytes(jb.items, jb.o, jb.keep, al256(3 * n * 8) + dots_bytes + 4096, &need);
     if (s0 != REXII_OK) return s0;
     Arena ar(ws, ws_bytes);
     if (!ws) {
@@ -978,11 +1269,18 @@ void rexii_default_opts(rexii_opts* o) {
 const char* rexii_last_error(void) { return g_err.c_str(); }
 
 rexii_status rexii_rho(const rexii_swe_op* op, hipStream_t stream, double* rho) {
-  (void)stream;
   rexii_status st = validate_op(op);
   if (st != REXII_OK) return st;
   if (!rho) return set_error(REXII_ERR_INVALID_ARG, "rho is NULL");
-  if (op->H_field) return set_error(REXII_ERR_INVALID_ARG, "variable depth: not supported yet");
+  if (op->H_field) {
+    try {
+      const double hm = device_hmax(op->H_field, size_t(op->nx) * op->ny, stream);
+      *rho = rho_bound_var(op->nx, op->ny, op->g, hm, op->f_cor);
+    } catch (const HipError& he) {
+      return set_error(he.st, he.msg);
+    }
+    return clear_error();
+  }
   *rho = rho_const(op->nx, op->ny, op->g, op->H0, op->f_cor);
   return clear_error();
 }
@@ -996,6 +1294,23 @@ rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts
     return clear_error();
   }
   rexii_opts o = resolve_opts(opts);
+  if (op->H_field) {
+    // flux-form path: one problem, needs max H (read on the null stream)
+    JobItem it;
+    it.op = op;
+    it.t = t;
+    try {
+      it.hmax = device_hmax(op->H_field, size_t(op->nx) * op->ny, nullptr);
+    } catch (const HipError& he) {
+      return set_error(he.st, he.msg);
+    }
+    o.method = 1;
+    size_t b = 0;
+    st = job_bytes({it}, o, false, 0, &b);
+    if (st != REXII_OK) return st;
+    *bytes = b + 4096;
+    return clear_error();
+  }
   // the adjoint with dJ/dH is the largest user of one operator: two
   // problems, every solution kept, plus W^{-1} gbar and the dot buffers
   const size_t n = size_t(op->nx) * op->ny;
@@ -1056,7 +1371,7 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
 rexii_status rexii_apply_adjoint(const rexii_swe_op* op, const double* f, const double* gbar, double* dJdf,
                                  double* dJdH, double t, const rexii_opts* opts, void* workspace, size_t ws_bytes,
                                  hipStream_t stream, rexii_report* rep) {
-  rexii_status v = check_op_and_t(op, t, false);
+  rexii_status v = check_op_and_t(op, t, false, false);
   if (v != REXII_OK) return v;
   if (!gbar) return set_error(REXII_ERR_INVALID_ARG, "gbar is NULL");
   if (!dJdf && !dJdH) return set_error(REXII_ERR_INVALID_ARG, "nothing to compute (dJdf and dJdH are NULL)");

@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("m0", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("pole_batch", ctypes.c_int32), ("pair_conjugate", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("profile", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("method", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -50,7 +50,7 @@ class Report(ctypes.Structure):
                 ("rho", ctypes.c_double), ("kappa_sum", ctypes.c_double),
                 ("pole_tol", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double),
-                ("stagnated", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("stagnated", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
                 ("kernel_bytes", ctypes.c_double)]
 
@@ -107,7 +107,7 @@ def _check(st, report=None):
 
 
 def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=None,
-              pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None):
+              pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None, method=None):
     o = Opts()
     load().rexii_default_opts(ctypes.byref(o))
     if h is not None:
@@ -134,6 +134,8 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
         o.inner_tol = inner_tol
     if profile is not None:
         o.profile = int(profile)
+    if method is not None:
+        o.method = {"auto": 0, "cocg": 0, "bicgstab": 1}.get(method, method)
     return o
 
 

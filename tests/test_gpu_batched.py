@@ -53,3 +53,17 @@ def test_batched_with_t_zero_and_single(rx):
     assert em.rel_l2(us[1].cpu().numpy(), em.expm_closed_real(op1, f1, t1)) <= 1e-10
     us, reps = rx.apply_batched([_dev(f1)], [t1], fc=10.0)
     assert em.rel_l2(us[0].cpu().numpy(), em.expm_closed_real(op1, f1, t1)) <= 1e-10
+
+
+def test_autotuned_slots(rx, tmp_path, monkeypatch):
+    monkeypatch.setenv("REXII_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    op = lrsw.LRSW(128, 128, fc=10.0)
+    t = 200.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(128, nbumps=16, seed=9)
+    u1, r1 = rx.apply(_dev(f), t, fc=10.0, pole_batch=-1)
+    text = (tmp_path / "tune.txt").read_text()
+    assert "nx=128 ny=128" in text and f"B={r1['slots']}" in text
+    u2, r2 = rx.apply(_dev(f), t, fc=10.0, pole_batch=-1)   # from the cache
+    assert r2["slots"] == r1["slots"]
+    assert bool((u1 == u2).all())
+    assert em.rel_l2(u1.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10

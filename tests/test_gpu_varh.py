@@ -1,0 +1,95 @@
+"""Variable depth (flux form) through BiCGStab: parity with dense matrix
+exponentials on small grids and the Chebyshev-Bessel reference on larger
+ones; BiCGStab on constant depth against the exact exponential."""
+import numpy as np
+import pytest
+
+from oracle import expm_modes as em
+from oracle import lrsw, varh
+from paper_2008_11607_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2008_11607_amd import rexii
+    rexii.load()
+    return rexii
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("nx,ny,velocity", [(16, 16, False), (24, 20, True)])
+def test_varh_vs_dense_expm(rx, nx, ny, velocity):
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, g=1.0, fc=10.0, Hfield=Hf)
+    t = 30.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=5, velocity=velocity)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, Hfield=_dev(Hf))
+    assert rep["not_converged"] == 0
+    assert abs(rep["rho"] - lrsw.rho(op)) <= 1e-12 * lrsw.rho(op)
+    assert em.rel_l2(u.cpu().numpy(), em.expm_dense(op, f, t)) <= 1e-10
+
+
+def test_varh_vs_chebyshev_64(rx):
+    D = 64
+    Hf = inputs.variable_depth(D)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = 100.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(D, nbumps=16, seed=50)
+    u, rep = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf))
+    ref = varh.chebyshev_expm(op, f, t)
+    assert em.rel_l2(u.cpu().numpy(), ref) <= 1e-10
+    # W-energy (g |eta|^2 + H |v|^2) is conserved by exp(tA)
+    assert abs(varh.w_energy(op, u.cpu().numpy()) / varh.w_energy(op, f) - 1.0) <= 1e-10
+
+
+def test_varh_mixed_vs_fp64(rx):
+    D = 96
+    Hf = inputs.variable_depth(D)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = 150.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(D, nbumps=16, seed=51)
+    u64, _ = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf))
+    u32, rep = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf), precision="mixed")
+    assert rep["not_converged"] == 0
+    assert em.rel_l2(u32.cpu().numpy(), u64.cpu().numpy()) <= 1e-6
+
+
+def test_bicgstab_on_constant_depth(rx):
+    op = lrsw.LRSW(64, 48, g=1.3, H=0.8, fc=7.0)
+    t = 80.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(64, 48, nbumps=4, seed=6, velocity=True)
+    u, rep = rx.apply(_dev(f), t, g=1.3, fc=7.0, H=0.8, method="bicgstab")
+    assert rep["solves"] == rep["P"]
+    assert em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
+def test_varh_shifted_solves(rx):
+    nx, ny = 16, 12
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, fc=5.0, Hfield=Hf)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=2, seed=8, velocity=True)
+    z = np.array([0.5 * (-5.1333 - 4j), -0.5 * (-5.1333 + 9j)])
+    x, _ = rx.shifted_solve(_dev(f), 0.9, z, fc=5.0, Hfield=_dev(Hf), tol=1e-12)
+    for k in range(len(z)):
+        ref = varh.resolvent_dense(op, f, 0.9, z[k])
+        assert np.linalg.norm(x[k].cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_varh_rho_and_bad_depth(rx):
+    Hf = inputs.variable_depth(32)
+    r = rx.rho(32, 32, fc=20.0, Hfield=_dev(Hf))
+    assert abs(r - lrsw.rho(lrsw.LRSW(32, 32, fc=20.0, Hfield=Hf))) <= 1e-12 * r
+    bad = Hf.copy()
+    bad[3, 4] = -1.0
+    f = inputs.gaussian_bumps(32, nbumps=1, seed=1)
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(_dev(f), 0.1, fc=20.0, Hfield=_dev(bad))
+    assert e.value.status == -2

@@ -620,9 +620,9 @@ struct Engine {
       const double pts = double(inst_points[solve_inst[j]]);
       if (z.method == 1) {
         // BiCGStab iteration: A reads r, p, v, r_hat, writes p, v; B reads
-        // r, v; C reads x, r, v, p, r_hat, writes x, r (15 complex values)
-        // plus the depth field once per pass
-        pass_bytes += pts * stats[j].it_total * (15.0 * double(z.eb) + 3.0 * 0.5 * double(z.eb));
+        // r, v; C reads d, r, v, p, r_hat, writes d, r (15 complex values)
+        // plus the FP64 depth field once per pass
+        pass_bytes += pts * stats[j].it_total * (15.0 * double(z.eb) + 3.0 * 8.0);
       } else {
         pass_bytes += pts * double(z.eb) * (6.0 * stats[j].it_total + 3.0 * std::max(0, stats[j].rounds - 1));
       }

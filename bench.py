@@ -65,6 +65,19 @@ def cpu_baseline(f, t, budget_s=12.0):
                       f"{el:.1f} s"}
 
 
+def copy_calibration(nbytes=1 << 30, reps=8):
+    """A copy of known size (nbytes read + nbytes written per launch): the
+    per-dispatch FETCH_SIZE / WRITE_SIZE it reports scale the counters of
+    the solver kernels to bytes."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +87,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--slots", type=int, default=-1,
                     help="concurrent solves; -1 (default) autotunes on the first call and caches the choice")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 8 times (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the pole-sharded multi-GPU "
               "form is a design, not part of this build.", file=sys.stderr)

@@ -95,6 +95,28 @@ __device__ __forceinline__ P* ldc_ptr(P* const* p) {
                                                  __HIP_MEMORY_SCOPE_AGENT);
   return reinterpret_cast<P*>(v);
 }
+// Coherent load of a value at a block-uniform address, returned in scalar
+// registers (the atomic load itself is a vector load).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double2 uni(double2 v) { return make_double2(uni(v.x), uni(v.y)); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* v) {
+  const unsigned long long b = reinterpret_cast<unsigned long long>(v);
+  const unsigned int lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(b & 0xffffffffull));
+  const unsigned int hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(b >> 32));
+  return reinterpret_cast<P*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+template <typename X>
+__device__ __forceinline__ X ldu(const X* p) { return uni(ldc(p)); }
+template <typename P>
+__device__ __forceinline__ P* ldu_ptr(P* const* p) { return uni(ldc_ptr(p)); }
+
 // Problem and solve tables are uploaded once per call into reused workspace
 // addresses: read them the same way.
 __device__ __forceinline__ Inst ld_inst(const Inst* p) {
@@ -125,6 +147,10 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 // Either form, chosen once per tile (block-uniform): the single-step form
 // is exact when the tile with its halo is no larger than the grid.
 __device__ __forceinline__ int wrapc(int i, int n, bool big) { return big ? wrap1(i, n) : wrap(i, n); }
+// The same with the choice fixed at compile time (pass kernels are
+// instantiated for both and pick one per work item).
+template <bool BIG>
+__device__ __forceinline__ int wrp(int i, int n) { return BIG ? wrap1(i, n) : wrap(i, n); }
 
 // ---------------------------------------------------------------------------
 // deterministic reductions (256 threads = 4 wavefronts of 64)
@@ -150,6 +176,63 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh, double (
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < N; ++k) out[k] = (sh[k] + sh[N + k]) + (sh[2 * N + k] + sh[3 * N + k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile staging.  fetch() issues all of a thread's global loads of a tile
+// (element k of the TH x TW tile comes from f(k / TW, k % TW)) before any
+// of them is used, so the tile costs one memory round trip; store() then
+// writes the registers to LDS (after the caller's barrier).
+// ---------------------------------------------------------------------------
+template <typename V, int TH, int TW>
+struct TileRegs {
+  static constexpr int kN = TH * TW;
+  static constexpr int kPer = (kN + kNT - 1) / kNT;
+  V v[kPer];
+  template <typename F>
+  __device__ __forceinline__ void fetch(F f) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int k = threadIdx.x + m * kNT;
+      if (k < kN) {
+        const int ly = k / TW;
+        v[m] = f(ly, k - ly * TW);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(V* lds) const {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int k = threadIdx.x + m * kNT;
+      if (k < kN) lds[k] = v[m];
+    }
+  }
+};
+
+// The same staging straight into LDS in PARTS rounds of loads (fewer live
+// registers, one memory round trip per round); call between barriers.
+template <typename V, int TH, int TW, int PARTS, typename F>
+__device__ __forceinline__ void stage_tile(V* lds, F f) {
+  constexpr int kN = TH * TW;
+  constexpr int kPer = (kN + kNT - 1) / kNT;
+  constexpr int kStep = (kPer + PARTS - 1) / PARTS;
+#pragma unroll
+  for (int m0 = 0; m0 < kPer; m0 += kStep) {
+    V v[kStep];
+#pragma unroll
+    for (int m = 0; m < kStep; ++m) {
+      const int k = threadIdx.x + (m0 + m) * kNT;
+      if (m0 + m < kPer && k < kN) {
+        const int ly = k / TW;
+        v[m] = f(ly, k - ly * TW);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kStep; ++m) {
+      const int k = threadIdx.x + (m0 + m) * kNT;
+      if (m0 + m < kPer && k < kN) lds[k] = v[m];
+    }
   }
 }
 
@@ -181,7 +264,7 @@ __device__ __forceinline__ Item item_of(const Eng& e, int pos, int uniform_nblk)
   if (uniform_nblk > 0) {
     const int k = pos / uniform_nblk;
     Item it;
-    it.slot = ldc(&e.work[2 + k]);
+    it.slot = ldu(&e.work[2 + k]);
     it.tile = pos - k * uniform_nblk;
     return it;
   }

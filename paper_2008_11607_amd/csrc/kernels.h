@@ -49,6 +49,7 @@ enum SlotStatus : int {
   kDone = 4,          // converged (waiting to be accumulated)
   kFailMaxIter = 5,   // stopped at max_iter (x64 holds the best iterate)
   kFailBreakdown = 6, // non-finite scalars
+  kInnerLast = 7,     // BiCGStab: stop test fired, last update of d pending
 };
 
 // One problem (an initial state on a grid) of the launch.
@@ -90,6 +91,13 @@ struct Slot {
   double prev_rn2;   // residual of the previous FP64 round
   double in_tol2;    // inner stop: recursive ||r||^2 <= in_tol2
   double tol2;       // final relative tolerance^2 of this solve
+  double cx, cy, cxy;  // stencil coefficients of the solve's problem
+  const double* H;     // its depth field (BiCGStab path) or nullptr
+  const double* eta0;  // its right-hand side fields (see Inst)
+  const double* D0;
+  const double* Z0;
+  int nx, ny, tiles_x, nblk;  // its grid (copied at assignment so a pass
+                              // reads every control field in one round)
   int status;
   int parity;        // which r/p buffers hold the current iterate
   int prime;         // 1: next pass only forms p = r and its dots
@@ -111,6 +119,7 @@ struct Eng {
   double inner_eta2;     // relative reduction^2 of one inner solve
   int max_iter;
   int method;            // 0: COCG on the constant-depth Helmholtz; 1: BiCGStab (flux form)
+  int d_is_f32;          // inner precision of d, r, p (1: FP32, 0: FP64)
   Slot* slots;           // [B]
   const Inst* inst;      // [ninst]
   const SolveDev* solves;// [S]
@@ -156,9 +165,7 @@ void launch_pass(const Eng& e, int grid, hipStream_t s);
 //   a1 = t m1, a2 = t m2, D_H = div(H (u0, v0)), Z_H = dx(H v0) - dy(H u0),
 // solved by BiCGStab (K is not complex-symmetric: C_H is antisymmetric).
 template <typename T>
-void launch_bcg(const Eng& e, int grid, hipStream_t s);   // passes A, B, C with their scalar kernels
-template <typename T>
-void launch_outer_residual_vh(const Eng& e, int grid, hipStream_t s);
+void launch_bcg(const Eng& e, int grid, hipStream_t s);   // passes U and S with their scalar kernels
 void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
                     double* hmax_part, hipStream_t s);
 int prep_vh_blocks();
@@ -166,12 +173,7 @@ void launch_hmax(const double* H, size_t n, int* flags, double* part, hipStream_
 void launch_fill_value(double* p, size_t n, double v, hipStream_t s);
 int bcg_occupancy(int mixed);
 
-template <typename T>
-void launch_outer_update(const Eng& e, int grid, hipStream_t s);
-template <typename T>
-void launch_outer_residual(const Eng& e, int grid, hipStream_t s);
 void launch_pass_scalars(const Eng& e, hipStream_t s);
-void launch_outer_scalars(const Eng& e, hipStream_t s);
 void launch_retire(const Eng& e, hipStream_t s);
 void launch_assign(const Eng& e, hipStream_t s);
 void launch_count_finished(const Eng& e, hipStream_t s);

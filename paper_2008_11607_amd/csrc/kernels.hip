@@ -32,18 +32,33 @@ __device__ __forceinline__ V helm(const V* t, int y, int x, S cx, S cy, V zeta) 
 }
 
 // ---------------------------------------------------------------------------
-// The COCG pass.  Input (x_i = d, r_i, p_i) with alpha_i, beta_i known:
+// The COCG pass.  Each launch advances every live slot by one step; what the
+// step is depends on the slot's state.
+//
+// Inner step (status kInner), input (x_i = d, r_i, p_i) with alpha_i, beta_i:
 //   q_i = (L - zeta) p_i                      (tile + halo 2, from p with halo 4)
 //   d  += alpha_i p_i,  r_{i+1} = r_i - alpha_i q_i,  p_{i+1} = r_{i+1} + beta_i p_i
 //   q_{i+1} = (L - zeta) p_{i+1}              (tile)
 //   partial sums: p_{i+1}^T q_{i+1}, q_{i+1}^T r_{i+1}, q_{i+1}^T q_{i+1},
 //                 r_{i+1}^T r_{i+1}, |r_{i+1}|^2
-// The last block of the slot then sets alpha_{i+1} = rr_{i+1} / pq_{i+1} and
+// k_pass_scalars then sets alpha_{i+1} = rr_{i+1} / pq_{i+1} and
 // beta_{i+1} = (rr_{i+1} - 2 alpha qr + alpha^2 qq) / rr_{i+1}.
-// A "prime" pass (after an FP64 residual) only sets p = r and its sums.
+//
+// Outer step (status kOuterPending or kInnerDone): the FP64 residual round
+// of iterative refinement, folded into the same launch.  With the current
+// iterate x = x64 + d (x = 0 for a fresh solve)
+//   r64 = b - (L - zeta) x   in FP64 on tile + halo 2  (x with halo 4),
+//   r = p = (T) r64,  q = (L - zeta) p  (tile),
+// partial sums of the restarted COCG (as above) and |r64|^2 instead of
+// |r|^2; k_pass_scalars decides convergence and, if the solve goes on, sets
+// alpha and beta of the first inner step.  x64 and d are only read here
+// (other blocks read them as halo); the first inner step of the round then
+// folds d into x64 (x64 += d, point by point) and restarts d = alpha p.  The
+// solution of a finished solve is therefore x64 + d once it has run at least
+// one inner round.
 // ---------------------------------------------------------------------------
-constexpr int kPW = kTX + 8, kPH = kTY + 8;   // p tile with halo 4
-constexpr int kNW = kTX + 4, kNH = kTY + 4;   // p_{i+1} tile with halo 2
+constexpr int kPW = kTX + 8, kPH = kTY + 8;   // tile with halo 4
+constexpr int kNW = kTX + 4, kNH = kTY + 4;   // tile with halo 2
 constexpr int kRing = kNW * kNH - kTX * kTY;  // halo-2 ring points
 
 __device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
@@ -63,142 +78,240 @@ __device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_pass(Eng e) {
-  using V = typename C2<T>::t;
-  __shared__ V PT[kPH * kPW];
-  __shared__ V PN[kNH * kNW];
-  __shared__ double red[4 * kNDots];
+// Control fields of a slot, read in one round of coherent loads.
+struct SlotCtl {
+  int status, par, rounds, it_inner, nx, ny, tiles_x;
+  double cx, cy;
+  double2 alpha, beta, zeta;
+};
 
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
+__device__ __forceinline__ SlotCtl load_ctl(const Slot* S) {
+  SlotCtl c;
+  c.status = ldu(&S->status);
+  c.par = ldu(&S->parity);
+  c.rounds = ldu(&S->rounds);
+  c.it_inner = ldu(&S->it_inner);
+  c.nx = ldu(&S->nx);
+  c.ny = ldu(&S->ny);
+  c.tiles_x = ldu(&S->tiles_x);
+  c.cx = ldu(&S->cx);
+  c.cy = ldu(&S->cy);
+  c.alpha = ldu(&S->alpha);
+  c.beta = ldu(&S->beta);
+  c.zeta = ldu(&S->zeta);
+  return c;
+}
+
+// LDS of the pass: a T tile with halo 2 (p_{i+1}, or r of the outer step),
+// then either a T tile of p with halo 4 (inner) or an FP64 tile of x with
+// halo 4 (outer).
+template <typename T>
+struct PassLds {
+  using V = typename C2<T>::t;
+  static constexpr size_t kN = sizeof(V) * kNH * kNW;
+  static constexpr size_t kInner = kN + sizeof(V) * kPH * kPW;
+  static constexpr size_t kOuter = kN + sizeof(double2) * kPH * kPW;
+  static constexpr size_t kBytes = kInner > kOuter ? kInner : kOuter;
+};
+
+// the nine partial sums of one tile, accumulated in FP64
+template <typename V>
+__device__ __forceinline__ void cocg_dots(double (&s)[kNDots], V p, V r, V q) {
+  const double px = p.x, py = p.y, rx = r.x, ry = r.y, qx = q.x, qy = q.y;
+  s[0] += px * qx - py * qy;
+  s[1] += px * qy + py * qx;
+  s[2] += qx * rx - qy * ry;
+  s[3] += qx * ry + qy * rx;
+  s[4] += qx * qx - qy * qy;
+  s[5] += 2.0 * qx * qy;
+  s[6] += rx * rx - ry * ry;
+  s[7] += 2.0 * rx * ry;
+}
+
+template <typename T>
+__device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+                                           double (&s)[kNDots]) {
+  using V = typename C2<T>::t;
+  V* PN = reinterpret_cast<V*>(lds);
+  V* PT = reinterpret_cast<V*>(lds + PassLds<T>::kN);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
+  const V* ps = reinterpret_cast<const V*>(c.par ? e.p1 : e.p0) + base;
+  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  V* d = reinterpret_cast<V*>(e.d) + base;
+  double2* x64 = e.x64 + base;
+  const bool first = c.it_inner == 0;        // d restarts this step
+  const bool fold = first && c.rounds >= 2;  // ... after x64 += d
+  const V alpha = mk<V>(c.alpha.x, c.alpha.y);
+  const V beta = mk<V>(c.beta.x, c.beta.y);
+  const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kPW) && (ny >= kPH);
+
+  // every global load of the step is issued before the first wait:
+  // r and d (interior), r (halo-2 ring) and p (halo 4) into registers
+  size_t gi[kTY / 4];
+  V rv[kTY / 4], dv[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    gi[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
+    rv[j] = rs[gi[j]];
+    if (!first) dv[j] = nt_load(&d[gi[j]]);
+  }
+  constexpr int kRingPerThread = (kRing + kNT - 1) / kNT;
+  V rr_[kRingPerThread];
+  int rly[kRingPerThread], rlx[kRingPerThread];
+#pragma unroll
+  for (int m = 0; m < kRingPerThread; ++m) {
+    const int k = threadIdx.x + m * kNT;
+    rly[m] = -1;
+    if (k < kRing) {
+      ring_pos(k, rly[m], rlx[m]);
+      rr_[m] = rs[size_t(wrapc(y0 - 2 + rly[m], ny, big)) * nx + wrapc(x0 - 2 + rlx[m], nx, big)];
+    }
+  }
+  TileRegs<V, kPH, kPW> pt;
+  pt.fetch([&](int ly, int lx) { return ps[size_t(wrapc(y0 - 4 + ly, ny, big)) * nx + wrapc(x0 - 4 + lx, nx, big)]; });
+  __syncthreads();  // LDS of the previous work item is free
+  pt.store(PT);
+  __syncthreads();
+  // interior: rows ty + 4j, column tx
+  V rn[kTY / 4], pn[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    const bool in = (x0 + tx < nx) && (y0 + ly < ny);
+    const V pc = PT[(ly + 4) * kPW + tx + 4];
+    const V q = helm<V, T, kPW>(PT, ly + 4, tx + 4, cx, cy, zeta);
+    const V r1 = csub(rv[j], cmul(alpha, q));
+    const V p1 = cadd(r1, cmul(beta, pc));
+    if (in) {
+      if (fold) {
+        // once per round: the previous round's correction moves into x64
+        const V dold = d[gi[j]];
+        const double2 xo = x64[gi[j]];
+        x64[gi[j]] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
+      }
+      nt_store(first ? cmul(alpha, pc) : cadd(dv[j], cmul(alpha, pc)), &d[gi[j]]);
+      rd[gi[j]] = r1;
+      pd[gi[j]] = p1;
+    }
+    PN[(ly + 2) * kNW + tx + 2] = p1;
+    rn[j] = r1;
+    pn[j] = p1;
+  }
+  // halo ring of p_{i+1}
+#pragma unroll
+  for (int m = 0; m < kRingPerThread; ++m) {
+    if (rly[m] < 0) continue;
+    const int ly = rly[m], lx = rlx[m];
+    const V pc = PT[(ly + 2) * kPW + lx + 2];
+    const V q = helm<V, T, kPW>(PT, ly + 2, lx + 2, cx, cy, zeta);
+    PN[ly * kNW + lx] = cadd(csub(rr_[m], cmul(alpha, q)), cmul(beta, pc));
+  }
+  __syncthreads();
+  // dot products accumulated in FP64 (the beta recurrence cancels)
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V qv = helm<V, T, kNW>(PN, ly + 2, tx + 2, cx, cy, zeta);
+      cocg_dots(s, pn[j], rn[j], qv);
+      s[8] += double(rn[j].x) * rn[j].x + double(rn[j].y) * rn[j].y;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cocg_outer(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+                                           double (&s)[kNDots]) {
+  using V = typename C2<T>::t;
+  V* RN = reinterpret_cast<V*>(lds);
+  double2* XT = reinterpret_cast<double2*>(lds + PassLds<T>::kN);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const double2* x64 = e.x64 + base;
+  const V* d = reinterpret_cast<const V*>(e.d) + base;
+  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
+  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
+  // right-hand side b = eta0 + a1 D0 + a2 Z0 (outer steps only)
+  const Slot* S = &e.slots[slot];
+  const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2);
+  const double* eta0 = ldu_ptr(&S->eta0);
+  const double* D0 = ldu_ptr(&S->D0);
+  const double* Z0 = ldu_ptr(&S->Z0);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kPW) && (ny >= kPH);
+
+  __syncthreads();  // LDS of the previous work item is free
+  if (!zero_x) stage_tile<double2, kPH, kPW, 2>(XT, [&](int ly, int lx) {
+    const size_t g = size_t(wrapc(y0 - 4 + ly, ny, big)) * nx + wrapc(x0 - 4 + lx, nx, big);
+    const V dv = d[g];
+    const double2 xv = x64[g];
+    return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
+  });
+  __syncthreads();
+  // r64 = b - (L - zeta) x on tile + halo 2; r = p = (T) r64
+  for (int k = threadIdx.x; k < kNH * kNW; k += kNT) {
+    const int ly = k / kNW, lx = k - ly * kNW;
+    const int gy = y0 - 2 + ly, gx = x0 - 2 + lx;
+    const size_t g = size_t(wrapc(gy, ny, big)) * nx + wrapc(gx, nx, big);
+    double2 rv = make_double2(eta0[g], 0.0);
+    if (D0) {
+      const double dv = D0[g], zv = Z0[g];
+      rv.x += a1.x * dv + a2.x * zv;
+      rv.y += a1.y * dv + a2.y * zv;
+    }
+    if (!zero_x) rv = csub(rv, helm<double2, double, kPW>(XT, ly + 2, lx + 2, c.cx, c.cy, c.zeta));
+    const V rt = mk<V>(rv.x, rv.y);
+    RN[k] = rt;
+    const bool interior = ly >= 2 && ly < kTY + 2 && lx >= 2 && lx < kTX + 2 && gx < nx && gy < ny;
+    if (interior) {
+      rd[g] = rt;
+      pd[g] = rt;
+      s[8] += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+  __syncthreads();
+  const T cx = T(c.cx), cy = T(c.cy);
+  const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V rt = RN[(ly + 2) * kNW + tx + 2];
+      cocg_dots(s, rt, rt, helm<V, T, kNW>(RN, ly + 2, tx + 2, cx, cy, zeta));
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cocg_pass(const Eng& e) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[PassLds<T>::kBytes];
+  __shared__ double red[4 * kNDots];
+  const int total = ldu(&e.tile_start[e.B]);
+  const int un = ldu(&e.work[1]);
+  const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
     const Item it = item_of(e, pos, un);
-    Slot* S = &e.slots[it.slot];
-#ifdef REXII_DEBUG_CHECKS
-    {
-      const int tot_fresh = __hip_atomic_load(&e.tile_start[e.B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (threadIdx.x == 0 && tot_fresh != total) atomicAdd(&e.dbg[4], 1);
-      if (threadIdx.x == 0 && it.tile >= e.inst[S->inst].nblk) atomicAdd(&e.dbg[5], 1);
-    }
-    if (it.tile >= e.inst[S->inst].nblk) continue;
-    {
-      __shared__ int seen[4];
-      __syncthreads();
-      if (threadIdx.x == 0) { seen[0] = S->status; seen[1] = S->parity; seen[2] = S->prime; }
-      __syncthreads();
-      if (S->status != seen[0] || S->parity != seen[1] || S->prime != seen[2]) atomicAdd(&e.dbg[0], 1);
-      __syncthreads();
-    }
-#endif
-    if (ldc(&S->status) != kInner) continue;
-    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
-    const size_t base = size_t(it.slot) * e.cap;
-    const int par = ldc(&S->parity);
-    const V* rs = reinterpret_cast<const V*>(par ? e.r1 : e.r0) + base;
-    V* rd = reinterpret_cast<V*>(par ? e.r0 : e.r1) + base;
-    const V* ps = reinterpret_cast<const V*>(par ? e.p1 : e.p0) + base;
-    V* pd = reinterpret_cast<V*>(par ? e.p0 : e.p1) + base;
-    V* d = reinterpret_cast<V*>(e.d) + base;
-    const bool prime = ldc(&S->prime) != 0;
-    const double2 al2 = ldc(&S->alpha), be2 = ldc(&S->beta), ze2 = ldc(&S->zeta);
-    const V alpha = mk<V>(al2.x, al2.y);
-    const V beta = mk<V>(be2.x, be2.y);
-    const V zeta = mk<V>(ze2.x, ze2.y);
-    const T cx = T(I.cx), cy = T(I.cy);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= kPW) && (I.ny >= kPH);
-
-    // issue the interior and ring loads of r and d before the p tile
-    // barrier so their latency overlaps the tile load
-    size_t gi[kTY / 4];
-    V rv[kTY / 4], dv[kTY / 4];
-#pragma unroll
-    for (int j = 0; j < kTY / 4; ++j) {
-      gi[j] = size_t(wrapc(y0 + ty + 4 * j, I.ny, big)) * I.nx + wrapc(x0 + tx, I.nx, big);
-      rv[j] = rs[gi[j]];
-      if (!prime) dv[j] = nt_load(&d[gi[j]]);
-    }
-    constexpr int kRingPerThread = (kRing + kNT - 1) / kNT;
-    V rr_[kRingPerThread];
-    int rly[kRingPerThread], rlx[kRingPerThread];
-#pragma unroll
-    for (int m = 0; m < kRingPerThread; ++m) {
-      const int k = threadIdx.x + m * kNT;
-      rly[m] = -1;
-      if (k < kRing) {
-        ring_pos(k, rly[m], rlx[m]);
-        rr_[m] = rs[size_t(wrapc(y0 - 2 + rly[m], I.ny, big)) * I.nx + wrapc(x0 - 2 + rlx[m], I.nx, big)];
-      }
-    }
-    __syncthreads();  // LDS of the previous work item is free
-    if (!prime) {
-      for (int k = threadIdx.x; k < kPH * kPW; k += kNT) {
-        const int ly = k / kPW, lx = k - ly * kPW;
-        PT[k] = ps[size_t(wrapc(y0 - 4 + ly, I.ny, big)) * I.nx + wrapc(x0 - 4 + lx, I.nx, big)];
-      }
-    }
-    __syncthreads();
-    // interior: rows ty + 4j, column tx
-    V rn[kTY / 4], pn[kTY / 4];
-#pragma unroll
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      const bool in = (x0 + tx < I.nx) && (y0 + ly < I.ny);
-      V r1 = rv[j], p1 = rv[j];
-      if (!prime) {
-        const V pc = PT[(ly + 4) * kPW + tx + 4];
-        const V q = helm<V, T, kPW>(PT, ly + 4, tx + 4, cx, cy, zeta);
-        r1 = csub(rv[j], cmul(alpha, q));
-        p1 = cadd(r1, cmul(beta, pc));
-        if (in) nt_store(cadd(dv[j], cmul(alpha, pc)), &d[gi[j]]);
-      }
-      PN[(ly + 2) * kNW + tx + 2] = p1;
-      if (in) {
-        rd[gi[j]] = r1;
-        pd[gi[j]] = p1;
-      }
-      rn[j] = r1;
-      pn[j] = p1;
-    }
-    // halo ring of p_{i+1}
-#pragma unroll
-    for (int m = 0; m < kRingPerThread; ++m) {
-      if (rly[m] < 0) continue;
-      const int ly = rly[m], lx = rlx[m];
-      V p1 = rr_[m];
-      if (!prime) {
-        const V pc = PT[(ly + 2) * kPW + lx + 2];
-        const V q = helm<V, T, kPW>(PT, ly + 2, lx + 2, cx, cy, zeta);
-        p1 = cadd(csub(rr_[m], cmul(alpha, q)), cmul(beta, pc));
-      }
-      PN[ly * kNW + lx] = p1;
-    }
-    __syncthreads();
+    const SlotCtl c = load_ctl(&e.slots[it.slot]);
     double s[kNDots];
 #pragma unroll
     for (int k = 0; k < kNDots; ++k) s[k] = 0.0;
-    // dot products accumulated in FP64 (the beta recurrence cancels)
-#pragma unroll
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      if (x0 + tx < I.nx && y0 + ly < I.ny) {
-        const V qv = helm<V, T, kNW>(PN, ly + 2, tx + 2, cx, cy, zeta);
-        const double px = pn[j].x, py = pn[j].y, rx = rn[j].x, ry = rn[j].y, qx = qv.x, qy = qv.y;
-        s[0] += px * qx - py * qy;
-        s[1] += px * qy + py * qx;
-        s[2] += qx * rx - qy * ry;
-        s[3] += qx * ry + qy * rx;
-        s[4] += qx * qx - qy * qy;
-        s[5] += 2.0 * qx * qy;
-        s[6] += rx * rx - ry * ry;
-        s[7] += 2.0 * rx * ry;
-        s[8] += rx * rx + ry * ry;
-      }
+    if (c.status == kInner) {
+      cocg_inner<T>(e, c, it.slot, it.tile, lds, s);
+    } else if (c.status == kOuterPending || c.status == kInnerDone) {
+      cocg_outer<T>(e, c, it.slot, it.tile, lds, s);
+    } else {
+      continue;
     }
     double tot[kNDots];
     block_sum_n<kNDots>(s, red, tot);
@@ -210,14 +323,23 @@ __global__ __launch_bounds__(kNT) void k_pass(Eng e) {
   }
 }
 
+// FP32 inner precision at 4 waves per SIMD (<= 128 VGPRs); FP64 as compiled
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_pass_f32(Eng e) {
+  cocg_pass<float>(e);
+}
+__global__ __launch_bounds__(kNT) void k_pass_f64(Eng e) { cocg_pass<double>(e); }
+
 // One block per slot after each pass: add the partial sums of the slot's
-// tiles in index order and set alpha_{i+1}, beta_{i+1} (or end the inner
-// solve).
+// tiles in index order.  Inner step: set alpha_{i+1}, beta_{i+1} or end the
+// inner solve.  Outer step: decide done / stagnated / failed, or restart the
+// inner solve with the residual as its right-hand side.
 __global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
   __shared__ double red[4 * kNDots];
   Slot* S = &e.slots[blockIdx.x];
-  if (ldc(&S->status) != kInner) return;
-  const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
+  const int status = ldc(&S->status);
+  const bool outer = (status == kOuterPending || status == kInnerDone);
+  if (status != kInner && !outer) return;
+  const int nblk = ldc(&S->nblk);
   double v[kNDots], tot[kNDots];
 #pragma unroll
   for (int k = 0; k < kNDots; ++k) v[k] = 0.0;
@@ -233,186 +355,70 @@ __global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
   const double2 qq = make_double2(tot[4], tot[5]);
   const double2 rr = make_double2(tot[6], tot[7]);
   const double n2 = tot[8];
-  const bool prime = ldc(&S->prime) != 0;
   S->parity = ldc(&S->parity) ^ 1;
+  const bool ok = finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) && (fabs(pq.x) + fabs(pq.y) > 0.0) &&
+                  (fabs(rr.x) + fabs(rr.y) > 0.0);
   int it_total = ldc(&S->it_total);
-  if (!prime) {
+  if (outer) {
+    // n2 is the FP64 residual |b - K x|^2 of the current iterate
+    const int rounds0 = ldc(&S->rounds);
+    double bn2 = ldc(&S->bn2);
+    if (rounds0 == 0) {
+      bn2 = n2;
+      S->bn2 = n2;
+    }
+    const int rounds = rounds0 + 1;
+    S->rounds = rounds;
+    const double prev = ldc(&S->prev_rn2);
+    const double tol2 = ldc(&S->tol2);
+    S->rn2 = n2;
+    S->prev_rn2 = n2;
+    if (!isfinite(n2)) {
+      S->status = kFailBreakdown;
+      return;
+    }
+    if (n2 <= tol2 * bn2) {
+      S->status = kDone;
+      return;
+    }
+    if (rounds >= 3 && n2 > 0.25 * prev) {
+      // a whole inner solve did not halve the FP64 residual: it sits at its
+      // rounding floor, above the requested tolerance
+      S->status = kDone;
+      S->stagnated = 1;
+      return;
+    }
+    if (it_total >= e.max_iter) {
+      S->status = kFailMaxIter;
+      return;
+    }
+    if (!ok) {
+      S->status = kFailBreakdown;
+      return;
+    }
+    S->status = kInner;
+    S->it_inner = 0;
+    // the requested reduction of this residual, never below a quarter of
+    // the final tolerance
+    S->in_tol2 = fmax(e.inner_eta2 * n2, 0.0625 * tol2 * bn2);
+  } else {
     S->it_inner = ldc(&S->it_inner) + 1;
     it_total += 1;
     S->it_total = it_total;
-  }
-  S->prime = 0;
-  const bool ok = isfinite(n2) && finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) &&
-                  (fabs(pq.x) + fabs(pq.y) > 0.0) && (fabs(rr.x) + fabs(rr.y) > 0.0);
-  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
-    S->status = kInnerDone;
-  } else {
-    const double2 al = cdiv(rr, pq);
-    // rr_{i+2} = rr - 2 alpha qr + alpha^2 qq
-    const double2 a2 = make_double2(al.x * al.x - al.y * al.y, 2.0 * al.x * al.y);
-    const double2 aqr = make_double2(al.x * qr.x - al.y * qr.y, al.x * qr.y + al.y * qr.x);
-    const double2 aqq = make_double2(a2.x * qq.x - a2.y * qq.y, a2.x * qq.y + a2.y * qq.x);
-    const double2 rr2 = make_double2(rr.x - 2.0 * aqr.x + aqq.x, rr.y - 2.0 * aqr.y + aqq.y);
-    S->alpha = al;
-    S->beta = cdiv(rr2, rr);
-    S->rr = rr;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 outer steps
-// ---------------------------------------------------------------------------
-// x64 += d for slots whose inner solve finished
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_outer_update(Eng e) {
-  using V = typename C2<T>::t;
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
-    const Slot* S = &e.slots[it.slot];
-    if (ldc(&S->status) != kInnerDone) continue;
-    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
-    const size_t base = size_t(it.slot) * e.cap;
-    const V* d = reinterpret_cast<const V*>(e.d) + base;
-    double2* x = e.x64 + base;
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int gx = x0 + tx, gy = y0 + ty + 4 * j;
-      if (gx < I.nx && gy < I.ny) {
-        const size_t gi = size_t(gy) * I.nx + gx;
-        const V dv = d[gi];
-        double2 xv = x[gi];
-        xv.x += double(dv.x);
-        xv.y += double(dv.y);
-        x[gi] = xv;
-      }
+    if (!ok || !isfinite(n2) || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
+      S->status = kInnerDone;
+      return;
     }
   }
-}
-
-// r64 = b - (L - zeta) x64 in FP64; r = (T) r64 into the current r buffer,
-// d = 0.  The last block of a slot decides: done, failed, or a new inner
-// solve (prime pass next).
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_outer_residual(Eng e) {
-  using V = typename C2<T>::t;
-  constexpr int W = kTX + 4, H = kTY + 4;
-  __shared__ double2 XT[H * W];
-  __shared__ double red[4 * 2];
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
-    Slot* S = &e.slots[it.slot];
-    const int st = ldc(&S->status);
-    if (st != kInnerDone && st != kOuterPending) continue;
-    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
-    const size_t base = size_t(it.slot) * e.cap;
-    const double2* x = e.x64 + base;
-    V* r = reinterpret_cast<V*>(ldc(&S->parity) ? e.r1 : e.r0) + base;
-    V* d = reinterpret_cast<V*>(e.d) + base;
-    const double2 zeta = ldc(&S->zeta), a1 = ldc(&S->a1), a2 = ldc(&S->a2);
-    const bool zero_x = (ldc(&S->rounds) == 0);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= W) && (I.ny >= H);
-    __syncthreads();
-    if (!zero_x) {
-      for (int k = threadIdx.x; k < H * W; k += kNT) {
-        const int ly = k / W, lx = k - ly * W;
-        XT[k] = x[size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big)];
-      }
-    }
-    __syncthreads();
-    double s[2] = {0.0, 0.0};
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      const int gx = x0 + tx, gy = y0 + ly;
-      if (gx < I.nx && gy < I.ny) {
-        const size_t gi = size_t(gy) * I.nx + gx;
-        double2 bv = make_double2(I.eta0[gi], 0.0);
-        if (I.D0) {
-          const double dv = I.D0[gi], zv = I.Z0[gi];
-          bv.x += a1.x * dv + a2.x * zv;
-          bv.y += a1.y * dv + a2.y * zv;
-        }
-        double2 rv = bv;
-#ifdef REXII_DEBUG_CHECKS
-        if (zero_x && (x[gi].x != 0.0 || x[gi].y != 0.0)) atomicAdd(&e.dbg[3], 1);
-#endif
-        if (!zero_x) rv = csub(bv, helm<double2, double, W>(XT, ly + 2, tx + 2, I.cx, I.cy, zeta));
-        r[gi] = mk<V>(rv.x, rv.y);
-        d[gi] = mk<V>(0.0, 0.0);
-        s[0] += rv.x * rv.x + rv.y * rv.y;
-      }
-    }
-    double tot[2];
-    block_sum_n<2>(s, red, tot);
-    if (threadIdx.x == 0) e.part[(size_t(it.slot) * e.cap_blk + it.tile) * kNDots] = tot[0];
-  }
-}
-
-// One block per slot after the FP64 residual: done, failed, or a new inner
-// solve (prime pass next).
-__global__ __launch_bounds__(kNT) void k_outer_scalars(Eng e) {
-  __shared__ double red[4 * 2];
-  Slot* S = &e.slots[blockIdx.x];
-  const int st = ldc(&S->status);
-  if (st != kInnerDone && st != kOuterPending) return;
-  const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
-  double v[2] = {0.0, 0.0}, tot[2];
-  const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
-  for (int b = threadIdx.x; b < nblk; b += kNT) {
-    v[0] += ldc(&pp[size_t(b) * kNDots]);
-    if (e.method == 1) v[1] += ldc(&pp[size_t(b) * kNDots + 1]);
-  }
-  block_sum_n<2>(v, red, tot);
-  if (threadIdx.x != 0) return;
-  const double rn2 = tot[0];
-  const int rounds0 = ldc(&S->rounds);
-  double bn2 = ldc(&S->bn2);
-  if (rounds0 == 0) {
-    bn2 = rn2;
-    S->bn2 = rn2;
-  }
-  const int rounds = rounds0 + 1;
-  S->rounds = rounds;
-  const double prev = ldc(&S->prev_rn2);
-  const double tol2 = ldc(&S->tol2);
-  S->rn2 = rn2;
-  S->prev_rn2 = rn2;
-  if (!isfinite(rn2)) {
-    S->status = kFailBreakdown;
-  } else if (rn2 <= tol2 * bn2) {
-    S->status = kDone;
-  } else if (rounds >= 3 && rn2 > 0.25 * prev) {
-    // a whole inner solve did not halve the FP64 residual: it sits at its
-    // rounding floor, above the requested tolerance
-    S->status = kDone;
-    S->stagnated = 1;
-  } else if (ldc(&S->it_total) >= e.max_iter) {
-    S->status = kFailMaxIter;
-  } else {
-    S->status = kInner;
-    S->prime = 1;
-    S->it_inner = 0;
-    S->alpha = make_double2(0.0, 0.0);
-    S->beta = make_double2(0.0, 0.0);
-    S->omega = make_double2(0.0, 0.0);
-    // BiCGStab starts from rho = <r_hat, r> = |r|^2 of the rounded residual
-    if (e.method == 1) S->rr = make_double2(tot[1], 0.0);
-    // the requested reduction of this residual, never below a quarter of
-    // the final tolerance
-    S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
-  }
+  const double2 al = cdiv(rr, pq);
+  // rr_{i+2} = rr - 2 alpha qr + alpha^2 qq
+  const double2 a2 = make_double2(al.x * al.x - al.y * al.y, 2.0 * al.x * al.y);
+  const double2 aqr = make_double2(al.x * qr.x - al.y * qr.y, al.x * qr.y + al.y * qr.x);
+  const double2 aqq = make_double2(a2.x * qq.x - a2.y * qq.y, a2.x * qq.y + a2.y * qq.x);
+  const double2 rr2 = make_double2(rr.x - 2.0 * aqr.x + aqq.x, rr.y - 2.0 * aqr.y + aqq.y);
+  S->alpha = al;
+  S->beta = cdiv(rr2, rr);
+  S->rr = rr;
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +440,20 @@ __global__ void k_retire(Eng e) {
       const int n = I.nx * I.ny;
       if (i >= n) continue;
       double2* xp = e.x64 + size_t(s) * e.cap + i;
-      const double2 x = *xp;
+      double2 x = *xp;
+      // the last inner correction d is still to be added (once the solve
+      // has run an inner round)
+      if (ldc(&S->rounds) >= 2) {
+        if (e.d_is_f32) {
+          const float2 dv = reinterpret_cast<const float2*>(e.d)[size_t(s) * e.cap + i];
+          x.x += double(dv.x);
+          x.y += double(dv.y);
+        } else {
+          const double2 dv = reinterpret_cast<const double2*>(e.d)[size_t(s) * e.cap + i];
+          x.x += dv.x;
+          x.y += dv.y;
+        }
+      }
       const int sv = ldc(&S->solve);
       if (e.yout) e.yout[size_t(sv) * e.cap + i] = x;
       const double2 c0 = ldc(&e.solves[sv].c0), c1 = ldc(&e.solves[sv].c1), c2 = ldc(&e.solves[sv].c2);
@@ -494,6 +513,20 @@ __global__ void k_assign(Eng e) {
       S->it_total = S->it_inner = S->rounds = 0;
       S->solve = next;
       S->inst = dinst;
+      {
+        const Inst* I = &e.inst[dinst];
+        S->nx = ldc(&I->nx);
+        S->ny = ldc(&I->ny);
+        S->tiles_x = ldc(&I->tiles_x);
+        S->nblk = ldc(&I->nblk);
+        S->cx = ldc(&I->cx);
+        S->cy = ldc(&I->cy);
+        S->cxy = ldc(&I->cxy);
+        S->H = ldc_ptr(&I->H);
+        S->eta0 = ldc_ptr(&I->eta0);
+        S->D0 = ldc_ptr(&I->D0);
+        S->Z0 = ldc_ptr(&I->Z0);
+      }
       S->stagnated = 0;
       status = kOuterPending;
       ++next;
@@ -703,21 +736,13 @@ static inline unsigned flat_blocks(size_t n) {
 
 template <typename T>
 void launch_pass(const Eng& e, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass<T>, dim3(grid), dim3(kNT), 0, s, e);
-}
-template <typename T>
-void launch_outer_update(const Eng& e, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update<T>, dim3(grid), dim3(kNT), 0, s, e);
-}
-template <typename T>
-void launch_outer_residual(const Eng& e, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_residual<T>, dim3(grid), dim3(kNT), 0, s, e);
+  if (sizeof(T) == 4)
+    hipLaunchKernelGGL(k_pass_f32, dim3(grid), dim3(kNT), 0, s, e);
+  else
+    hipLaunchKernelGGL(k_pass_f64, dim3(grid), dim3(kNT), 0, s, e);
 }
 void launch_pass_scalars(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_scalars, dim3(e.B), dim3(kNT), 0, s, e);
-}
-void launch_outer_scalars(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_scalars, dim3(e.B), dim3(kNT), 0, s, e);
 }
 void launch_retire(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(256), 0, s, e);
@@ -750,16 +775,12 @@ void launch_expand(const double2* y, const double* f, int nx, int ny, double2 is
 
 int pass_occupancy(int mixed) {
   int occ = 0;
-  hipError_t err = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass<float>, kNT, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass<double>, kNT, 0);
+  hipError_t err = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass_f32, kNT, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pass_f64, kNT, 0);
   return err == hipSuccess ? occ : 1;
 }
 
 template void launch_pass<float>(const Eng&, int, hipStream_t);
 template void launch_pass<double>(const Eng&, int, hipStream_t);
-template void launch_outer_update<float>(const Eng&, int, hipStream_t);
-template void launch_outer_update<double>(const Eng&, int, hipStream_t);
-template void launch_outer_residual<float>(const Eng&, int, hipStream_t);
-template void launch_outer_residual<double>(const Eng&, int, hipStream_t);
 
 }  // namespace rexii

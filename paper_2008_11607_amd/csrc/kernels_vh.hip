@@ -1,37 +1,53 @@
 // Variable-depth (flux form) shifted solves: BiCGStab on
 //   K eta = (L_H + gamma C_H - zeta) eta = b        (see kernels.h)
-// for every live slot, three passes per iteration, each followed by a
-// one-block-per-slot scalar kernel (deterministic partial sums):
-//   A: p = r + beta (p - omega v)  (p = r on the first iteration),  v = K p,
-//      partial <r_hat, v>                       -> alpha = rho / <r_hat, v>
-//   B: s = r - alpha v,  t = K s,  partials <t, s>, <t, t>
-//                                               -> omega = <t, s> / <t, t>
-//   C: s, t again,  x += alpha p + omega s,  r = s - omega t,
-//      partials <r_hat, r>, |r|^2               -> beta = (rho'/rho)(alpha/omega)
-// <a, b> = sum conj(a) b.  r, p, v are ping-pong buffers so that no pass
-// reads (with a halo) what it writes.  The FP64 residual / refinement loop
-// around the inner solve is shared with the COCG path (k_outer_update) plus
-// the variable-coefficient residual below.
+// for every live slot, with <a, b> = sum conj(a) b and the shadow residual
+// r_hat fixed to the first residual of each inner solve.  One iteration is
+// three stencil passes and two one-block-per-slot scalar kernels
+// (deterministic partial sums):
+//
+//   pass S  (alpha known):  s = r - alpha v (tile + halo 2), t = K s;
+//           partials <t, s>, <t, t>, <s, s>, <r_hat, s>, <r_hat, t>
+//   scalars: omega = <t, s>/<t, t> and, with no further pass,
+//           rho' = <r_hat, r'> = <r_hat, s> - omega <r_hat, t>,
+//           |r'|^2 = <s, s> - |<t, s>|^2/<t, t>  (stop test),
+//           beta = (rho'/rho)(alpha/omega)
+//   pass U1 (omega, beta known):  s and t again, then on the tile
+//           d += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v)
+//   pass U2: v' = K p',  partial <r_hat, v'>
+//   scalars: alpha' = rho'/<r_hat, v'>
+//
+// The FP64 residual round of iterative refinement is folded into pass U1: a
+// slot whose inner solve ended computes, with x = x64 + d (0 for a fresh
+// solve), r64 = sc (eta0 + a1 D_H + a2 Z_H) - K x in FP64 and sets
+// r = r_hat = p = (T) r64; pass U2 then forms v = K p and the scalar kernel
+// decides convergence or restarts the inner solve.  As in the COCG pass,
+// x64 and d are only read in a residual round; the first pass U1 of the next
+// round moves d into x64.  A slot whose stop test fired in the scalars of
+// pass S still gets its last update d += alpha p + omega s in pass U1
+// (status kInnerLast) before its residual round.  r, p and v are ping-pong
+// buffers so that no pass reads (with a halo) what another block of the
+// same pass writes.
 #include "device_util.h"
 #include "kernels.h"
 
 namespace rexii {
 
-constexpr int kVW = kTX + 4, kVH = kTY + 4;   // field tile with halo 2
+constexpr int kBW = kTX + 4, kBH = kTY + 4;   // tile with halo 2
+constexpr int kSW = kTX + 8, kSH = kTY + 8;   // grids at least this large take the cheap wrap
 constexpr int kHW = kTX + 2, kHH = kTY + 2;   // depth tile with halo 1
 
-// K phi at interior position (ly, lx) of a tile: phi tile with halo 2
-// (row width kVW), depth tile with halo 1 (row width kHW).
-template <typename V, typename S>
-__device__ __forceinline__ V kop(const V* P, const S* Hs, int ly, int lx, S cx, S cy, S cxy, V gamma, V zeta) {
-  const int y = ly + 2, x = lx + 2;
-  const V c = P[y * kVW + x];
-  const V e = P[y * kVW + x + 2], w = P[y * kVW + x - 2];
-  const V n = P[(y + 2) * kVW + x], s = P[(y - 2) * kVW + x];
-  const V ne = P[(y + 1) * kVW + x + 1], nw = P[(y + 1) * kVW + x - 1];
-  const V se = P[(y - 1) * kVW + x + 1], sw = P[(y - 1) * kVW + x - 1];
-  const S hxp = Hs[(ly + 1) * kHW + lx + 2], hxm = Hs[(ly + 1) * kHW + lx];
-  const S hyp = Hs[(ly + 2) * kHW + lx + 1], hym = Hs[ly * kHW + lx + 1];
+// K phi at position (y, x) of a phi tile with row width PW; the same grid
+// point is (y + DH, x + DH) of the depth tile (row width HW).
+template <int PW, int HW, int DH, typename V, typename S, typename HT>
+__device__ __forceinline__ V kop(const V* P, const HT* Hs, int y, int x, S cx, S cy, S cxy, V gamma, V zeta) {
+  const V c = P[y * PW + x];
+  const V e = P[y * PW + x + 2], w = P[y * PW + x - 2];
+  const V n = P[(y + 2) * PW + x], s = P[(y - 2) * PW + x];
+  const V ne = P[(y + 1) * PW + x + 1], nw = P[(y + 1) * PW + x - 1];
+  const V se = P[(y - 1) * PW + x + 1], sw = P[(y - 1) * PW + x - 1];
+  const int hy = y + DH, hx = x + DH;
+  const S hxp = S(Hs[hy * HW + hx + 1]), hxm = S(Hs[hy * HW + hx - 1]);
+  const S hyp = S(Hs[(hy + 1) * HW + hx]), hym = S(Hs[(hy - 1) * HW + hx]);
   V lh, ch;
   lh.x = cx * (hxp * (e.x - c.x) - hxm * (c.x - w.x)) + cy * (hyp * (n.x - c.x) - hym * (c.x - s.x));
   lh.y = cx * (hxp * (e.y - c.y) - hxm * (c.y - w.y)) + cy * (hyp * (n.y - c.y) - hym * (c.y - s.y));
@@ -43,92 +59,400 @@ __device__ __forceinline__ V kop(const V* P, const S* Hs, int ly, int lx, S cx, 
   return q;
 }
 
-template <typename T>
-__device__ __forceinline__ void load_depth(T* Hs, const double* H, int x0, int y0, const Inst& I, bool big) {
-  for (int k = threadIdx.x; k < kHH * kHW; k += kNT) {
-    const int ly = k / kHW, lx = k - ly * kHW;
-    Hs[k] = T(H[size_t(wrapc(y0 - 1 + ly, I.ny, big)) * I.nx + wrapc(x0 - 1 + lx, I.nx, big)]);
-  }
+// conj(a) b accumulated in FP64
+template <typename V>
+__device__ __forceinline__ void cdot(double* acc, V a, V b) {
+  acc[0] += double(a.x) * b.x + double(a.y) * b.y;
+  acc[1] += double(a.x) * b.y - double(a.y) * b.x;
 }
 
-struct SlotView {
-  int slot, par;
-  bool first;
+// Control fields of a slot, read in one round of coherent loads.
+struct BcgCtl {
+  int status, par, rounds, it_inner, nx, ny, tiles_x;
+  double cx, cy, cxy;
+  const double* H;
   double2 alpha, beta, omega, gamma, zeta;
 };
 
-// Resolves work item w of the pass; returns false if the block has nothing
-// to do for it (uniform across the block).
-__device__ __forceinline__ bool bcg_item(const Eng& e, int w, int per, int total, int un, Item& it, SlotView& sv,
-                                         Inst& I) {
-  const int pos = xcd_pos(w, per);
-  if (pos >= total) return false;
-  it = item_of(e, pos, un);
-  const Slot* S = &e.slots[it.slot];
-  if (ldc(&S->status) != kInner) return false;
-  I = ld_inst(&e.inst[ldc(&S->inst)]);
-  sv.slot = it.slot;
-  sv.par = ldc(&S->parity);
-  sv.first = ldc(&S->prime) != 0;
-  sv.alpha = ldc(&S->alpha);
-  sv.beta = ldc(&S->beta);
-  sv.omega = ldc(&S->omega);
-  sv.gamma = ldc(&S->gamma);
-  sv.zeta = ldc(&S->zeta);
-  return true;
+__device__ __forceinline__ BcgCtl load_bctl(const Slot* S) {
+  BcgCtl c;
+  c.status = ldu(&S->status);
+  c.par = ldu(&S->parity);
+  c.rounds = ldu(&S->rounds);
+  c.it_inner = ldu(&S->it_inner);
+  c.nx = ldu(&S->nx);
+  c.ny = ldu(&S->ny);
+  c.tiles_x = ldu(&S->tiles_x);
+  c.cx = ldu(&S->cx);
+  c.cy = ldu(&S->cy);
+  c.cxy = ldu(&S->cxy);
+  c.H = ldu_ptr(&S->H);
+  c.alpha = ldu(&S->alpha);
+  c.beta = ldu(&S->beta);
+  c.omega = ldu(&S->omega);
+  c.gamma = ldu(&S->gamma);
+  c.zeta = ldu(&S->zeta);
+  return c;
 }
 
-// ---- pass A ----------------------------------------------------------------
+// ---- pass S ----------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_bcg_a(Eng e) {
+struct LdsS {
   using V = typename C2<T>::t;
-  __shared__ V PT[kVH * kVW];
-  __shared__ T Hs[kHH * kHW];
-  __shared__ double red[4 * 2];
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
+  static constexpr size_t kBytes = sizeof(V) * kBH * kBW + sizeof(T) * kHH * kHW;
+};
+
+template <typename T>
+__device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
+                                      double (&acc)[8]) {
+  using V = typename C2<T>::t;
+  V* ST = reinterpret_cast<V*>(lds);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    Item it;
-    SlotView sv;
-    Inst I;
-    if (!bcg_item(e, w, per, total, un, it, sv, I)) continue;
-    const size_t base = size_t(it.slot) * e.cap;
-    const V* rs = reinterpret_cast<const V*>(sv.par ? e.r1 : e.r0) + base;
-    const V* ps = reinterpret_cast<const V*>(sv.par ? e.p1 : e.p0) + base;
-    const V* vs = reinterpret_cast<const V*>(sv.par ? e.v1 : e.v0) + base;
-    V* pd = reinterpret_cast<V*>(sv.par ? e.p0 : e.p1) + base;
-    V* vd = reinterpret_cast<V*>(sv.par ? e.v0 : e.v1) + base;
-    const V* rh = reinterpret_cast<const V*>(e.rh) + base;
-    const V beta = mk<V>(sv.beta.x, sv.beta.y), omega = mk<V>(sv.omega.x, sv.omega.y);
-    const V gamma = mk<V>(sv.gamma.x, sv.gamma.y), zeta = mk<V>(sv.zeta.x, sv.zeta.y);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= kVW) && (I.ny >= kVH);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kVH * kVW; k += kNT) {
-      const int ly = k / kVW, lx = k - ly * kVW;
-      const size_t gi = size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big);
-      V pn = rs[gi];
-      if (!sv.first) pn = cadd(pn, cmul(beta, csub(ps[gi], cmul(omega, vs[gi]))));
-      PT[k] = pn;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  const V* vs = reinterpret_cast<const V*>(c.par ? e.v1 : e.v0) + base;
+  const V* rh = reinterpret_cast<const V*>(e.rh) + base;
+  const V alpha = mk<V>(c.alpha.x, c.alpha.y);
+  const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kSW) && (ny >= kSH);
+  TileRegs<V, kBH, kBW> sr;
+  sr.fetch([&](int ly, int lx) {
+    const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+    return csub(rs[g], cmul(alpha, vs[g]));
+  });
+  TileRegs<T, kHH, kHW> hr;
+  hr.fetch([&](int ly, int lx) {
+    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+  });
+  V hv[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j)
+    hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
+  __syncthreads();  // LDS of the previous work item is free
+  sr.store(ST);
+  hr.store(Hs);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
+      const V s = ST[(ly + 2) * kBW + tx + 2];
+      cdot(acc + 0, t, s);
+      acc[2] += double(t.x) * t.x + double(t.y) * t.y;
+      acc[3] += double(s.x) * s.x + double(s.y) * s.y;
+      cdot(acc + 4, hv[j], s);
+      cdot(acc + 6, hv[j], t);
     }
-    load_depth<T>(Hs, I.H, x0, y0, I, big);
-    __syncthreads();
-    double acc[2] = {0.0, 0.0};
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      const int gx = x0 + tx, gy = y0 + ly;
-      if (gx < I.nx && gy < I.ny) {
-        const size_t gi = size_t(gy) * I.nx + gx;
-        const V vn = kop<V, T>(PT, Hs, ly, tx, T(I.cx), T(I.cy), T(I.cxy), gamma, zeta);
-        pd[gi] = PT[(ly + 2) * kVW + tx + 2];
-        vd[gi] = vn;
-        const V h = rh[gi];
-        acc[0] += double(h.x) * vn.x + double(h.y) * vn.y;   // conj(h) vn
-        acc[1] += double(h.x) * vn.y - double(h.y) * vn.x;
+  }
+}
+
+// ---- pass U1: updates ------------------------------------------------------
+// Inner step: s = r - alpha v (tile + halo 2), t = K s, then on the tile
+// d += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v).
+template <typename T>
+__device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds) {
+  using V = typename C2<T>::t;
+  V* ST = reinterpret_cast<V*>(lds);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
+  const V* ps = reinterpret_cast<const V*>(c.par ? e.p1 : e.p0) + base;
+  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  const V* vs = reinterpret_cast<const V*>(c.par ? e.v1 : e.v0) + base;
+  V* d = reinterpret_cast<V*>(e.d) + base;
+  double2* x64 = e.x64 + base;
+  const bool first = c.it_inner == 1;        // d restarts this pass
+  const bool fold = first && c.rounds >= 2;  // ... after x64 += d
+  const V alpha = mk<V>(c.alpha.x, c.alpha.y), beta = mk<V>(c.beta.x, c.beta.y);
+  const V omega = mk<V>(c.omega.x, c.omega.y);
+  const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kSW) && (ny >= kSH);
+  TileRegs<V, kBH, kBW> sr;
+  sr.fetch([&](int ly, int lx) {
+    const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+    return csub(rs[g], cmul(alpha, vs[g]));
+  });
+  TileRegs<T, kHH, kHW> hr;
+  hr.fetch([&](int ly, int lx) {
+    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+  });
+  size_t gi[kTY / 4];
+  V pv[kTY / 4], vv[kTY / 4], dv[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    gi[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
+    pv[j] = ps[gi[j]];
+    vv[j] = vs[gi[j]];
+    if (!first) dv[j] = nt_load(&d[gi[j]]);
+  }
+  __syncthreads();  // LDS of the previous work item is free
+  sr.store(ST);
+  hr.store(Hs);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
+      const V sv = ST[(ly + 2) * kBW + tx + 2];
+      const V r1 = csub(sv, cmul(omega, t));
+      const V p1 = cadd(r1, cmul(beta, csub(pv[j], cmul(omega, vv[j]))));
+      const V upd = cadd(cmul(alpha, pv[j]), cmul(omega, sv));
+      if (fold) {
+        // once per round: the previous round's correction moves into x64
+        const V dold = d[gi[j]];
+        const double2 xo = x64[gi[j]];
+        x64[gi[j]] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
       }
+      nt_store(first ? upd : cadd(dv[j], upd), &d[gi[j]]);
+      rd[gi[j]] = r1;
+      pd[gi[j]] = p1;
     }
+  }
+}
+
+// last update of an inner solve (no halo): d += alpha p + omega (r - alpha v)
+template <typename T>
+__device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int slot, int tile) {
+  using V = typename C2<T>::t;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  const V* ps = reinterpret_cast<const V*>(c.par ? e.p1 : e.p0) + base;
+  const V* vs = reinterpret_cast<const V*>(c.par ? e.v1 : e.v0) + base;
+  V* d = reinterpret_cast<V*>(e.d) + base;
+  double2* x64 = e.x64 + base;
+  const bool first = c.it_inner == 1;
+  const bool fold = first && c.rounds >= 2;
+  const V alpha = mk<V>(c.alpha.x, c.alpha.y), omega = mk<V>(c.omega.x, c.omega.y);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int gx = x0 + tx, gy = y0 + ty + 4 * j;
+    if (gx < nx && gy < ny) {
+      const size_t g = size_t(gy) * nx + gx;
+      const V s = csub(rs[g], cmul(alpha, vs[g]));
+      const V upd = cadd(cmul(alpha, ps[g]), cmul(omega, s));
+      const V dold = d[g];
+      if (fold) {
+        const double2 xo = x64[g];
+        x64[g] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
+      }
+      d[g] = first ? upd : cadd(dold, upd);
+    }
+  }
+}
+
+// FP64 residual round: with x = x64 + d (0 for a fresh solve) on tile +
+// halo 2, r64 = sc (eta0 + a1 D_H + a2 Z_H) - K x on the tile;
+// r = r_hat = p = (T) r64; partials |r64|^2 (index 2) and |r|^2 (index 3).
+template <typename T>
+__device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
+                                             double (&acc)[2]) {
+  using V = typename C2<T>::t;
+  double2* XT = reinterpret_cast<double2*>(lds);
+  double* Hs = reinterpret_cast<double*>(lds + sizeof(double2) * kBH * kBW);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const double2* x64 = e.x64 + base;
+  const V* d = reinterpret_cast<const V*>(e.d) + base;
+  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
+  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  V* rh = reinterpret_cast<V*>(e.rh) + base;
+  const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
+  const Slot* S = &e.slots[slot];
+  const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2), sc = ldu(&S->sc);
+  const double* eta0 = ldu_ptr(&S->eta0);
+  const double* D0 = ldu_ptr(&S->D0);
+  const double* Z0 = ldu_ptr(&S->Z0);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kSW) && (ny >= kSH);
+  __syncthreads();  // LDS of the previous work item is free
+  if (!zero_x) {
+    stage_tile<double2, kBH, kBW, 2>(XT, [&](int ly, int lx) {
+      const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+      const V dv = d[g];
+      const double2 xv = x64[g];
+      return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
+    });
+    stage_tile<double, kHH, kHW, 1>(Hs, [&](int ly, int lx) {
+      return c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)];
+    });
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    const int gx = x0 + tx, gy = y0 + ly;
+    if (gx < nx && gy < ny) {
+      const size_t g = size_t(gy) * nx + gx;
+      double2 bv = make_double2(eta0[g], 0.0);
+      if (D0) {
+        const double dz = D0[g], zz = Z0[g];
+        bv.x += a1.x * dz + a2.x * zz;
+        bv.y += a1.y * dz + a2.y * zz;
+      }
+      double2 rv = cmul(sc, bv);
+      if (!zero_x) rv = csub(rv, kop<kBW, kHW, -1>(XT, Hs, ly + 2, tx + 2, c.cx, c.cy, c.cxy, c.gamma, c.zeta));
+      const V rt = mk<V>(rv.x, rv.y);
+      rd[g] = rt;
+      pd[g] = rt;
+      rh[g] = rt;
+      acc[0] += rv.x * rv.x + rv.y * rv.y;
+      acc[1] += double(rt.x) * rt.x + double(rt.y) * rt.y;
+    }
+  }
+}
+
+// ---- pass U2: v' = K p' and <r_hat, v'> -------------------------------------
+template <typename T>
+__device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
+                                       double (&acc)[2]) {
+  using V = typename C2<T>::t;
+  V* PT = reinterpret_cast<V*>(lds);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  // p' was written by pass U1 into the buffers of the next parity
+  const V* pn = reinterpret_cast<const V*>(c.par ? e.p0 : e.p1) + base;
+  V* vd = reinterpret_cast<V*>(c.par ? e.v0 : e.v1) + base;
+  const V* rh = reinterpret_cast<const V*>(e.rh) + base;
+  const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kSW) && (ny >= kSH);
+  TileRegs<V, kBH, kBW> pr;
+  pr.fetch([&](int ly, int lx) {
+    return pn[size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big)];
+  });
+  TileRegs<T, kHH, kHW> hr;
+  hr.fetch([&](int ly, int lx) {
+    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+  });
+  V hv[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j)
+    hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
+  __syncthreads();  // LDS of the previous work item is free
+  pr.store(PT);
+  hr.store(Hs);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = ty + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V v1 = kop<kBW, kHW, -1>(PT, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
+      vd[size_t(y0 + ly) * nx + x0 + tx] = v1;
+      cdot(acc, hv[j], v1);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bcg_pass_s(const Eng& e) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  __shared__ double red[4 * 8];
+  const int total = ldu(&e.tile_start[e.B]);
+  const int un = ldu(&e.work[1]);
+  const int per = (total + 7) >> 3;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e, pos, un);
+    const BcgCtl c = load_bctl(&e.slots[it.slot]);
+    if (c.status != kInner) continue;
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    bcg_s<T>(e, c, it.slot, it.tile, lds, acc);
+    double tot[8];
+    block_sum_n<8>(acc, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pp[k] = tot[k];
+    }
+  }
+}
+
+template <typename T>
+struct LdsU1 {
+  static constexpr size_t kX = sizeof(double2) * kBH * kBW + sizeof(double) * kHH * kHW;  // residual round
+};
+
+template <typename T>
+__device__ __forceinline__ void bcg_pass_u1(const Eng& e) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  const int total = ldu(&e.tile_start[e.B]);
+  const int un = ldu(&e.work[1]);
+  const int per = (total + 7) >> 3;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e, pos, un);
+    const BcgCtl c = load_bctl(&e.slots[it.slot]);
+    if (c.status == kInner)
+      bcg_u1_inner<T>(e, c, it.slot, it.tile, lds);
+    else if (c.status == kInnerLast)
+      bcg_u1_last<T>(e, c, it.slot, it.tile);
+  }
+}
+
+// the FP64 residual rounds (a kernel of their own: sharing pass U1 would
+// raise its register count for a step that runs once per round)
+template <typename T>
+__device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsU1<T>::kX];
+  __shared__ double red[4 * 2];
+  const int total = ldu(&e.tile_start[e.B]);
+  const int un = ldu(&e.work[1]);
+  const int per = (total + 7) >> 3;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e, pos, un);
+    const BcgCtl c = load_bctl(&e.slots[it.slot]);
+    if (c.status != kOuterPending && c.status != kInnerDone) continue;
+    double acc[2] = {0.0, 0.0};
+    bcg_u1_outer<T>(e, c, it.slot, it.tile, lds, acc);
+    double tot[2];
+    block_sum_n<2>(acc, red, tot);
+    if (threadIdx.x == 0) {
+      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
+      pp[2] = tot[0];
+      pp[3] = tot[1];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  __shared__ double red[4 * 2];
+  const int total = ldu(&e.tile_start[e.B]);
+  const int un = ldu(&e.work[1]);
+  const int per = (total + 7) >> 3;
+  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
+    const int pos = xcd_pos(w, per);
+    if (pos >= total) continue;
+    const Item it = item_of(e, pos, un);
+    const BcgCtl c = load_bctl(&e.slots[it.slot]);
+    if (c.status != kInner && c.status != kOuterPending && c.status != kInnerDone) continue;
+    double acc[2] = {0.0, 0.0};
+    bcg_u2<T>(e, c, it.slot, it.tile, lds, acc);
     double tot[2];
     block_sum_n<2>(acc, red, tot);
     if (threadIdx.x == 0) {
@@ -139,126 +463,19 @@ __global__ __launch_bounds__(kNT) void k_bcg_a(Eng e) {
   }
 }
 
-// ---- pass B ----------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_bcg_b(Eng e) {
-  using V = typename C2<T>::t;
-  __shared__ V PT[kVH * kVW];
-  __shared__ T Hs[kHH * kHW];
-  __shared__ double red[4 * 3];
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    Item it;
-    SlotView sv;
-    Inst I;
-    if (!bcg_item(e, w, per, total, un, it, sv, I)) continue;
-    const size_t base = size_t(it.slot) * e.cap;
-    const V* rs = reinterpret_cast<const V*>(sv.par ? e.r1 : e.r0) + base;
-    const V* vn = reinterpret_cast<const V*>(sv.par ? e.v0 : e.v1) + base;
-    const V alpha = mk<V>(sv.alpha.x, sv.alpha.y);
-    const V gamma = mk<V>(sv.gamma.x, sv.gamma.y), zeta = mk<V>(sv.zeta.x, sv.zeta.y);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= kVW) && (I.ny >= kVH);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kVH * kVW; k += kNT) {
-      const int ly = k / kVW, lx = k - ly * kVW;
-      const size_t gi = size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big);
-      PT[k] = csub(rs[gi], cmul(alpha, vn[gi]));
-    }
-    load_depth<T>(Hs, I.H, x0, y0, I, big);
-    __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      if (x0 + tx < I.nx && y0 + ly < I.ny) {
-        const V t = kop<V, T>(PT, Hs, ly, tx, T(I.cx), T(I.cy), T(I.cxy), gamma, zeta);
-        const V s = PT[(ly + 2) * kVW + tx + 2];
-        acc[0] += double(t.x) * s.x + double(t.y) * s.y;   // conj(t) s
-        acc[1] += double(t.x) * s.y - double(t.y) * s.x;
-        acc[2] += double(t.x) * t.x + double(t.y) * t.y;
-      }
-    }
-    double tot[3];
-    block_sum_n<3>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-      pp[0] = tot[0];
-      pp[1] = tot[1];
-      pp[2] = tot[2];
-    }
-  }
-}
-
-// ---- pass C ----------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_bcg_c(Eng e) {
-  using V = typename C2<T>::t;
-  __shared__ V PT[kVH * kVW];
-  __shared__ T Hs[kHH * kHW];
-  __shared__ double red[4 * 3];
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    Item it;
-    SlotView sv;
-    Inst I;
-    if (!bcg_item(e, w, per, total, un, it, sv, I)) continue;
-    const size_t base = size_t(it.slot) * e.cap;
-    const V* rs = reinterpret_cast<const V*>(sv.par ? e.r1 : e.r0) + base;
-    V* rd = reinterpret_cast<V*>(sv.par ? e.r0 : e.r1) + base;
-    const V* vn = reinterpret_cast<const V*>(sv.par ? e.v0 : e.v1) + base;
-    const V* pn = reinterpret_cast<const V*>(sv.par ? e.p0 : e.p1) + base;
-    const V* rh = reinterpret_cast<const V*>(e.rh) + base;
-    V* d = reinterpret_cast<V*>(e.d) + base;
-    const V alpha = mk<V>(sv.alpha.x, sv.alpha.y), omega = mk<V>(sv.omega.x, sv.omega.y);
-    const V gamma = mk<V>(sv.gamma.x, sv.gamma.y), zeta = mk<V>(sv.zeta.x, sv.zeta.y);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= kVW) && (I.ny >= kVH);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kVH * kVW; k += kNT) {
-      const int ly = k / kVW, lx = k - ly * kVW;
-      const size_t gi = size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big);
-      PT[k] = csub(rs[gi], cmul(alpha, vn[gi]));
-    }
-    load_depth<T>(Hs, I.H, x0, y0, I, big);
-    __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      const int gx = x0 + tx, gy = y0 + ly;
-      if (gx < I.nx && gy < I.ny) {
-        const size_t gi = size_t(gy) * I.nx + gx;
-        const V t = kop<V, T>(PT, Hs, ly, tx, T(I.cx), T(I.cy), T(I.cxy), gamma, zeta);
-        const V s = PT[(ly + 2) * kVW + tx + 2];
-        d[gi] = cadd(d[gi], cadd(cmul(alpha, pn[gi]), cmul(omega, s)));
-        const V r = csub(s, cmul(omega, t));
-        rd[gi] = r;
-        const V h = rh[gi];
-        acc[0] += double(h.x) * r.x + double(h.y) * r.y;   // conj(h) r
-        acc[1] += double(h.x) * r.y - double(h.y) * r.x;
-        acc[2] += double(r.x) * r.x + double(r.y) * r.y;
-      }
-    }
-    double tot[3];
-    block_sum_n<3>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-      pp[0] = tot[0];
-      pp[1] = tot[1];
-      pp[2] = tot[2];
-    }
-  }
-}
+__global__ __launch_bounds__(kNT) void k_bcg_s_f32(Eng e) { bcg_pass_s<float>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_s_f64(Eng e) { bcg_pass_s<double>(e); }
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_bcg_u1_f32(Eng e) { bcg_pass_u1<float>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f64(Eng e) { bcg_pass_u1<double>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f32(Eng e) { bcg_pass_outer<float>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f64(Eng e) { bcg_pass_outer<double>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f32(Eng e) { bcg_pass_u2<float>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f64(Eng e) { bcg_pass_u2<double>(e); }
 
 // ---- scalar kernels (one block per slot, partials in tile order) -----------
 template <int N>
-__device__ __forceinline__ bool slot_sums(const Eng& e, Slot* S, double (&tot)[N], double* red) {
-  const int nblk = ldc(&e.inst[ldc(&S->inst)].nblk);
+__device__ __forceinline__ bool slot_sums(const Eng& e, const Slot* S, double (&tot)[N], double* red) {
+  const int nblk = ldc(&S->nblk);
   double v[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] = 0.0;
@@ -271,128 +488,108 @@ __device__ __forceinline__ bool slot_sums(const Eng& e, Slot* S, double (&tot)[N
   return threadIdx.x == 0;
 }
 
-__global__ __launch_bounds__(kNT) void k_bcg_sa(Eng e) {
-  __shared__ double red[4 * 2];
-  Slot* S = &e.slots[blockIdx.x];
-  if (ldc(&S->status) != kInner) return;
-  double tot[2];
-  if (!slot_sums<2>(e, S, tot, red)) return;
-  const double2 rv = make_double2(tot[0], tot[1]);
-  if (!finite2(rv) || !(fabs(rv.x) + fabs(rv.y) > 0.0)) {
-    S->status = kInnerDone;  // breakdown: restart from the FP64 residual
-    return;
-  }
-  S->alpha = cdiv(ldc(&S->rr), rv);
-}
+__device__ __forceinline__ bool nonzero(double2 v) { return fabs(v.x) + fabs(v.y) > 0.0; }
 
-__global__ __launch_bounds__(kNT) void k_bcg_sb(Eng e) {
-  __shared__ double red[4 * 3];
+// after pass S: omega, rho', beta and the stop test
+__global__ __launch_bounds__(kNT) void k_bcg_scalars_s(Eng e) {
+  __shared__ double red[4 * 8];
   Slot* S = &e.slots[blockIdx.x];
   if (ldc(&S->status) != kInner) return;
-  double tot[3];
-  if (!slot_sums<3>(e, S, tot, red)) return;
+  double tot[8];
+  if (!slot_sums<8>(e, S, tot, red)) return;
   const double2 ts = make_double2(tot[0], tot[1]);
-  const double tt = tot[2];
-  S->omega = (tt > 0.0 && isfinite(tt) && finite2(ts)) ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0.0, 0.0);
-}
-
-__global__ __launch_bounds__(kNT) void k_bcg_sc(Eng e) {
-  __shared__ double red[4 * 3];
-  Slot* S = &e.slots[blockIdx.x];
-  if (ldc(&S->status) != kInner) return;
-  double tot[3];
-  if (!slot_sums<3>(e, S, tot, red)) return;
-  const double2 rr = make_double2(tot[0], tot[1]);
-  const double n2 = tot[2];
-  S->parity = ldc(&S->parity) ^ 1;
-  S->prime = 0;
+  const double tt = tot[2], ss = tot[3];
+  const double2 hs = make_double2(tot[4], tot[5]), ht = make_double2(tot[6], tot[7]);
   S->it_inner = ldc(&S->it_inner) + 1;
   const int it_total = ldc(&S->it_total) + 1;
   S->it_total = it_total;
-  const double2 om = ldc(&S->omega), al = ldc(&S->alpha), rho = ldc(&S->rr);
-  const bool ok = isfinite(n2) && finite2(rr) && (fabs(rr.x) + fabs(rr.y) > 0.0) && (fabs(om.x) + fabs(om.y) > 0.0) &&
-                  (fabs(rho.x) + fabs(rho.y) > 0.0);
-  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
-    S->status = kInnerDone;
+  const bool ok_t = tt > 0.0 && isfinite(tt) && finite2(ts) && isfinite(ss) && finite2(hs) && finite2(ht);
+  if (!ok_t) {
+    // breakdown: keep the BiCG half step (d += alpha p) and restart
+    S->omega = make_double2(0.0, 0.0);
+    S->status = kInnerLast;
     return;
   }
-  S->beta = cmul(cdiv(rr, rho), cdiv(al, om));
-  S->rr = rr;
+  const double2 om = make_double2(ts.x / tt, ts.y / tt);
+  S->omega = om;
+  const double2 rho1 = csub(hs, cmul(om, ht));
+  const double n2 = fmax(ss - (ts.x * ts.x + ts.y * ts.y) / tt, 0.0);
+  const double2 rho = ldc(&S->rr), al = ldc(&S->alpha);
+  const bool ok = nonzero(om) && nonzero(rho1) && nonzero(rho) && finite2(rho1);
+  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
+    S->status = kInnerLast;
+    return;
+  }
+  S->beta = cmul(cdiv(rho1, rho), cdiv(al, om));
+  S->rr = rho1;
+}
+
+// after pass U: alpha of the next iteration; end of the last update; or the
+// decision of an FP64 residual round
+__global__ __launch_bounds__(kNT) void k_bcg_scalars_u(Eng e) {
+  __shared__ double red[4 * 4];
+  Slot* S = &e.slots[blockIdx.x];
+  const int status = ldc(&S->status);
+  if (status == kInnerLast) {
+    if (threadIdx.x == 0) S->status = kInnerDone;
+    return;
+  }
+  const bool outer = (status == kOuterPending || status == kInnerDone);
+  if (status != kInner && !outer) return;
+  double tot[4];
+  if (!slot_sums<4>(e, S, tot, red)) return;
+  const double2 hv = make_double2(tot[0], tot[1]);
+  S->parity = ldc(&S->parity) ^ 1;
+  double2 rho = ldc(&S->rr);
+  if (outer) {
+    const double rn2 = tot[2];
+    const int rounds0 = ldc(&S->rounds);
+    double bn2 = ldc(&S->bn2);
+    if (rounds0 == 0) {
+      bn2 = rn2;
+      S->bn2 = rn2;
+    }
+    const int rounds = rounds0 + 1;
+    S->rounds = rounds;
+    const double prev = ldc(&S->prev_rn2);
+    const double tol2 = ldc(&S->tol2);
+    S->rn2 = rn2;
+    S->prev_rn2 = rn2;
+    if (!isfinite(rn2)) {
+      S->status = kFailBreakdown;
+      return;
+    }
+    if (rn2 <= tol2 * bn2) {
+      S->status = kDone;
+      return;
+    }
+    if (rounds >= 3 && rn2 > 0.25 * prev) {
+      // a whole inner solve did not halve the FP64 residual: it sits at its
+      // rounding floor, above the requested tolerance
+      S->status = kDone;
+      S->stagnated = 1;
+      return;
+    }
+    if (ldc(&S->it_total) >= e.max_iter) {
+      S->status = kFailMaxIter;
+      return;
+    }
+    // restart: r_hat = r, rho = <r_hat, r> = |r|^2 of the rounded residual
+    rho = make_double2(tot[3], 0.0);
+    S->rr = rho;
+    S->it_inner = 0;
+    S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
+    S->status = kInner;
+  }
+  if (!finite2(hv) || !nonzero(hv) || !nonzero(rho)) {
+    // breakdown: the iterate is x64 + d as it stands
+    S->status = outer ? kFailBreakdown : kInnerDone;
+    return;
+  }
+  S->alpha = cdiv(rho, hv);
 }
 
 int prep_vh_blocks() { return 256; }
-
-// ---- FP64 residual of the variable-coefficient system -----------------------
-// r64 = sc (eta0 + a1 D + a2 Z) - K x64; r = r_hat = (T) r64, d = 0;
-// partials |r64|^2 (index 0) and |r|^2 of the rounded residual (index 1).
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_outer_residual_vh(Eng e) {
-  using V = typename C2<T>::t;
-  __shared__ double2 XT[kVH * kVW];
-  __shared__ double Hs[kHH * kHW];
-  __shared__ double red[4 * 2];
-  const int total = ldc(&e.tile_start[e.B]);
-  const int un = ldc(&e.work[1]);
-  const int per = (total + 7) >> 3;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
-    Slot* S = &e.slots[it.slot];
-    const int st = ldc(&S->status);
-    if (st != kInnerDone && st != kOuterPending) continue;
-    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
-    const size_t base = size_t(it.slot) * e.cap;
-    const double2* x = e.x64 + base;
-    V* r = reinterpret_cast<V*>(ldc(&S->parity) ? e.r1 : e.r0) + base;
-    V* rh = reinterpret_cast<V*>(e.rh) + base;
-    V* d = reinterpret_cast<V*>(e.d) + base;
-    const double2 zeta = ldc(&S->zeta), a1 = ldc(&S->a1), a2 = ldc(&S->a2);
-    const double2 gamma = ldc(&S->gamma), sc = ldc(&S->sc);
-    const bool zero_x = (ldc(&S->rounds) == 0);
-    const int x0 = (it.tile % I.tiles_x) * kTX, y0 = (it.tile / I.tiles_x) * kTY;
-    const bool big = (I.nx >= kVW) && (I.ny >= kVH);
-    __syncthreads();
-    if (!zero_x) {
-      for (int k = threadIdx.x; k < kVH * kVW; k += kNT) {
-        const int ly = k / kVW, lx = k - ly * kVW;
-        XT[k] = x[size_t(wrapc(y0 - 2 + ly, I.ny, big)) * I.nx + wrapc(x0 - 2 + lx, I.nx, big)];
-      }
-      load_depth<double>(Hs, I.H, x0, y0, I, big);
-    }
-    __syncthreads();
-    double acc[2] = {0.0, 0.0};
-    for (int j = 0; j < kTY / 4; ++j) {
-      const int ly = ty + 4 * j;
-      const int gx = x0 + tx, gy = y0 + ly;
-      if (gx < I.nx && gy < I.ny) {
-        const size_t gi = size_t(gy) * I.nx + gx;
-        double2 bv = make_double2(I.eta0[gi], 0.0);
-        if (I.D0) {
-          const double dv = I.D0[gi], zv = I.Z0[gi];
-          bv.x += a1.x * dv + a2.x * zv;
-          bv.y += a1.y * dv + a2.y * zv;
-        }
-        double2 rv = cmul(sc, bv);
-        if (!zero_x) rv = csub(rv, kop<double2, double>(XT, Hs, ly, tx, I.cx, I.cy, I.cxy, gamma, zeta));
-        const V rt = mk<V>(rv.x, rv.y);
-        r[gi] = rt;
-        rh[gi] = rt;
-        d[gi] = mk<V>(0.0, 0.0);
-        acc[0] += rv.x * rv.x + rv.y * rv.y;
-        acc[1] += double(rt.x) * rt.x + double(rt.y) * rt.y;
-      }
-    }
-    double tot[2];
-    block_sum_n<2>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-      pp[0] = tot[0];
-      pp[1] = tot[1];
-    }
-  }
-}
 
 // ---- input preparation with a depth field ----------------------------------
 // D_H = dx(H u0) + dy(H v0), Z_H = dx(H v0) - dy(H u0); flags: bit0
@@ -463,16 +660,20 @@ void launch_fill_value(double* p, size_t n, double v, hipStream_t s) {
 }
 template <typename T>
 void launch_bcg(const Eng& e, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcg_a<T>, dim3(grid), dim3(kNT), 0, s, e);
-  hipLaunchKernelGGL(k_bcg_sa, dim3(e.B), dim3(kNT), 0, s, e);
-  hipLaunchKernelGGL(k_bcg_b<T>, dim3(grid), dim3(kNT), 0, s, e);
-  hipLaunchKernelGGL(k_bcg_sb, dim3(e.B), dim3(kNT), 0, s, e);
-  hipLaunchKernelGGL(k_bcg_c<T>, dim3(grid), dim3(kNT), 0, s, e);
-  hipLaunchKernelGGL(k_bcg_sc, dim3(e.B), dim3(kNT), 0, s, e);
-}
-template <typename T>
-void launch_outer_residual_vh(const Eng& e, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_residual_vh<T>, dim3(grid), dim3(kNT), 0, s, e);
+  if (sizeof(T) == 4) {
+    hipLaunchKernelGGL(k_bcg_outer_f32, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_u1_f32, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_u2_f32, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_s_f32, dim3(grid), dim3(kNT), 0, s, e);
+  } else {
+    hipLaunchKernelGGL(k_bcg_outer_f64, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_u1_f64, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_u2_f64, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_s_f64, dim3(grid), dim3(kNT), 0, s, e);
+  }
+  hipLaunchKernelGGL(k_bcg_scalars_s, dim3(e.B), dim3(kNT), 0, s, e);
 }
 void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
                     double* hmax_part, hipStream_t s) {
@@ -481,11 +682,11 @@ void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0
 int bcg_occupancy(int mixed) {
   int a = 0, b = 0;
   if (mixed) {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_a<float>, kNT, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_c<float>, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_u1_f32, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_s_f32, kNT, 0);
   } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_a<double>, kNT, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_c<double>, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_u1_f64, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_s_f64, kNT, 0);
   }
   const int m = a < b ? a : b;
   return m > 0 ? m : 1;
@@ -493,7 +694,5 @@ int bcg_occupancy(int mixed) {
 
 template void launch_bcg<float>(const Eng&, int, hipStream_t);
 template void launch_bcg<double>(const Eng&, int, hipStream_t);
-template void launch_outer_residual_vh<float>(const Eng&, int, hipStream_t);
-template void launch_outer_residual_vh<double>(const Eng&, int, hipStream_t);
 
 }  // namespace rexii

@@ -414,6 +414,7 @@ struct Engine {
     e.B = z.B;
     e.S = z.S;
     e.method = z.method;
+    e.d_is_f32 = (prec == REXII_PREC_MIXED) ? 1 : 0;
     e.cap = z.cap;
     e.cap_blk = z.cap_blk;
     e.max_iter = max_iter;
@@ -523,12 +524,6 @@ struct Engine {
   void enqueue_chunk(bool with_events) {
     launch_retire(e, st);
     launch_assign(e, st);
-    launch_outer_update<T>(e, grid, st);
-    if (z.method == 1)
-      launch_outer_residual_vh<T>(e, grid, st);
-    else
-      launch_outer_residual<T>(e, grid, st);
-    launch_outer_scalars(e, st);
     for (int i = 0; i < chunk; ++i) {
       if (with_events) HIPCHK(hipEventRecord(evs[2 * i], st));
       if (z.method == 1) {
@@ -613,18 +608,28 @@ struct Engine {
     fprintf(stderr, "rexii debug: nonuniform=%d fin_mismatch=%d missed_retire=%d nonzero_x0=%d stale_total=%d bad_tile=%d\n",
             dbg[0], dbg[1], dbg[2], dbg[3], dbg[4], dbg[5]);
 #endif
-    // algorithmic bytes of all pass launches: a pass reads d, r, p and writes
-    // them (6 complex values per point); a prime pass reads r and writes r, p
+    // algorithmic bytes of all pass launches (per point of the solve's grid)
     pass_bytes = 0.0;
     for (int j = 0; j < z.S; ++j) {
       const double pts = double(inst_points[solve_inst[j]]);
       if (z.method == 1) {
-        // BiCGStab iteration: A reads r, p, v, r_hat, writes p, v; B reads
-        // r, v; C reads d, r, v, p, r_hat, writes d, r (15 complex values)
-        // plus the FP64 depth field once per pass
-        pass_bytes += pts * stats[j].it_total * (15.0 * double(z.eb) + 3.0 * 8.0);
+        // BiCGStab iteration: pass S reads r, v, r_hat; pass U reads r, v,
+        // p, d, r_hat and writes d, r, p, v (12 complex values), each pass
+        // reads the FP64 depth; an FP64 round reads x64 (16 B), d, eta0 and
+        // the depth (8 B each) and writes r, r_hat, p, v
+        const double eb = double(z.eb);
+        const int R = stats[j].rounds;
+        pass_bytes += pts * (stats[j].it_total * (12.0 * eb + 16.0) + (16.0 + 4.0 * eb) +
+                             std::max(0, R - 1) * (32.0 + 5.0 * eb));
       } else {
-        pass_bytes += pts * double(z.eb) * (6.0 * stats[j].it_total + 3.0 * std::max(0, stats[j].rounds - 1));
+        // COCG: an inner step reads d, r, p and writes them (6 complex
+        // values); an FP64 round reads x64 (16 B), d and eta0 (8 B) and
+        // writes r and p (the first round reads only eta0); the first inner
+        // step of every later round moves d into x64 (32 B instead of a d read)
+        const double eb = double(z.eb);
+        const int R = stats[j].rounds;
+        pass_bytes += pts * (6.0 * eb * stats[j].it_total + (8.0 + 2.0 * eb) +
+                             std::max(0, R - 1) * (24.0 + 3.0 * eb) + std::max(0, R - 2) * (32.0 - eb));
       }
     }
     return 0.0;
@@ -821,7 +826,6 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
   // one engine runs one method: a depth field anywhere puts every problem
   // of the call on the flux-form path
   if (any_depth_field) jb.o.method = 1;
-  std::vector<double> hpart(size_t(prep_vh_blocks()));
   for (size_t i = 0; i < ni; ++i) {
     JobItem& it = jb.items[i];
     if (it.skip) continue;

@@ -93,3 +93,41 @@ def test_varh_rho_and_bad_depth(rx):
     with pytest.raises(rx.RexiiError) as e:
         rx.apply(_dev(f), 0.1, fc=20.0, Hfield=_dev(bad))
     assert e.value.status == -2
+
+
+# ---- 2048 x 2048, t rho = 100: full REXII sum against stored oracle samples
+def _golden_2048():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "varh2048_trho100.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.fixture(scope="module")
+def case2048(rx):
+    g = _golden_2048()
+    D = g["D"]
+    Hf = inputs.variable_depth(D)
+    f = inputs.gaussian_bumps(D, nbumps=g["nbumps"], seed=g["seed"])
+    Hd = _dev(Hf)
+    rho = rx.rho(D, D, fc=g["f_c"], Hfield=Hd)
+    return g, Hf, Hd, f, rho
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("mixed", 1e-6, 1e-6), ("fp64", 1e-10, 1e-10)])
+def test_varh_2048_vs_oracle_samples(rx, case2048, precision, tol, bar):
+    """Full pole sum (P ~ 470) at the real 2048^2 shape; the oracle's
+    Chebyshev-Bessel result is stored at 4096 sampled points."""
+    g, Hf, Hd, f, rho = case2048
+    assert abs(rho - g["rho"]) <= 1e-12 * rho
+    t = g["t_rho"] / rho
+    u, rep = rx.apply(_dev(f), t, fc=g["f_c"], Hfield=Hd, precision=precision, tol=tol)
+    assert rep["not_converged"] == 0
+    idx = np.asarray(g["index"])
+    ref = np.asarray(g["value"])
+    un = u.cpu().numpy()
+    got = un.reshape(-1)[idx]
+    assert np.linalg.norm(got - ref) <= bar * np.linalg.norm(ref)
+    # W-energy of the whole field (the oracle's value is conserved to 1e-14)
+    op = lrsw.LRSW(g["D"], g["D"], fc=g["f_c"], Hfield=Hf)
+    assert abs(varh.w_energy(op, un) / g["w_energy_f"] - 1.0) <= 10 * bar

@@ -10,8 +10,9 @@ timed region.
 
 Prints one JSON line (see the keys at the bottom).  Also reported:
   * the all-FP64 path on the same workload (one untimed-warm run),
-  * roofline of the dominant kernel (inner COCG update), timed with HIP
-    events on the stream it runs on,
+  * roofline of the dominant kernel (k_pass_f32: one COCG step or FP64
+    residual round of every live solve), timed with HIP events on the
+    stream it runs on,
   * the CPU oracle's per-mode REXII on a bounded sample of poles.
 """
 import argparse
@@ -143,7 +144,7 @@ def main():
         "krylov": {"total_iters": reps[0]["total_iters"], "max_iters": reps[0]["max_iters"],
                    "max_refine": reps[0]["max_refine"], "kappa_sum": reps[0]["kappa_sum"],
                    "pole_tol": reps[0]["pole_tol"], "max_rel_residual": reps[0]["max_rel_residual"]},
-        "roofline": {"bound": "hbm", "kernel": "k_pass<float>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_pass_f32", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "avg_launch_ms": k_ms / k_l, "launches": k_l,
                      "alg_bytes_per_launch": k_b / k_l,

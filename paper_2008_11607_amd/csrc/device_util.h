@@ -105,12 +105,14 @@ __device__ __forceinline__ double uni(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 __device__ __forceinline__ double2 uni(double2 v) { return make_double2(uni(v.x), uni(v.y)); }
+__device__ __forceinline__ unsigned long long uni(unsigned long long v) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(v & 0xffffffffull));
+  const unsigned int hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(v >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
 template <typename P>
 __device__ __forceinline__ P* uni(P* v) {
-  const unsigned long long b = reinterpret_cast<unsigned long long>(v);
-  const unsigned int lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(b & 0xffffffffull));
-  const unsigned int hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned int>(b >> 32));
-  return reinterpret_cast<P*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return reinterpret_cast<P*>(uni(reinterpret_cast<unsigned long long>(v)));
 }
 template <typename X>
 __device__ __forceinline__ X ldu(const X* p) { return uni(ldc(p)); }
@@ -258,14 +260,34 @@ __device__ __forceinline__ Item item_of_search(const int* ts, int B, int pos) {
   return it;
 }
 
-// (slot, tile) of position pos: one load from the compact list of working
-// slots when they all have the same tile count, else a binary search.
-__device__ __forceinline__ Item item_of(const Eng& e, int pos, int uniform_nblk) {
-  if (uniform_nblk > 0) {
-    const int k = pos / uniform_nblk;
+constexpr int kWorkIdentity = 1 << 30;
+
+// Head of the work list: item count, common tile count, identity flag (one
+// 8-byte coherent load).
+struct WorkHead {
+  int total, un;
+  bool ident;
+};
+__device__ __forceinline__ WorkHead load_work_head(const Eng& e) {
+  const unsigned long long v = uni(static_cast<unsigned long long>(
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(e.work), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+  WorkHead h;
+  h.total = int(v & 0xffffffffull);
+  const int w1 = int(v >> 32);
+  h.un = w1 & (kWorkIdentity - 1);
+  h.ident = (w1 & kWorkIdentity) != 0;
+  return h;
+}
+
+// (slot, tile) of position pos: when every working slot has the same tile
+// count, the slot follows by one division (and, if every slot works, with no
+// load at all); else a binary search in the tile offsets.
+__device__ __forceinline__ Item item_of(const Eng& e, int pos, const WorkHead& h) {
+  if (h.un > 0) {
+    const int k = pos / h.un;
     Item it;
-    it.slot = ldu(&e.work[2 + k]);
-    it.tile = pos - k * uniform_nblk;
+    it.slot = h.ident ? k : ldu(&e.work[2 + k]);
+    it.tile = pos - k * h.un;
     return it;
   }
   return item_of_search(e.tile_start, e.B, pos);

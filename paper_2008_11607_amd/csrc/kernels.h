@@ -126,8 +126,10 @@ struct Eng {
   SolveStat* stats;      // [S]
   int* next;             // [1] next solve to hand out
   int* tile_start;       // [B + 1] exclusive prefix of tiles of working slots
-  int* work;             // [B + 2]: [0] working slots, [1] their common tile
-                         // count (0 if they differ), [2..] slot indices
+  int* work;             // [B + 2]: [0] work items (tiles of working slots),
+                         // [1] their common tile count (0 if they differ;
+                         // bit 30 set when every slot works, so the list is
+                         // 0, 1, ..., B-1), [2..] working slot indices
   int* counter;          // [4] host-visible counts
   double* part;          // [B][cap_blk][kNDots]
   double2* x64;          // [B][cap]

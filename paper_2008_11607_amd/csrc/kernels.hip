@@ -295,13 +295,13 @@ template <typename T>
 __device__ __forceinline__ void cocg_pass(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[PassLds<T>::kBytes];
   __shared__ double red[4 * kNDots];
-  const int total = ldu(&e.tile_start[e.B]);
-  const int un = ldu(&e.work[1]);
+  const WorkHead h = load_work_head(e);
+  const int total = h.total;
   const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
+    const Item it = item_of(e, pos, h);
     const SlotCtl c = load_ctl(&e.slots[it.slot]);
     double s[kNDots];
 #pragma unroll
@@ -541,8 +541,8 @@ __global__ void k_assign(Eng e) {
     }
   }
   e.tile_start[e.B] = acc;
-  e.work[0] = working;
-  e.work[1] = uniform;
+  e.work[0] = acc;
+  e.work[1] = uniform | ((working == e.B && uniform > 0) ? kWorkIdentity : 0);
   *e.next = next;
   e.counter[0] = working + (next < e.S ? 1 : 0);
   e.counter[1] = next;

@@ -365,13 +365,13 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_s(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
   __shared__ double red[4 * 8];
-  const int total = ldu(&e.tile_start[e.B]);
-  const int un = ldu(&e.work[1]);
+  const WorkHead h = load_work_head(e);
+  const int total = h.total;
   const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
+    const Item it = item_of(e, pos, h);
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kInner) continue;
     double acc[8];
@@ -396,13 +396,13 @@ struct LdsU1 {
 template <typename T>
 __device__ __forceinline__ void bcg_pass_u1(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
-  const int total = ldu(&e.tile_start[e.B]);
-  const int un = ldu(&e.work[1]);
+  const WorkHead h = load_work_head(e);
+  const int total = h.total;
   const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
+    const Item it = item_of(e, pos, h);
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status == kInner)
       bcg_u1_inner<T>(e, c, it.slot, it.tile, lds);
@@ -417,13 +417,13 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsU1<T>::kX];
   __shared__ double red[4 * 2];
-  const int total = ldu(&e.tile_start[e.B]);
-  const int un = ldu(&e.work[1]);
+  const WorkHead h = load_work_head(e);
+  const int total = h.total;
   const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
+    const Item it = item_of(e, pos, h);
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};
@@ -442,13 +442,13 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
   __shared__ double red[4 * 2];
-  const int total = ldu(&e.tile_start[e.B]);
-  const int un = ldu(&e.work[1]);
+  const WorkHead h = load_work_head(e);
+  const int total = h.total;
   const int per = (total + 7) >> 3;
   for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
-    const Item it = item_of(e, pos, un);
+    const Item it = item_of(e, pos, h);
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kInner && c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};

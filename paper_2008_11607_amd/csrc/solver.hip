@@ -1105,6 +1105,8 @@ static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts
       ar.reserve_own(need + 4096);
     } else if (ws_bytes < need) {
       return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_workspace_size()");
+    } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
+      return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     }
     run_job(jb, ar);
     for (size_t i = 0; i < jb.items.size(); ++i) {
@@ -1180,6 +1182,8 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
       ar.reserve_own(need + 4096);
     } else if (ws_bytes < need) {
       return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_workspace_size()");
+    } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
+      return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     }
     // b' = W^{-1} gbar, W = diag(g, H, H)
     double* bprime = ar.take<double>(3 * n);

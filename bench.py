@@ -43,6 +43,25 @@ def workload():
     return f, rho, TRHO / rho
 
 
+def golden(name):
+    """Stored oracle values (tests/golden, written by the scripts there)."""
+    with open(os.path.join(ROOT, "tests", "golden", name)) as fh:
+        return json.load(fh)
+
+
+def sampled_rel_l2(u, gold):
+    """Relative L2 error of a [3, ny, nx] result over the stored sample points."""
+    idx = np.asarray(gold["index"])
+    ref = np.asarray(gold["value"])
+    got = u.cpu().numpy().reshape(-1)[idx]
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def w_energy(u, H, g=1.0):
+    """g |eta|^2 + H (|u|^2 + |v|^2) summed over the grid (conserved by exp(tA))."""
+    return float(g * np.sum(u[0] ** 2) + np.sum(H * (u[1] ** 2 + u[2] ** 2)))
+
+
 def cpu_baseline(f, t, budget_s=12.0):
     """The oracle's per-mode REXII (one batched 3x3 solve per pole over all
     D^2 Fourier modes, numpy), on the leading poles of the same pole set
@@ -79,6 +98,126 @@ def copy_calibration(nbytes=1 << 30, reps=8):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
+def run_varh2048(args):
+    """2048 x 2048 flux-form variable depth H = 1 + 0.3 sin(2 pi x) cos(2 pi y),
+    g = 1, f_c = 20, rho the guaranteed spectral bound.
+    (a) full REXII sum at t rho = 100 for 8 seeded states (seeds 50..57, 16
+        bumps each) in one batched call, mixed precision; state 50 against
+        the oracle's stored Chebyshev-Bessel samples; plus the same state in
+        FP64;
+    (b) throughput at t rho = 5000 (P ~ 2e4 poles) on a stratified subset of
+        the poles (both poles of n = 0, ..., N in even steps), per-pole
+        tolerance tol / kappa_sum as in the full sum; the full-sum time is
+        extrapolated from it."""
+    import torch
+    from paper_2008_11607_amd import inputs, rexii
+    D, FC = 2048, 20.0
+    gold = golden("varh2048_trho100.json")
+    Hf = inputs.variable_depth(D)
+    Hd = torch.from_numpy(Hf).cuda()
+    rho = rexii.rho(D, D, fc=FC, Hfield=Hd)
+    seeds = list(range(50, 50 + args.rhs))
+    fs = [torch.from_numpy(inputs.gaussian_bumps(D, nbumps=16, seed=sd)).cuda() for sd in seeds]
+    t = 100.0 / rho
+    opts = dict(fc=FC, Hfield=Hd, precision="mixed", tol=1e-6, profile=1, pole_batch=args.slots if args.slots > 0 else 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, reps = rexii.apply_batched(fs, [t] * len(fs), **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    u0 = us[0].cpu().numpy()
+    err = sampled_rel_l2(us[0], gold)
+    wE = w_energy(u0, Hf) / gold["w_energy_f"] - 1.0
+    P = reps[0]["P"]
+    k_l = reps[0]["kernel_launches"]
+    k_ms = reps[0]["kernel_ms"]
+    k_b = reps[0]["kernel_bytes"]
+    out = {"metric": METRIC, "value": len(fs) * D * D * P / el, "unit": "grid-pt·pole solves/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": 1000 * el, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"varh-fd-2048x2048-fc20-trho100-{len(fs)}rhs-batched", "D": D, "t_rho": 100.0,
+                      "f_c": FC, "precision": "mixed (FP32 inner BiCGStab, FP64 residual/refinement/pole sum)",
+                      "tol": 1e-6, "P": P, "rhs": len(fs), "slots": reps[0]["slots"]},
+           "rel_l2_vs_oracle_samples": err, "w_energy_drift": wE,
+           "krylov": {"total_iters": sum(r["total_iters"] for r in reps), "max_iters": max(r["max_iters"] for r in reps),
+                      "not_converged": sum(r["not_converged"] for r in reps), "stagnated": sum(r["stagnated"] for r in reps)},
+           "roofline": {"bound": "hbm", "kernel": "BiCGStab iteration (k_bcg_outer, k_bcg_u1, k_bcg_u2, k_bcg_s + scalars)",
+                        "achieved": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "avg_launch_ms": k_ms / k_l, "launches": k_l, "alg_bytes_per_launch": k_b / k_l,
+                        "kernel_time_share": k_ms * 1e-3 / el}}
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u64, r64 = rexii.apply(fs[0], t, fc=FC, Hfield=Hd, precision="fp64", tol=1e-10)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t1
+        u64n = u64.cpu().numpy()
+        out["fp64"] = {"value": D * D * r64["P"] / e64, "ms": 1000 * e64, "P": r64["P"],
+                       "rel_l2_vs_oracle_samples": sampled_rel_l2(u64, gold),
+                       "mixed_vs_fp64_rel_l2": float(np.linalg.norm(u0 - u64n) / np.linalg.norm(u64n)),
+                       "total_iters": r64["total_iters"]}
+    if args.subset > 0:
+        t5 = 5000.0 / rho
+        beta, alpha, kap = rexii.coeffs(t5, rho, h=0.5, tol=1e-6)
+        z = beta * t5
+        Pf = len(z)
+        ns = np.unique(np.linspace(0, Pf // 2 - 1, args.subset).round().astype(int))
+        ks = np.concatenate([[2 * n, 2 * n + 1] for n in ns])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, rs = rexii.shifted_solve(fs[0], t5, z[ks], fc=FC, Hfield=Hd, precision="mixed", tol=1e-6 / kap,
+                                    profile=1, max_iter=400000)
+        torch.cuda.synchronize()
+        e5 = time.perf_counter() - t2
+        out["trho5000_subset"] = {
+            "poles": int(len(ks)), "of_P": Pf, "seconds": e5, "value": D * D * len(ks) / e5,
+            "extrapolated_full_sum_s": e5 * Pf / len(ks), "total_iters": rs["total_iters"],
+            "max_iters": rs["max_iters"], "not_converged": rs["not_converged"], "stagnated": rs["stagnated"],
+            "iteration_gbs": (rs["kernel_bytes"] / rs["kernel_launches"]) / (rs["kernel_ms"] / rs["kernel_launches"] * 1e-3) / 1e9}
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """Heterogeneous batch: 16 states (seeds 300..315) on grids drawn from
+    {128, 256, 512}^2 and t rho from U[50, 500] (a reduced form of 64 states on
+    up to 1024^2 with t rho up to 2000), mixed precision; one batched call
+    against one call per state (the oracle parity of batched calls is in the
+    tests)."""
+    import torch
+    from paper_2008_11607_amd import inputs, rexii
+    spec = inputs.batched_instances(count=args.rhs if args.rhs > 8 else 16, seed0=300, sizes=(128, 256, 512),
+                                    trho_range=(50.0, 500.0))
+    fs, ts, sizes = [], [], []
+    for s_ in spec:
+        f = inputs.gaussian_bumps(s_["D"], nbumps=16, seed=s_["seed"])
+        fs.append(torch.from_numpy(f).cuda())
+        ts.append(s_["trho"] / rexii.rho(s_["D"], s_["D"], fc=FC))
+        sizes.append(s_["D"])
+    opts = dict(fc=FC, precision="mixed", tol=1e-6)
+    rexii.apply_batched(fs[:2], ts[:2], **opts)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, reps = rexii.apply_batched(fs, ts, **opts)
+    torch.cuda.synchronize()
+    eb = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    plain = [rexii.apply(f, t, **opts)[0] for f, t in zip(fs, ts)]
+    torch.cuda.synchronize()
+    ep = time.perf_counter() - t1
+    work = sum(n * n * r["P"] for n, r in zip(sizes, reps))
+    diffs = [float(torch.linalg.norm(u - v) / torch.linalg.norm(v)) for u, v in zip(us, plain)]
+    print(json.dumps({"metric": METRIC, "value": work / eb, "unit": "grid-pt·pole solves/s", "n_gpus": 1, "steps": 1,
+                      "warmup": 1, "ms_per_step": 1000 * eb, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+                      "config": {"workload": f"lrsw-fd-batched-{len(fs)}-mixed-grids-128-512-trho50-500",
+                                 "states": len(fs), "grids": sorted(set(sizes)),
+                                 "precision": "mixed", "tol": 1e-6},
+                      "plain_calls_value": work / ep, "speedup_vs_plain_calls": ep / eb,
+                      "max_rel_l2_batched_vs_plain": max(diffs),
+                      "not_converged": sum(r["not_converged"] for r in reps)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +227,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--slots", type=int, default=-1,
                     help="concurrent solves; -1 (default) autotunes on the first call and caches the choice")
+    ap.add_argument("--workload", default="lrsw512", choices=["lrsw512", "varh2048", "batched"],
+                    help="lrsw512 (default): the headline line; varh2048: 2048^2 variable depth; "
+                         "batched: heterogeneous batch against plain calls")
+    ap.add_argument("--rhs", type=int, default=8, help="states of the varh2048 / batched workloads")
+    ap.add_argument("--subset", type=int, default=16,
+                    help="varh2048: values of n in the t rho = 5000 pole subset (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 8 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -99,10 +244,15 @@ def main():
               "form is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "varh2048":
+        run_varh2048(args)
+        return
+    if args.workload == "batched":
+        run_batched(args)
+        return
+
     import torch
     from paper_2008_11607_amd import rexii
-    from oracle import expm_modes as em
-    from oracle import lrsw
 
     f, rho, t = workload()
     fd = torch.from_numpy(f).cuda()
@@ -122,9 +272,9 @@ def main():
     P = reps[0]["P"]
     value = D * D * P / (el / args.steps)
 
-    op = lrsw.LRSW(D, D, fc=FC)
-    ref = em.expm_closed_real(op, f, t)
-    err = em.rel_l2(u.cpu().numpy(), ref)
+    gold = golden("lrsw512_trho1000.json")
+    assert abs(gold["t"] - t) <= 1e-12 * t, "workload differs from the stored oracle values"
+    err = sampled_rel_l2(u, gold)
 
     k_l = sum(r["kernel_launches"] for r in reps)
     k_ms = sum(r["kernel_ms"] for r in reps)
@@ -157,7 +307,7 @@ def main():
         torch.cuda.synchronize()
         e64 = time.perf_counter() - t1
         out["fp64"] = {"value": D * D * r64["P"] / e64, "ms": 1000 * e64, "P": r64["P"],
-                       "rel_l2_vs_oracle": em.rel_l2(u64.cpu().numpy(), ref),
+                       "rel_l2_vs_oracle": sampled_rel_l2(u64, gold),
                        "total_iters": r64["total_iters"], "max_iters": r64["max_iters"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, t)

@@ -245,21 +245,6 @@ struct Item {
   int slot, tile;
 };
 
-// Position pos in [0, total) -> (slot, tile) by binary search in the
-// exclusive prefix sums ts[0..B].
-__device__ __forceinline__ Item item_of_search(const int* ts, int B, int pos) {
-  int lo = 0, hi = B;  // ts[lo] <= pos < ts[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (ldc(&ts[mid]) <= pos) lo = mid;
-    else hi = mid;
-  }
-  Item it;
-  it.slot = lo;
-  it.tile = pos - ldc(&ts[lo]);
-  return it;
-}
-
 constexpr int kWorkIdentity = 1 << 30;
 
 // Head of the work list: item count, common tile count, identity flag (one
@@ -281,16 +266,20 @@ __device__ __forceinline__ WorkHead load_work_head(const Eng& e) {
 
 // (slot, tile) of position pos: when every working slot has the same tile
 // count, the slot follows by one division (and, if every slot works, with no
-// load at all); else a binary search in the tile offsets.
+// load at all); else one load from the position table.
 __device__ __forceinline__ Item item_of(const Eng& e, int pos, const WorkHead& h) {
+  Item it;
   if (h.un > 0) {
     const int k = pos / h.un;
-    Item it;
     it.slot = h.ident ? k : ldu(&e.work[2 + k]);
     it.tile = pos - k * h.un;
     return it;
   }
-  return item_of_search(e.tile_start, e.B, pos);
+  const unsigned long long v = uni(static_cast<unsigned long long>(__hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(e.items + pos), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+  it.slot = int(v & 0xffffffffull);
+  it.tile = int(v >> 32);
+  return it;
 }
 
 // XCD-major numbering: loop index w (block b handles w = b, b + G, ...)

@@ -131,6 +131,8 @@ struct Eng {
                          // bit 30 set when every slot works, so the list is
                          // 0, 1, ..., B-1), [2..] working slot indices
   int* counter;          // [4] host-visible counts
+  int2* items;           // [B * cap_blk] (slot, tile) of each work position
+                         // (filled when the working slots' tile counts differ)
   double* part;          // [B][cap_blk][kNDots]
   double2* x64;          // [B][cap]
   void* d;               // [B][cap] T2

@@ -465,10 +465,26 @@ __global__ void k_retire(Eng e) {
   }
 }
 
-// One thread: record finished solves, hand out the next ones in queue order,
-// rebuild the tile table of working slots and the host-visible counts.
-__global__ void k_assign(Eng e) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__device__ void assign_serial(Eng& e, int* working_out, int* uniform_out);
+
+// Thread 0: record finished solves, hand out the next ones in queue order,
+// rebuild the tile table of working slots and the host-visible counts.  Then
+// the whole block writes the (slot, tile) table of the work positions when
+// the working slots' tile counts differ.
+__global__ __launch_bounds__(256) void k_assign(Eng e) {
+  __shared__ int sh_working, sh_uniform;
+  if (threadIdx.x == 0) assign_serial(e, &sh_working, &sh_uniform);
+  __syncthreads();
+  if (sh_uniform > 0) return;
+  for (int k = 0; k < sh_working; ++k) {
+    const int s = e.work[2 + k];
+    const int start = e.tile_start[s];
+    const int nb = e.slots[s].nblk;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) e.items[start + t] = make_int2(s, t);
+  }
+}
+
+__device__ void assign_serial(Eng& e, int* working_out, int* uniform_out) {
   int next = ldc(e.next);
   int working = 0;
   int acc = 0;
@@ -546,6 +562,8 @@ __global__ void k_assign(Eng e) {
   *e.next = next;
   e.counter[0] = working + (next < e.S ? 1 : 0);
   e.counter[1] = next;
+  *working_out = working;
+  *uniform_out = uniform;
 }
 
 // Count of slots that finished during the chunk (read by the next retire).
@@ -748,7 +766,7 @@ void launch_retire(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(256), 0, s, e);
 }
 void launch_assign(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_assign, dim3(1), dim3(64), 0, s, e);
+  hipLaunchKernelGGL(k_assign, dim3(1), dim3(256), 0, s, e);
 }
 void launch_count_finished(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_count_finished, dim3(1), dim3(64), 0, s, e);

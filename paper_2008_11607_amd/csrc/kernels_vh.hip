@@ -279,17 +279,35 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   const double* Z0 = ldu_ptr(&S->Z0);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  __syncthreads();  // LDS of the previous work item is free
+  // every load of the work item in one round: x = x64 + d (halo 2), the
+  // depth (halo 1) and the right-hand side fields (interior)
+  TileRegs<double2, kBH, kBW> xr;
+  TileRegs<double, kHH, kHW> hr;
   if (!zero_x) {
-    stage_tile<double2, kBH, kBW, 2>(XT, [&](int ly, int lx) {
+    xr.fetch([&](int ly, int lx) {
       const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
       const V dv = d[g];
       const double2 xv = x64[g];
       return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
     });
-    stage_tile<double, kHH, kHW, 1>(Hs, [&](int ly, int lx) {
+    hr.fetch([&](int ly, int lx) {
       return c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)];
     });
+  }
+  double bre[kTY / 4], bdz[kTY / 4], bzz[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const size_t g = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
+    bre[j] = eta0[g];
+    if (D0) {
+      bdz[j] = D0[g];
+      bzz[j] = Z0[g];
+    }
+  }
+  __syncthreads();  // LDS of the previous work item is free
+  if (!zero_x) {
+    xr.store(XT);
+    hr.store(Hs);
   }
   __syncthreads();
 #pragma unroll
@@ -298,11 +316,10 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
     const int gx = x0 + tx, gy = y0 + ly;
     if (gx < nx && gy < ny) {
       const size_t g = size_t(gy) * nx + gx;
-      double2 bv = make_double2(eta0[g], 0.0);
+      double2 bv = make_double2(bre[j], 0.0);
       if (D0) {
-        const double dz = D0[g], zz = Z0[g];
-        bv.x += a1.x * dz + a2.x * zz;
-        bv.y += a1.y * dz + a2.y * zz;
+        bv.x += a1.x * bdz[j] + a2.x * bzz[j];
+        bv.y += a1.y * bdz[j] + a2.y * bzz[j];
       }
       double2 rv = cmul(sc, bv);
       if (!zero_x) rv = csub(rv, kop<kBW, kHW, -1>(XT, Hs, ly + 2, tx + 2, c.cx, c.cy, c.cxy, c.gamma, c.zeta));

@@ -308,10 +308,13 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
 
 // Slots for a set of problems: enough tiles to fill the chip several times
 // over, within a memory budget, never more than the number of solves.
-static int choose_slots(int requested, size_t max_points, int max_nblk, size_t nsolves, int precision, int nvec) {
+// Slots: by default enough for about 16384 work items (tiles) per pass,
+// counted with the solve-weighted mean tile count when problems differ in
+// size; at most a 24 GiB engine.
+static int choose_slots(int requested, size_t max_points, double mean_nblk, size_t nsolves, int precision, int nvec) {
   int B = requested;
   if (B <= 0) {
-    B = (16384 + max_nblk - 1) / max_nblk;
+    B = int(std::ceil(16384.0 / std::max(1.0, mean_nblk)));
     B = std::max(8, std::min(B, 1024));
   }
   const size_t per_slot = max_points * (16 + nvec * inner_elem_bytes(precision));
@@ -343,18 +346,22 @@ struct EngineSize {
 static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_B, int precision) {
   EngineSize z;
   size_t maxp = 0;
+  double wsum = 0.0;
   for (Problem* p : probs) {
     maxp = std::max(maxp, p->n());
-    z.cap_blk = std::max(z.cap_blk, make_geo(p->pl.nx, p->pl.ny).nblk);
+    const int nb = make_geo(p->pl.nx, p->pl.ny).nblk;
+    z.cap_blk = std::max(z.cap_blk, nb);
     z.S += int(p->pl.solves.size());
+    wsum += double(nb) * double(p->pl.solves.size());
   }
+  const double mean_nblk = z.S > 0 ? wsum / z.S : double(std::max(1, z.cap_blk));
   z.cap = int(maxp);
   z.ninst = int(probs.size());
   z.eb = inner_elem_bytes(precision);
   z.method = 0;
   for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
   z.nvec = z.method ? 8 : 5;
-  z.B = choose_slots(requested_B, maxp, z.cap_blk, size_t(z.S), precision, z.nvec);
+  z.B = choose_slots(requested_B, maxp, mean_nblk, size_t(z.S), precision, z.nvec);
   return z;
 }
 
@@ -366,6 +373,7 @@ static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
   b += al256(z.S * sizeof(SolveDev)) + al256(z.S * sizeof(SolveStat));
   b += al256(sizeof(int)) + al256((z.B + 1) * sizeof(int)) + al256((z.B + 2) * sizeof(int)) + al256(4 * sizeof(int));
   b += al256(size_t(z.B) * z.cap_blk * kNDots * sizeof(double));
+  b += al256(size_t(z.B) * z.cap_blk * sizeof(int2));
   b += al256(size_t(z.B) * z.cap * 16);
   b += size_t(z.nvec) * al256(size_t(z.B) * z.cap * z.eb);
   if (keep_solutions) b += al256(size_t(z.S) * z.cap * 16);
@@ -429,6 +437,7 @@ struct Engine {
     e.tile_start = ar.take<int>(z.B + 1);
     e.work = ar.take<int>(z.B + 2);
     e.counter = ar.take<int>(4);
+    e.items = ar.take<int2>(size_t(z.B) * z.cap_blk);
     e.part = ar.take<double>(size_t(z.B) * z.cap_blk * kNDots);
     e.x64 = ar.take<double2>(size_t(z.B) * z.cap);
     e.d = ar.take<char>(size_t(z.B) * z.cap * z.eb);

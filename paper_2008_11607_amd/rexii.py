@@ -142,6 +142,8 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
 def make_op(nx, ny, g=1.0, fc=10.0, H=1.0, Hfield=None):
     op = SweOp()
     op.nx, op.ny, op.g, op.f_cor, op.H0 = int(nx), int(ny), float(g), float(fc), float(H)
+    if Hfield is not None:
+        _dev_f64(Hfield, (int(ny), int(nx)))
     op.H_field = None if Hfield is None else ctypes.c_void_p(Hfield.data_ptr())
     return op
 
@@ -254,10 +256,11 @@ def apply_adjoint(f, gbar, t, g=1.0, fc=10.0, H=1.0, want_dJdf=True, want_dJdH=T
     return dJdf, (dJdH.value if want_dJdH else None), rep.as_dict()
 
 
-def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, **opts):
+def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
     """u_i = exp(t_i A_i) f_i for a list of states (grids may differ) in one
-    call: all problems' solves share one slot scheduler.  g, fc, H may be
-    scalars or per-problem lists.  Returns (list of u, list of reports)."""
+    call: all problems' solves share one slot scheduler.  g, fc, H and Hfield
+    (depth fields, CUDA float64 [ny, nx]) may be scalars / one tensor or
+    per-problem lists.  Returns (list of u, list of reports)."""
     import torch
     lib = load()
     cnt = len(fs)
@@ -268,7 +271,7 @@ def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, **opts):
     ops = (SweOp * cnt)()
     us = [torch.empty_like(_dev_f64(f)) for f in fs]
     for i, f in enumerate(fs):
-        ops[i] = make_op(f.shape[2], f.shape[1], per(g, i), per(fc, i), per(H, i), None)
+        ops[i] = make_op(f.shape[2], f.shape[1], per(g, i), per(fc, i), per(H, i), per(Hfield, i))
     fptr = (ctypes.c_void_p * cnt)(*[ctypes.c_void_p(f.data_ptr()) for f in fs])
     uptr = (ctypes.c_void_p * cnt)(*[ctypes.c_void_p(u.data_ptr()) for u in us])
     tarr = (ctypes.c_double * cnt)(*[float(t) for t in ts])

@@ -181,6 +181,49 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh, double (
   }
 }
 
+// Wavefront sum by DPP lane moves (no LDS): adjacent lanes, pairs of lanes,
+// rotations by 4 and 8 within each row of 16, then the row totals are
+// carried across rows; the total ends in lane 63.  Fixed order, so the
+// result is reproducible.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double wave_total63(double v) {
+  v += dpp_f64<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x124, 0xf>(v);  // row_ror 4
+  v += dpp_f64<0x128, 0xf>(v);  // row_ror 8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3
+  return v;
+}
+
+// Block sums of v[0..N) (DPP within each wavefront, then the four wavefront
+// totals in fixed order through LDS) stored by thread 0 at dst[OFF..OFF+N).
+template <int N, int OFF = 0>
+__device__ __forceinline__ void store_block_sums(double (&v)[N], double* red, double* dst) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_total63(v[k]);
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[(threadIdx.x >> 6) * N + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[OFF + k] = (red[k] + red[N + k]) + (red[2 * N + k] + red[3 * N + k]);
+  }
+}
+
+// partial sums of work item (slot, tile): [slot][tile][kNDots]
+__device__ __forceinline__ double* item_part(const Eng& e, int slot, int tile) {
+  return e.part + (size_t(slot) * e.cap_blk + tile) * kNDots;
+}
+
 // ---------------------------------------------------------------------------
 // LDS tile staging.  fetch() issues all of a thread's global loads of a tile
 // (element k of the TH x TW tile comes from f(k / TW, k % TW)) before any

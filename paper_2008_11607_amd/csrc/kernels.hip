@@ -175,7 +175,8 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
     }
   }
   TileRegs<V, kPH, kPW> pt;
-  pt.fetch([&](int ly, int lx) { return ps[size_t(wrapc(y0 - 4 + ly, ny, big)) * nx + wrapc(x0 - 4 + lx, nx, big)]; });
+  pt.fetch([&](int ly, int lx) {
+    const unsigned g = unsigned(wrapc(y0 - 4 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 4 + lx, nx, big)); return ps[g]; });
   __syncthreads();  // LDS of the previous work item is free
   pt.store(PT);
   __syncthreads();
@@ -313,13 +314,7 @@ __device__ __forceinline__ void cocg_pass(const Eng& e) {
     } else {
       continue;
     }
-    double tot[kNDots];
-    block_sum_n<kNDots>(s, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-#pragma unroll
-      for (int k = 0; k < kNDots; ++k) pp[k] = tot[k];
-    }
+    store_block_sums<kNDots>(s, red, item_part(e, it.slot, it.tile));
   }
 }
 

@@ -121,12 +121,13 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const bool big = (nx >= kSW) && (ny >= kSH);
   TileRegs<V, kBH, kBW> sr;
   sr.fetch([&](int ly, int lx) {
-    const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
     return csub(rs[g], cmul(alpha, vs[g]));
   });
   TileRegs<T, kHH, kHW> hr;
   hr.fetch([&](int ly, int lx) {
-    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+    return T(c.H[g]);
   });
   V hv[kTY / 4];
 #pragma unroll
@@ -179,12 +180,13 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const bool big = (nx >= kSW) && (ny >= kSH);
   TileRegs<V, kBH, kBW> sr;
   sr.fetch([&](int ly, int lx) {
-    const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
     return csub(rs[g], cmul(alpha, vs[g]));
   });
   TileRegs<T, kHH, kHW> hr;
   hr.fetch([&](int ly, int lx) {
-    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+    return T(c.H[g]);
   });
   size_t gi[kTY / 4];
   V pv[kTY / 4], vv[kTY / 4], dv[kTY / 4];
@@ -285,13 +287,14 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   TileRegs<double, kHH, kHW> hr;
   if (!zero_x) {
     xr.fetch([&](int ly, int lx) {
-      const size_t g = size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big);
+    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
       const V dv = d[g];
       const double2 xv = x64[g];
       return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
     });
     hr.fetch([&](int ly, int lx) {
-      return c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)];
+    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+      return c.H[g];
     });
   }
   double bre[kTY / 4], bdz[kTY / 4], bzz[kTY / 4];
@@ -353,11 +356,13 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   const bool big = (nx >= kSW) && (ny >= kSH);
   TileRegs<V, kBH, kBW> pr;
   pr.fetch([&](int ly, int lx) {
-    return pn[size_t(wrapc(y0 - 2 + ly, ny, big)) * nx + wrapc(x0 - 2 + lx, nx, big)];
+    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
+    return pn[g];
   });
   TileRegs<T, kHH, kHW> hr;
   hr.fetch([&](int ly, int lx) {
-    return T(c.H[size_t(wrapc(y0 - 1 + ly, ny, big)) * nx + wrapc(x0 - 1 + lx, nx, big)]);
+    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+    return T(c.H[g]);
   });
   V hv[kTY / 4];
 #pragma unroll
@@ -395,13 +400,7 @@ __device__ __forceinline__ void bcg_pass_s(const Eng& e) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     bcg_s<T>(e, c, it.slot, it.tile, lds, acc);
-    double tot[8];
-    block_sum_n<8>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) pp[k] = tot[k];
-    }
+    store_block_sums<8>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 
@@ -445,13 +444,7 @@ __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
     if (c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};
     bcg_u1_outer<T>(e, c, it.slot, it.tile, lds, acc);
-    double tot[2];
-    block_sum_n<2>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-      pp[2] = tot[0];
-      pp[3] = tot[1];
-    }
+    store_block_sums<2, 2>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 
@@ -470,13 +463,7 @@ __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
     if (c.status != kInner && c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};
     bcg_u2<T>(e, c, it.slot, it.tile, lds, acc);
-    double tot[2];
-    block_sum_n<2>(acc, red, tot);
-    if (threadIdx.x == 0) {
-      double* pp = e.part + (size_t(it.slot) * e.cap_blk + it.tile) * kNDots;
-      pp[0] = tot[0];
-      pp[1] = tot[1];
-    }
+    store_block_sums<2>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 

@@ -202,15 +202,30 @@ __device__ __forceinline__ double wave_total63(double v) {
   return v;
 }
 
-// Block sums of v[0..N) (DPP within each wavefront, then the four wavefront
-// totals in fixed order through LDS) stored by thread 0 at dst[OFF..OFF+N).
-template <int N, int OFF = 0>
-__device__ __forceinline__ void store_block_sums(double (&v)[N], double* red, double* dst) {
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_total63(float v) {
+  v += dpp_f32<0xb1, 0xf>(v);
+  v += dpp_f32<0x4e, 0xf>(v);
+  v += dpp_f32<0x124, 0xf>(v);
+  v += dpp_f32<0x128, 0xf>(v);
+  v += dpp_f32<0x142, 0xa>(v);
+  v += dpp_f32<0x143, 0xc>(v);
+  return v;
+}
+
+// Block sums of v[0..N) (DPP within each wavefront in the type of v, then
+// the four wavefront totals in FP64, in fixed order, through LDS) stored by
+// thread 0 at dst[OFF..OFF+N).
+template <int N, int OFF = 0, typename A>
+__device__ __forceinline__ void store_block_sums(A (&v)[N], double* red, double* dst) {
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] = wave_total63(v[k]);
   if ((threadIdx.x & 63) == 63) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) red[(threadIdx.x >> 6) * N + k] = v[k];
+    for (int k = 0; k < N; ++k) red[(threadIdx.x >> 6) * N + k] = double(v[k]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {

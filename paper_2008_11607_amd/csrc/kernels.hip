@@ -114,6 +114,21 @@ struct PassLds {
   static constexpr size_t kBytes = kInner > kOuter ? kInner : kOuter;
 };
 
+// Partial sums of one thread's points in the inner precision T (FP32: the
+// products and the four-point sums; the block and slot sums are FP64).
+template <typename T, typename V>
+__device__ __forceinline__ void cocg_dots_t(T (&s)[kNDots], V p, V r, V q) {
+  s[0] += p.x * q.x - p.y * q.y;
+  s[1] += p.x * q.y + p.y * q.x;
+  s[2] += q.x * r.x - q.y * r.y;
+  s[3] += q.x * r.y + q.y * r.x;
+  s[4] += q.x * q.x - q.y * q.y;
+  s[5] += T(2) * q.x * q.y;
+  s[6] += r.x * r.x - r.y * r.y;
+  s[7] += T(2) * r.x * r.y;
+  s[8] += r.x * r.x + r.y * r.y;
+}
+
 // the nine partial sums of one tile, accumulated in FP64
 template <typename V>
 __device__ __forceinline__ void cocg_dots(double (&s)[kNDots], V p, V r, V q) {
@@ -130,7 +145,7 @@ __device__ __forceinline__ void cocg_dots(double (&s)[kNDots], V p, V r, V q) {
 
 template <typename T>
 __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
-                                           double (&s)[kNDots]) {
+                                           T (&a)[kNDots]) {
   using V = typename C2<T>::t;
   V* PN = reinterpret_cast<V*>(lds);
   V* PT = reinterpret_cast<V*>(lds + PassLds<T>::kN);
@@ -215,14 +230,14 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
     PN[ly * kNW + lx] = cadd(csub(rr_[m], cmul(alpha, q)), cmul(beta, pc));
   }
   __syncthreads();
-  // dot products accumulated in FP64 (the beta recurrence cancels)
+  // sums over the thread's four points (and over the wavefront) in T;
+  // the block and slot sums are FP64
 #pragma unroll
   for (int j = 0; j < kTY / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V qv = helm<V, T, kNW>(PN, ly + 2, tx + 2, cx, cy, zeta);
-      cocg_dots(s, pn[j], rn[j], qv);
-      s[8] += double(rn[j].x) * rn[j].x + double(rn[j].y) * rn[j].y;
+      cocg_dots_t(a, pn[j], rn[j], qv);
     }
   }
 }
@@ -304,17 +319,19 @@ __device__ __forceinline__ void cocg_pass(const Eng& e) {
     if (pos >= total) continue;
     const Item it = item_of(e, pos, h);
     const SlotCtl c = load_ctl(&e.slots[it.slot]);
-    double s[kNDots];
-#pragma unroll
-    for (int k = 0; k < kNDots; ++k) s[k] = 0.0;
     if (c.status == kInner) {
-      cocg_inner<T>(e, c, it.slot, it.tile, lds, s);
+      T a[kNDots];
+#pragma unroll
+      for (int k = 0; k < kNDots; ++k) a[k] = T(0);
+      cocg_inner<T>(e, c, it.slot, it.tile, lds, a);
+      store_block_sums<kNDots>(a, red, item_part(e, it.slot, it.tile));
     } else if (c.status == kOuterPending || c.status == kInnerDone) {
+      double s[kNDots];
+#pragma unroll
+      for (int k = 0; k < kNDots; ++k) s[k] = 0.0;
       cocg_outer<T>(e, c, it.slot, it.tile, lds, s);
-    } else {
-      continue;
+      store_block_sums<kNDots>(s, red, item_part(e, it.slot, it.tile));
     }
-    store_block_sums<kNDots>(s, red, item_part(e, it.slot, it.tile));
   }
 }
 

@@ -43,6 +43,24 @@ def workload():
     return f, rho, TRHO / rho
 
 
+# HBM bytes per launch of k_pass_f32 on this workload (128 slots), from two
+# rocprofv3 counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scales
+# from a 1 GiB copy); valid only for the kernel sources they were taken on.
+TRAFFIC = {"bytes_per_launch": 1518084147.7, "fetch_kib": 371859.84, "write_kib": 738802.37,
+           "sources_sha256": "f614266ab2a9fb078bcbb66d1d18aa0225876e253ca1bcf41d81938a54e59e63"}
+KERNEL_SOURCES = ["kernels.hip", "kernels.h", "device_util.h"]
+
+
+def traffic_if_current():
+    """The counter-based traffic when the pass kernel's sources are unchanged, else None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2008_11607_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC["bytes_per_launch"] if h.hexdigest() == TRAFFIC["sources_sha256"] else None
+
+
 def golden(name):
     """Stored oracle values (tests/golden, written by the scripts there)."""
     with open(os.path.join(ROOT, "tests", "golden", name)) as fh:
@@ -296,7 +314,7 @@ def main():
                    "pole_tol": reps[0]["pole_tol"], "max_rel_residual": reps[0]["max_rel_residual"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass_f32", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": k_ms / k_l, "launches": k_l,
+                     "traffic": traffic_if_current(), "avg_launch_ms": k_ms / k_l, "launches": k_l,
                      "alg_bytes_per_launch": k_b / k_l,
                      "kernel_time_share": k_ms * 1e-3 / el},
     }

@@ -59,24 +59,7 @@ __device__ __forceinline__ V helm(const V* t, int y, int x, S cx, S cy, V zeta) 
 // ---------------------------------------------------------------------------
 constexpr int kPW = kTX + 8, kPH = kTY + 8;   // tile with halo 4
 constexpr int kNW = kTX + 4, kNH = kTY + 4;   // tile with halo 2
-constexpr int kRing = kNW * kNH - kTX * kTY;  // halo-2 ring points
 
-__device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
-  // rows 0,1 and kNH-2, kNH-1 (full width), then columns 0,1,kNW-2,kNW-1
-  if (e < 2 * kNW) {
-    y = e / kNW;
-    x = e - y * kNW;
-  } else if (e < 4 * kNW) {
-    e -= 2 * kNW;
-    y = kNH - 2 + e / kNW;
-    x = e - (e / kNW) * kNW;
-  } else {
-    e -= 4 * kNW;
-    y = 2 + (e >> 2);
-    const int c = e & 3;
-    x = (c < 2) ? c : kNW - 4 + c;
-  }
-}
 
 // Control fields of a slot, read in one round of coherent loads.
 struct SlotCtl {
@@ -143,8 +126,28 @@ __device__ __forceinline__ void cocg_dots(double (&s)[kNDots], V p, V r, V q) {
   s[7] += 2.0 * rx * ry;
 }
 
+// Flat tile mapping (element k of a tile to thread k mod 256): used for the
+// FP64 inner precision, where it measured faster than the row mapping below.
+constexpr int kRing = kNW * kNH - kTX * kTY;  // halo-2 ring points
+__device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
+  // rows 0,1 and kNH-2, kNH-1 (full width), then columns 0,1,kNW-2,kNW-1
+  if (e < 2 * kNW) {
+    y = e / kNW;
+    x = e - y * kNW;
+  } else if (e < 4 * kNW) {
+    e -= 2 * kNW;
+    y = kNH - 2 + e / kNW;
+    x = e - (e / kNW) * kNW;
+  } else {
+    e -= 4 * kNW;
+    y = 2 + (e >> 2);
+    const int c = e & 3;
+    x = (c < 2) ? c : kNW - 4 + c;
+  }
+}
+
 template <typename T>
-__device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+__device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
                                            T (&a)[kNDots]) {
   using V = typename C2<T>::t;
   V* PN = reinterpret_cast<V*>(lds);
@@ -242,6 +245,121 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
   }
 }
 
+// Row mapping: used for the FP32 inner precision.
+template <typename T>
+__device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+                                           T (&a)[kNDots]) {
+  using V = typename C2<T>::t;
+  V* PN = reinterpret_cast<V*>(lds);
+  V* PT = reinterpret_cast<V*>(lds + PassLds<T>::kN);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
+  const V* ps = reinterpret_cast<const V*>(c.par ? e.p1 : e.p0) + base;
+  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  V* d = reinterpret_cast<V*>(e.d) + base;
+  double2* x64 = e.x64 + base;
+  const bool first = c.it_inner == 0;        // d restarts this step
+  const bool fold = first && c.rounds >= 2;  // ... after x64 += d
+  const V alpha = mk<V>(c.alpha.x, c.alpha.y);
+  const V beta = mk<V>(c.beta.x, c.beta.y);
+  const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kPW) && (ny >= kPH);
+
+  // Thread (tx, wave w) owns column x0 + tx of rows w, w + 4, w + 8, w + 12;
+  // a row is uniform across a wavefront, so row offsets live in scalar
+  // registers and one column offset serves every load of the thread.
+  const int w = __builtin_amdgcn_readfirstlane(ty);
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
+  auto row_off = [&](int y) { return size_t(wrapc(y, ny, big)) * size_t(nx); };
+  // every global load of the step is issued before the first wait:
+  // r and d (interior), r (halo-2 ring) and p (halo 4) into registers
+  size_t ro[kTY / 4];
+  V rv[kTY / 4], dv[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    ro[j] = row_off(y0 + w + 4 * j);
+    rv[j] = (rs + ro[j])[col];
+    if (!first) dv[j] = nt_load(&(d + ro[j])[col]);
+  }
+  // ring of the halo-2 tile: rows 0, 1, kNH-2, kNH-1 at columns 2..65 (one
+  // per thread: row index w -> 0, 1, kNH-2, kNH-1), and columns 0, 1,
+  // kNW-2, kNW-1 of all kNH rows (threads 0..4 kNH-1)
+  const int rrow = (w < 2) ? w : kNH - 4 + w;
+  const V rtop = (rs + row_off(y0 - 2 + rrow))[col];
+  const bool side = threadIdx.x < 4 * kNH;
+  const int sly = threadIdx.x >> 2, sc = threadIdx.x & 3;
+  const int slx = (sc < 2) ? sc : kNW - 4 + sc;
+  V rside;
+  if (side) rside = rs[row_off(y0 - 2 + sly) + unsigned(wrapc(x0 - 2 + slx, nx, big))];
+  // p with halo 4: rows w + 4m at columns 4..67 of the tile, and the 8 halo
+  // columns of all kPH rows (threads 0..8 kPH-1)
+  V pm[kPH / 4];
+#pragma unroll
+  for (int m = 0; m < kPH / 4; ++m) pm[m] = (ps + row_off(y0 - 4 + w + 4 * m))[col];
+  const bool pside = threadIdx.x < 8 * kPH;
+  const int ply = threadIdx.x >> 3, pc8 = threadIdx.x & 7;
+  const int plx = (pc8 < 4) ? pc8 : kTX + pc8;
+  V pside_v;
+  if (pside) pside_v = ps[row_off(y0 - 4 + ply) + unsigned(wrapc(x0 - 4 + plx, nx, big))];
+  __syncthreads();  // LDS of the previous work item is free
+#pragma unroll
+  for (int m = 0; m < kPH / 4; ++m) PT[(w + 4 * m) * kPW + tx + 4] = pm[m];
+  if (pside) PT[ply * kPW + plx] = pside_v;
+  __syncthreads();
+  // interior: rows w + 4j, column tx
+  V rn[kTY / 4], pn[kTY / 4];
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = w + 4 * j;
+    const bool in = (x0 + tx < nx) && (y0 + ly < ny);
+    const V pc = PT[(ly + 4) * kPW + tx + 4];
+    const V q = helm<V, T, kPW>(PT, ly + 4, tx + 4, cx, cy, zeta);
+    const V r1 = csub(rv[j], cmul(alpha, q));
+    const V p1 = cadd(r1, cmul(beta, pc));
+    if (in) {
+      if (fold) {
+        // once per round: the previous round's correction moves into x64
+        const V dold = (d + ro[j])[col];
+        const double2 xo = (x64 + ro[j])[col];
+        (x64 + ro[j])[col] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
+      }
+      nt_store(first ? cmul(alpha, pc) : cadd(dv[j], cmul(alpha, pc)), &(d + ro[j])[col]);
+      (rd + ro[j])[col] = r1;
+      (pd + ro[j])[col] = p1;
+    }
+    PN[(ly + 2) * kNW + tx + 2] = p1;
+    rn[j] = r1;
+    pn[j] = p1;
+  }
+  // halo ring of p_{i+1}
+  {
+    const V pc = PT[(rrow + 2) * kPW + tx + 4];
+    const V q = helm<V, T, kPW>(PT, rrow + 2, tx + 4, cx, cy, zeta);
+    PN[rrow * kNW + tx + 2] = cadd(csub(rtop, cmul(alpha, q)), cmul(beta, pc));
+  }
+  if (side) {
+    const V pc = PT[(sly + 2) * kPW + slx + 2];
+    const V q = helm<V, T, kPW>(PT, sly + 2, slx + 2, cx, cy, zeta);
+    PN[sly * kNW + slx] = cadd(csub(rside, cmul(alpha, q)), cmul(beta, pc));
+  }
+  __syncthreads();
+  // sums over the thread's four points (and over the wavefront) in T;
+  // the block and slot sums are FP64
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = w + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      const V qv = helm<V, T, kNW>(PN, ly + 2, tx + 2, cx, cy, zeta);
+      cocg_dots_t(a, pn[j], rn[j], qv);
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void cocg_outer(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
                                            double (&s)[kNDots]) {
@@ -323,7 +441,10 @@ __device__ __forceinline__ void cocg_pass(const Eng& e) {
       T a[kNDots];
 #pragma unroll
       for (int k = 0; k < kNDots; ++k) a[k] = T(0);
-      cocg_inner<T>(e, c, it.slot, it.tile, lds, a);
+      if (sizeof(T) == 4)
+        cocg_inner<T>(e, c, it.slot, it.tile, lds, a);
+      else
+        cocg_inner_flat<T>(e, c, it.slot, it.tile, lds, a);
       store_block_sums<kNDots>(a, red, item_part(e, it.slot, it.tile));
     } else if (c.status == kOuterPending || c.status == kInnerDone) {
       double s[kNDots];

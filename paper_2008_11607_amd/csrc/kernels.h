@@ -50,6 +50,7 @@ enum SlotStatus : int {
   kFailMaxIter = 5,   // stopped at max_iter (x64 holds the best iterate)
   kFailBreakdown = 6, // non-finite scalars
   kInnerLast = 7,     // BiCGStab: stop test fired, last update of d pending
+  kPrime = 8,         // COCG: residual taken, first step (p = r) pending
 };
 
 // One problem (an initial state on a grid) of the launch.

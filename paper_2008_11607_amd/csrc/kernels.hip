@@ -44,18 +44,18 @@ __device__ __forceinline__ V helm(const V* t, int y, int x, S cx, S cy, V zeta) 
 // k_pass_scalars then sets alpha_{i+1} = rr_{i+1} / pq_{i+1} and
 // beta_{i+1} = (rr_{i+1} - 2 alpha qr + alpha^2 qq) / rr_{i+1}.
 //
-// Outer step (status kOuterPending or kInnerDone): the FP64 residual round
-// of iterative refinement, folded into the same launch.  With the current
-// iterate x = x64 + d (x = 0 for a fresh solve)
-//   r64 = b - (L - zeta) x   in FP64 on tile + halo 2  (x with halo 4),
-//   r = p = (T) r64,  q = (L - zeta) p  (tile),
-// partial sums of the restarted COCG (as above) and |r64|^2 instead of
-// |r|^2; k_pass_scalars decides convergence and, if the solve goes on, sets
-// alpha and beta of the first inner step.  x64 and d are only read here
-// (other blocks read them as halo); the first inner step of the round then
-// folds d into x64 (x64 += d, point by point) and restarts d = alpha p.  The
-// solution of a finished solve is therefore x64 + d once it has run at least
-// one inner round.
+// Residual step (status kOuterPending or kInnerDone): the FP64 residual
+// round of iterative refinement, folded into the same launch.  With the
+// current iterate x = x64 + d (x = 0 for a fresh solve; x with halo 2)
+//   r64 = b - (L - zeta) x   in FP64 on the tile,   r = p = (T) r64,
+// partial sum |r64|^2; k_pass_scalars decides convergence.  If the solve
+// goes on, a prime step (status kPrime) forms q = (L - zeta) p from r with
+// halo 2 and the sums of the restarted COCG, which give alpha and beta of
+// the first inner step.  x64 and d are only read in a residual step (other
+// blocks read them as halo); the first inner step of the round then folds d
+// into x64 (x64 += d, point by point) and restarts d = alpha p.  The
+// solution of a finished solve is therefore x64 + d once it has run at
+// least one inner round.
 // ---------------------------------------------------------------------------
 constexpr int kPW = kTX + 8, kPH = kTY + 8;   // tile with halo 4
 constexpr int kNW = kTX + 4, kNH = kTY + 4;   // tile with halo 2
@@ -85,15 +85,15 @@ __device__ __forceinline__ SlotCtl load_ctl(const Slot* S) {
   return c;
 }
 
-// LDS of the pass: a T tile with halo 2 (p_{i+1}, or r of the outer step),
-// then either a T tile of p with halo 4 (inner) or an FP64 tile of x with
-// halo 4 (outer).
+// LDS of the pass: a T tile with halo 2 (p_{i+1}, or r in a prime step)
+// and a T tile of p with halo 4 (inner step), or an FP64 tile of x with
+// halo 2 (residual step).
 template <typename T>
 struct PassLds {
   using V = typename C2<T>::t;
   static constexpr size_t kN = sizeof(V) * kNH * kNW;
   static constexpr size_t kInner = kN + sizeof(V) * kPH * kPW;
-  static constexpr size_t kOuter = kN + sizeof(double2) * kPH * kPW;
+  static constexpr size_t kOuter = sizeof(double2) * kNH * kNW;   // residual round
   static constexpr size_t kBytes = kInner > kOuter ? kInner : kOuter;
 };
 
@@ -112,19 +112,6 @@ __device__ __forceinline__ void cocg_dots_t(T (&s)[kNDots], V p, V r, V q) {
   s[8] += r.x * r.x + r.y * r.y;
 }
 
-// the nine partial sums of one tile, accumulated in FP64
-template <typename V>
-__device__ __forceinline__ void cocg_dots(double (&s)[kNDots], V p, V r, V q) {
-  const double px = p.x, py = p.y, rx = r.x, ry = r.y, qx = q.x, qy = q.y;
-  s[0] += px * qx - py * qy;
-  s[1] += px * qy + py * qx;
-  s[2] += qx * rx - qy * ry;
-  s[3] += qx * ry + qy * rx;
-  s[4] += qx * qx - qy * qy;
-  s[5] += 2.0 * qx * qy;
-  s[6] += rx * rx - ry * ry;
-  s[7] += 2.0 * rx * ry;
-}
 
 // Flat tile mapping (element k of a tile to thread k mod 256): used for the
 // FP64 inner precision, where it measured faster than the row mapping below.
@@ -361,20 +348,21 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
 }
 
 template <typename T>
-__device__ __forceinline__ void cocg_outer(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
-                                           double (&s)[kNDots]) {
+__device__ __forceinline__ void cocg_residual(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+                                              double& n2) {
   using V = typename C2<T>::t;
-  V* RN = reinterpret_cast<V*>(lds);
-  double2* XT = reinterpret_cast<double2*>(lds + PassLds<T>::kN);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  double2* XT = reinterpret_cast<double2*>(lds);  // x = x64 + d with halo 2, FP64
+  const int tx = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const double2* x64 = e.x64 + base;
   const V* d = reinterpret_cast<const V*>(e.d) + base;
-  V* rd = reinterpret_cast<V*>(c.par ? e.r0 : e.r1) + base;
-  V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
+  // r and p of the current parity: no other block reads them in this launch
+  V* rc = reinterpret_cast<V*>(c.par ? e.r1 : e.r0) + base;
+  V* pc = reinterpret_cast<V*>(c.par ? e.p1 : e.p0) + base;
   const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
-  // right-hand side b = eta0 + a1 D0 + a2 Z0 (outer steps only)
+  // right-hand side b = eta0 + a1 D0 + a2 Z0
   const Slot* S = &e.slots[slot];
   const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2);
   const double* eta0 = ldu_ptr(&S->eta0);
@@ -382,45 +370,79 @@ __device__ __forceinline__ void cocg_outer(const Eng& e, const SlotCtl& c, int s
   const double* Z0 = ldu_ptr(&S->Z0);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kPW) && (ny >= kPH);
-
-  __syncthreads();  // LDS of the previous work item is free
-  if (!zero_x) stage_tile<double2, kPH, kPW, 2>(XT, [&](int ly, int lx) {
-    const size_t g = size_t(wrapc(y0 - 4 + ly, ny, big)) * nx + wrapc(x0 - 4 + lx, nx, big);
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
+  TileRegs<double2, kNH, kNW> xr;
+  if (!zero_x) xr.fetch([&](int ly, int lx) {
+    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
     const V dv = d[g];
     const double2 xv = x64[g];
     return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
   });
-  __syncthreads();
-  // r64 = b - (L - zeta) x on tile + halo 2; r = p = (T) r64
-  for (int k = threadIdx.x; k < kNH * kNW; k += kNT) {
-    const int ly = k / kNW, lx = k - ly * kNW;
-    const int gy = y0 - 2 + ly, gx = x0 - 2 + lx;
-    const size_t g = size_t(wrapc(gy, ny, big)) * nx + wrapc(gx, nx, big);
-    double2 rv = make_double2(eta0[g], 0.0);
-    if (D0) {
-      const double dv = D0[g], zv = Z0[g];
-      rv.x += a1.x * dv + a2.x * zv;
-      rv.y += a1.y * dv + a2.y * zv;
-    }
-    if (!zero_x) rv = csub(rv, helm<double2, double, kPW>(XT, ly + 2, lx + 2, c.cx, c.cy, c.zeta));
-    const V rt = mk<V>(rv.x, rv.y);
-    RN[k] = rt;
-    const bool interior = ly >= 2 && ly < kTY + 2 && lx >= 2 && lx < kTX + 2 && gx < nx && gy < ny;
-    if (interior) {
-      rd[g] = rt;
-      pd[g] = rt;
-      s[8] += rv.x * rv.x + rv.y * rv.y;
-    }
-  }
-  __syncthreads();
-  const T cx = T(c.cx), cy = T(c.cy);
-  const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+  double bv[kTY / 4], dz[kTY / 4], zz[kTY / 4];
+  size_t ro[kTY / 4];
 #pragma unroll
   for (int j = 0; j < kTY / 4; ++j) {
-    const int ly = ty + 4 * j;
+    ro[j] = size_t(wrapc(y0 + w + 4 * j, ny, big)) * size_t(nx);
+    bv[j] = (eta0 + ro[j])[col];
+    if (D0) {
+      dz[j] = (D0 + ro[j])[col];
+      zz[j] = (Z0 + ro[j])[col];
+    }
+  }
+  __syncthreads();  // LDS of the previous work item is free
+  if (!zero_x) xr.store(XT);
+  __syncthreads();
+  // r64 = b - (L - zeta) x on the tile; r = p = (T) r64
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = w + 4 * j;
+    if (x0 + tx < nx && y0 + ly < ny) {
+      double2 rv = make_double2(bv[j], 0.0);
+      if (D0) {
+        rv.x += a1.x * dz[j] + a2.x * zz[j];
+        rv.y += a1.y * dz[j] + a2.y * zz[j];
+      }
+      if (!zero_x) rv = csub(rv, helm<double2, double, kNW>(XT, ly + 2, tx + 2, c.cx, c.cy, c.zeta));
+      const V rt = mk<V>(rv.x, rv.y);
+      (rc + ro[j])[col] = rt;
+      (pc + ro[j])[col] = rt;
+      n2 += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+}
+
+// First step of an inner solve: p = r (the rounded residual), q = (L - zeta) p
+// on the tile (r with halo 2 from LDS) and the COCG partial sums, in FP64
+// (alpha and beta of the first step set the course of the whole inner solve:
+// FP32 sums here slowed the hardest solves several-fold).
+template <typename T>
+__device__ __forceinline__ void cocg_prime(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
+                                           double (&a)[kNDots]) {
+  using V = typename C2<T>::t;
+  V* RN = reinterpret_cast<V*>(lds);
+  const int tx = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = c.nx, ny = c.ny;
+  const size_t base = size_t(slot) * e.cap;
+  const V* rc = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
+  const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const T cx = T(c.cx), cy = T(c.cy);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const bool big = (nx >= kPW) && (ny >= kPH);
+  TileRegs<V, kNH, kNW> rr;
+  rr.fetch([&](int ly, int lx) {
+    return rc[unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big))];
+  });
+  __syncthreads();  // LDS of the previous work item is free
+  rr.store(RN);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTY / 4; ++j) {
+    const int ly = w + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V rt = RN[(ly + 2) * kNW + tx + 2];
-      cocg_dots(s, rt, rt, helm<V, T, kNW>(RN, ly + 2, tx + 2, cx, cy, zeta));
+      const V q = helm<V, T, kNW>(RN, ly + 2, tx + 2, cx, cy, zeta);
+      cocg_dots_t(a, make_double2(rt.x, rt.y), make_double2(rt.x, rt.y), make_double2(q.x, q.y));
     }
   }
 }
@@ -446,32 +468,36 @@ __device__ __forceinline__ void cocg_pass(const Eng& e) {
       else
         cocg_inner_flat<T>(e, c, it.slot, it.tile, lds, a);
       store_block_sums<kNDots>(a, red, item_part(e, it.slot, it.tile));
-    } else if (c.status == kOuterPending || c.status == kInnerDone) {
-      double s[kNDots];
+    } else if (c.status == kPrime) {
+      double a[kNDots];
 #pragma unroll
-      for (int k = 0; k < kNDots; ++k) s[k] = 0.0;
-      cocg_outer<T>(e, c, it.slot, it.tile, lds, s);
-      store_block_sums<kNDots>(s, red, item_part(e, it.slot, it.tile));
+      for (int k = 0; k < kNDots; ++k) a[k] = 0.0;
+      cocg_prime<T>(e, c, it.slot, it.tile, lds, a);
+      store_block_sums<kNDots>(a, red, item_part(e, it.slot, it.tile));
+    } else if (c.status == kOuterPending || c.status == kInnerDone) {
+      double n2[1] = {0.0};
+      cocg_residual<T>(e, c, it.slot, it.tile, lds, n2[0]);
+      store_block_sums<1, 8>(n2, red, item_part(e, it.slot, it.tile));
     }
   }
 }
 
-// FP32 inner precision at 4 waves per SIMD (<= 128 VGPRs); FP64 as compiled
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_pass_f32(Eng e) {
+// FP32 inner precision at 5 waves per SIMD (<= 96 VGPRs); FP64 as compiled
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5))) void k_pass_f32(Eng e) {
   cocg_pass<float>(e);
 }
 __global__ __launch_bounds__(kNT) void k_pass_f64(Eng e) { cocg_pass<double>(e); }
 
 // One block per slot after each pass: add the partial sums of the slot's
 // tiles in index order.  Inner step: set alpha_{i+1}, beta_{i+1} or end the
-// inner solve.  Outer step: decide done / stagnated / failed, or restart the
-// inner solve with the residual as its right-hand side.
+// inner solve.  Residual step: decide done / stagnated / failed, or go on
+// to a prime step.  Prime step: alpha, beta of the first inner step.
 __global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
   __shared__ double red[4 * kNDots];
   Slot* S = &e.slots[blockIdx.x];
   const int status = ldc(&S->status);
   const bool outer = (status == kOuterPending || status == kInnerDone);
-  if (status != kInner && !outer) return;
+  if (status != kInner && status != kPrime && !outer) return;
   const int nblk = ldc(&S->nblk);
   double v[kNDots], tot[kNDots];
 #pragma unroll
@@ -483,15 +509,7 @@ __global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
   }
   block_sum_n<kNDots>(v, red, tot);
   if (threadIdx.x != 0) return;
-  const double2 pq = make_double2(tot[0], tot[1]);
-  const double2 qr = make_double2(tot[2], tot[3]);
-  const double2 qq = make_double2(tot[4], tot[5]);
-  const double2 rr = make_double2(tot[6], tot[7]);
   const double n2 = tot[8];
-  S->parity = ldc(&S->parity) ^ 1;
-  const bool ok = finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) && (fabs(pq.x) + fabs(pq.y) > 0.0) &&
-                  (fabs(rr.x) + fabs(rr.y) > 0.0);
-  int it_total = ldc(&S->it_total);
   if (outer) {
     // n2 is the FP64 residual |b - K x|^2 of the current iterate
     const int rounds0 = ldc(&S->rounds);
@@ -508,35 +526,41 @@ __global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
     S->prev_rn2 = n2;
     if (!isfinite(n2)) {
       S->status = kFailBreakdown;
-      return;
-    }
-    if (n2 <= tol2 * bn2) {
+    } else if (n2 <= tol2 * bn2) {
       S->status = kDone;
-      return;
-    }
-    if (rounds >= 3 && n2 > 0.25 * prev) {
+    } else if (rounds >= 3 && n2 > 0.25 * prev) {
       // a whole inner solve did not halve the FP64 residual: it sits at its
       // rounding floor, above the requested tolerance
       S->status = kDone;
       S->stagnated = 1;
-      return;
-    }
-    if (it_total >= e.max_iter) {
+    } else if (ldc(&S->it_total) >= e.max_iter) {
       S->status = kFailMaxIter;
-      return;
+    } else {
+      S->status = kPrime;
+      S->it_inner = 0;
+      // the requested reduction of this residual, never below a quarter of
+      // the final tolerance
+      S->in_tol2 = fmax(e.inner_eta2 * n2, 0.0625 * tol2 * bn2);
     }
+    return;
+  }
+  const double2 pq = make_double2(tot[0], tot[1]);
+  const double2 qr = make_double2(tot[2], tot[3]);
+  const double2 qq = make_double2(tot[4], tot[5]);
+  const double2 rr = make_double2(tot[6], tot[7]);
+  const bool ok = finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) && (fabs(pq.x) + fabs(pq.y) > 0.0) &&
+                  (fabs(rr.x) + fabs(rr.y) > 0.0);
+  if (status == kPrime) {
     if (!ok) {
       S->status = kFailBreakdown;
       return;
     }
     S->status = kInner;
-    S->it_inner = 0;
-    // the requested reduction of this residual, never below a quarter of
-    // the final tolerance
-    S->in_tol2 = fmax(e.inner_eta2 * n2, 0.0625 * tol2 * bn2);
   } else {
+    // inner step: r and p were written to the other buffers
+    S->parity = ldc(&S->parity) ^ 1;
     S->it_inner = ldc(&S->it_inner) + 1;
-    it_total += 1;
+    const int it_total = ldc(&S->it_total) + 1;
     S->it_total = it_total;
     if (!ok || !isfinite(n2) || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
       S->status = kInnerDone;

@@ -632,13 +632,15 @@ struct Engine {
                              std::max(0, R - 1) * (32.0 + 5.0 * eb));
       } else {
         // COCG: an inner step reads d, r, p and writes them (6 complex
-        // values); an FP64 round reads x64 (16 B), d and eta0 (8 B) and
-        // writes r and p (the first round reads only eta0); the first inner
-        // step of every later round moves d into x64 (32 B instead of a d read)
+        // values); a residual step reads x64 (16 B), d and eta0 (8 B) and
+        // writes r and p (the first reads only eta0); each restart's prime
+        // step reads r; the first inner step of every later round moves d
+        // into x64 (32 B instead of a d read)
         const double eb = double(z.eb);
         const int R = stats[j].rounds;
         pass_bytes += pts * (6.0 * eb * stats[j].it_total + (8.0 + 2.0 * eb) +
-                             std::max(0, R - 1) * (24.0 + 3.0 * eb) + std::max(0, R - 2) * (32.0 - eb));
+                             std::max(0, R - 1) * (24.0 + 3.0 * eb) + std::max(0, R - 1) * eb +
+                             std::max(0, R - 2) * (32.0 - eb));
       }
     }
     return 0.0;

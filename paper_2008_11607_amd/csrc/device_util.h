@@ -270,6 +270,45 @@ struct TileRegs {
   }
 };
 
+// Row-mapped tile with halo HALO, (kTY + 2 HALO) x (kTX + 2 HALO): thread
+// (tx, wave w) loads rows w, w + 4, ... at tile column tx + HALO (grid column
+// x0 + tx, the same for every row, while each row is uniform across the
+// wavefront), and threads 0 .. 2 HALO (kTY + 2 HALO) - 1 load one point of
+// the 2 HALO side columns.  f(row_offset, column) returns the value of a
+// grid point (row_offset = wrapped row * nx).
+template <typename V, int HALO>
+struct RowTile {
+  static constexpr int kH = kTY + 2 * HALO, kW = kTX + 2 * HALO;
+  static constexpr int kRows = (kH + 3) / 4, kSide = 2 * HALO * kH;
+  V mainv[kRows];
+  V sidev;
+  int sly, slx;
+  template <typename F>
+  __device__ __forceinline__ void fetch(int x0, int y0, int nx, int ny, bool big, F f) {
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
+#pragma unroll
+    for (int m = 0; m < kRows; ++m) {
+      if (w + 4 * m < kH) mainv[m] = f(size_t(wrapc(y0 - HALO + w + 4 * m, ny, big)) * size_t(nx), col);
+    }
+    sly = int(threadIdx.x) / (2 * HALO);
+    const int c = int(threadIdx.x) - sly * 2 * HALO;
+    slx = (c < HALO) ? c : kTX + c;
+    if (int(threadIdx.x) < kSide)
+      sidev = f(size_t(wrapc(y0 - HALO + sly, ny, big)) * size_t(nx), unsigned(wrapc(x0 - HALO + slx, nx, big)));
+  }
+  __device__ __forceinline__ void store(V* lds) const {
+    const int tx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+#pragma unroll
+    for (int m = 0; m < kRows; ++m) {
+      if (w + 4 * m < kH) lds[(w + 4 * m) * kW + tx + HALO] = mainv[m];
+    }
+    if (int(threadIdx.x) < kSide) lds[sly * kW + slx] = sidev;
+  }
+};
+
 // The same staging straight into LDS in PARTS rounds of loads (fewer live
 // registers, one memory round trip per round); call between barriers.
 template <typename V, int TH, int TW, int PARTS, typename F>

@@ -139,7 +139,7 @@ __device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, 
   using V = typename C2<T>::t;
   V* PN = reinterpret_cast<V*>(lds);
   V* PT = reinterpret_cast<V*>(lds + PassLds<T>::kN);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
@@ -239,7 +239,7 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
   using V = typename C2<T>::t;
   V* PN = reinterpret_cast<V*>(lds);
   V* PT = reinterpret_cast<V*>(lds + PassLds<T>::kN);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;

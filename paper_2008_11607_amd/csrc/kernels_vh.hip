@@ -108,7 +108,7 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   using V = typename C2<T>::t;
   V* ST = reinterpret_cast<V*>(lds);
   T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
@@ -119,14 +119,14 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  TileRegs<V, kBH, kBW> sr;
-  sr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
+  RowTile<V, 2> sr;
+  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
   });
-  TileRegs<T, kHH, kHW> hr;
-  hr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+  RowTile<T, 1> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return T(c.H[g]);
   });
   V hv[kTY / 4];
@@ -160,7 +160,7 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   using V = typename C2<T>::t;
   V* ST = reinterpret_cast<V*>(lds);
   T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
@@ -178,14 +178,14 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  TileRegs<V, kBH, kBW> sr;
-  sr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
+  RowTile<V, 2> sr;
+  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
   });
-  TileRegs<T, kHH, kHW> hr;
-  hr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+  RowTile<T, 1> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return T(c.H[g]);
   });
   size_t gi[kTY / 4];
@@ -227,7 +227,7 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
 template <typename T>
 __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int slot, int tile) {
   using V = typename C2<T>::t;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const V* rs = reinterpret_cast<const V*>(c.par ? e.r1 : e.r0) + base;
@@ -265,7 +265,7 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   using V = typename C2<T>::t;
   double2* XT = reinterpret_cast<double2*>(lds);
   double* Hs = reinterpret_cast<double*>(lds + sizeof(double2) * kBH * kBW);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   const double2* x64 = e.x64 + base;
@@ -283,17 +283,17 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   const bool big = (nx >= kSW) && (ny >= kSH);
   // every load of the work item in one round: x = x64 + d (halo 2), the
   // depth (halo 1) and the right-hand side fields (interior)
-  TileRegs<double2, kBH, kBW> xr;
-  TileRegs<double, kHH, kHW> hr;
+  RowTile<double2, 2> xr;
+  RowTile<double, 1> hr;
   if (!zero_x) {
-    xr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
+    xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
       const V dv = d[g];
       const double2 xv = x64[g];
       return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
     });
-    hr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+    hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
       return c.H[g];
     });
   }
@@ -343,7 +343,7 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   using V = typename C2<T>::t;
   V* PT = reinterpret_cast<V*>(lds);
   T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
   // p' was written by pass U1 into the buffers of the next parity
@@ -354,14 +354,14 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  TileRegs<V, kBH, kBW> pr;
-  pr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
+  RowTile<V, 2> pr;
+  pr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return pn[g];
   });
-  TileRegs<T, kHH, kHW> hr;
-  hr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 1 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 1 + lx, nx, big));
+  RowTile<T, 1> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
     return T(c.H[g]);
   });
   V hv[kTY / 4];

@@ -234,6 +234,36 @@ __device__ __forceinline__ void store_block_sums(A (&v)[N], double* red, double*
   }
 }
 
+// Slot sums of N partials over nblk tiles by a block of kSNT threads: each
+// thread adds its tiles in index order, then DPP within each wavefront and
+// the kSNT/64 wavefront totals in fixed order (valid in thread 0).
+constexpr int kSNT = 512;
+template <int N>
+__device__ __forceinline__ void slot_sums_n(const double* pp, int nblk, double (&tot)[N], double* red) {
+  double v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kSNT) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += ldc(&pp[size_t(b) * kNDots + k]);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_total63(v[k]);
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[(threadIdx.x >> 6) * N + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = 0.0;
+      for (int q = 0; q < kSNT / 64; ++q) a += red[q * N + k];
+      tot[k] = a;
+    }
+  }
+}
+
 // partial sums of work item (slot, tile): [slot][tile][kNDots]
 __device__ __forceinline__ double* item_part(const Eng& e, int slot, int tile) {
   return e.part + (size_t(slot) * e.cap_blk + tile) * kNDots;

@@ -40,6 +40,7 @@ constexpr int kTX = 64;
 constexpr int kTY = 16;
 constexpr int kNT = 256;
 constexpr int kNDots = 9;   // pq(2) qr(2) qq(2) rr(2) |r|^2(1)
+constexpr int kMaxSlots = 1024;
 
 enum SlotStatus : int {
   kIdle = 0,          // slot holds no solve
@@ -108,7 +109,8 @@ struct Slot {
   int solve;         // index into the SolveDev table
   int inst;
   int stagnated;
-  int pad;
+  int discard;       // BiCGStab: d holds no usable correction (its last
+                     // inner round went non-finite); the iterate is x64
 };
 
 // Everything the kernels of one engine need (passed by value).
@@ -121,6 +123,7 @@ struct Eng {
   int max_iter;
   int method;            // 0: COCG on the constant-depth Helmholtz; 1: BiCGStab (flux form)
   int d_is_f32;          // inner precision of d, r, p (1: FP32, 0: FP64)
+  int grid_small;        // persistent grid of kernels that mostly find no work
   Slot* slots;           // [B]
   const Inst* inst;      // [ninst]
   const SolveDev* solves;// [S]

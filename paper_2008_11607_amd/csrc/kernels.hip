@@ -492,22 +492,14 @@ __global__ __launch_bounds__(kNT) void k_pass_f64(Eng e) { cocg_pass<double>(e);
 // tiles in index order.  Inner step: set alpha_{i+1}, beta_{i+1} or end the
 // inner solve.  Residual step: decide done / stagnated / failed, or go on
 // to a prime step.  Prime step: alpha, beta of the first inner step.
-__global__ __launch_bounds__(kNT) void k_pass_scalars(Eng e) {
-  __shared__ double red[4 * kNDots];
+__global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
+  __shared__ double red[kSNT / 64 * kNDots];
   Slot* S = &e.slots[blockIdx.x];
   const int status = ldc(&S->status);
   const bool outer = (status == kOuterPending || status == kInnerDone);
   if (status != kInner && status != kPrime && !outer) return;
-  const int nblk = ldc(&S->nblk);
-  double v[kNDots], tot[kNDots];
-#pragma unroll
-  for (int k = 0; k < kNDots; ++k) v[k] = 0.0;
-  const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
-  for (int b = threadIdx.x; b < nblk; b += kNT) {
-#pragma unroll
-    for (int k = 0; k < kNDots; ++k) v[k] += ldc(&pp[size_t(b) * kNDots + k]);
-  }
-  block_sum_n<kNDots>(v, red, tot);
+  double tot[kNDots];
+  slot_sums_n<kNDots>(e.part + size_t(blockIdx.x) * e.cap_blk * kNDots, ldc(&S->nblk), tot, red);
   if (threadIdx.x != 0) return;
   const double n2 = tot[8];
   if (outer) {
@@ -600,7 +592,7 @@ __global__ void k_retire(Eng e) {
       double2 x = *xp;
       // the last inner correction d is still to be added (once the solve
       // has run an inner round)
-      if (ldc(&S->rounds) >= 2) {
+      if (ldc(&S->rounds) >= 2 && ldc(&S->discard) == 0) {
         if (e.d_is_f32) {
           const float2 dv = reinterpret_cast<const float2*>(e.d)[size_t(s) * e.cap + i];
           x.x += double(dv.x);
@@ -701,6 +693,7 @@ __device__ void assign_serial(Eng& e, int* working_out, int* uniform_out) {
         S->Z0 = ldc_ptr(&I->Z0);
       }
       S->stagnated = 0;
+      S->discard = 0;
       status = kOuterPending;
       ++next;
     }
@@ -917,7 +910,7 @@ void launch_pass(const Eng& e, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_pass_f64, dim3(grid), dim3(kNT), 0, s, e);
 }
 void launch_pass_scalars(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_scalars, dim3(e.B), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(k_pass_scalars, dim3(e.B), dim3(kSNT), 0, s, e);
 }
 void launch_retire(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(256), 0, s, e);

@@ -27,6 +27,8 @@
 // (status kInnerLast) before its residual round.  r, p and v are ping-pong
 // buffers so that no pass reads (with a halo) what another block of the
 // same pass writes.
+#include <algorithm>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -68,7 +70,7 @@ __device__ __forceinline__ void cdot(double* acc, V a, V b) {
 
 // Control fields of a slot, read in one round of coherent loads.
 struct BcgCtl {
-  int status, par, rounds, it_inner, nx, ny, tiles_x;
+  int status, par, rounds, it_inner, discard, nx, ny, tiles_x;
   double cx, cy, cxy;
   const double* H;
   double2 alpha, beta, omega, gamma, zeta;
@@ -80,6 +82,7 @@ __device__ __forceinline__ BcgCtl load_bctl(const Slot* S) {
   c.par = ldu(&S->parity);
   c.rounds = ldu(&S->rounds);
   c.it_inner = ldu(&S->it_inner);
+  c.discard = ldu(&S->discard);
   c.nx = ldu(&S->nx);
   c.ny = ldu(&S->ny);
   c.tiles_x = ldu(&S->tiles_x);
@@ -170,8 +173,8 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const V* vs = reinterpret_cast<const V*>(c.par ? e.v1 : e.v0) + base;
   V* d = reinterpret_cast<V*>(e.d) + base;
   double2* x64 = e.x64 + base;
-  const bool first = c.it_inner == 1;        // d restarts this pass
-  const bool fold = first && c.rounds >= 2;  // ... after x64 += d
+  const bool first = c.it_inner == 1;                      // d restarts this pass
+  const bool fold = first && c.rounds >= 2 && !c.discard;  // ... after x64 += d
   const V alpha = mk<V>(c.alpha.x, c.alpha.y), beta = mk<V>(c.beta.x, c.beta.y);
   const V omega = mk<V>(c.omega.x, c.omega.y);
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
@@ -236,7 +239,7 @@ __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int s
   V* d = reinterpret_cast<V*>(e.d) + base;
   double2* x64 = e.x64 + base;
   const bool first = c.it_inner == 1;
-  const bool fold = first && c.rounds >= 2;
+  const bool fold = first && c.rounds >= 2 && !c.discard;
   const V alpha = mk<V>(c.alpha.x, c.alpha.y), omega = mk<V>(c.omega.x, c.omega.y);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
 #pragma unroll
@@ -274,6 +277,7 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   V* pd = reinterpret_cast<V*>(c.par ? e.p0 : e.p1) + base;
   V* rh = reinterpret_cast<V*>(e.rh) + base;
   const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
+  const bool use_d = !c.discard;   // else the iterate is x64 alone
   const Slot* S = &e.slots[slot];
   const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2), sc = ldu(&S->sc);
   const double* eta0 = ldu_ptr(&S->eta0);
@@ -287,9 +291,10 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   RowTile<double, 1> hr;
   if (!zero_x) {
     xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-      const V dv = d[g];
+      const size_t g = ro + col;
       const double2 xv = x64[g];
+      if (!use_d) return xv;
+      const V dv = d[g];
       return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
     });
     hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
@@ -433,6 +438,19 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsU1<T>::kX];
   __shared__ double red[4 * 2];
+  __shared__ int st[kMaxSlots];
+  __shared__ int any;
+  // the statuses of all slots in one round of loads; most launches find no
+  // slot in a residual round and end here
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < e.B; q += kNT) {
+    const int v = ldc(&e.slots[q].status);
+    st[q] = v;
+    if (v == kOuterPending || v == kInnerDone) any = 1;
+  }
+  __syncthreads();
+  if (!any) return;
   const WorkHead h = load_work_head(e);
   const int total = h.total;
   const int per = (total + 7) >> 3;
@@ -440,8 +458,8 @@ __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
     const int pos = xcd_pos(w, per);
     if (pos >= total) continue;
     const Item it = item_of(e, pos, h);
+    if (st[it.slot] != kOuterPending && st[it.slot] != kInnerDone) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
-    if (c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};
     bcg_u1_outer<T>(e, c, it.slot, it.tile, lds, acc);
     store_block_sums<2, 2>(acc, red, item_part(e, it.slot, it.tile));
@@ -479,24 +497,15 @@ __global__ __launch_bounds__(kNT) void k_bcg_u2_f64(Eng e) { bcg_pass_u2<double>
 // ---- scalar kernels (one block per slot, partials in tile order) -----------
 template <int N>
 __device__ __forceinline__ bool slot_sums(const Eng& e, const Slot* S, double (&tot)[N], double* red) {
-  const int nblk = ldc(&S->nblk);
-  double v[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = 0.0;
-  const double* pp = e.part + size_t(blockIdx.x) * e.cap_blk * kNDots;
-  for (int b = threadIdx.x; b < nblk; b += kNT) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] += ldc(&pp[size_t(b) * kNDots + k]);
-  }
-  block_sum_n<N>(v, red, tot);
+  slot_sums_n<N>(e.part + size_t(blockIdx.x) * e.cap_blk * kNDots, ldc(&S->nblk), tot, red);
   return threadIdx.x == 0;
 }
 
 __device__ __forceinline__ bool nonzero(double2 v) { return fabs(v.x) + fabs(v.y) > 0.0; }
 
 // after pass S: omega, rho', beta and the stop test
-__global__ __launch_bounds__(kNT) void k_bcg_scalars_s(Eng e) {
-  __shared__ double red[4 * 8];
+__global__ __launch_bounds__(kSNT) void k_bcg_scalars_s(Eng e) {
+  __shared__ double red[kSNT / 64 * 8];
   Slot* S = &e.slots[blockIdx.x];
   if (ldc(&S->status) != kInner) return;
   double tot[8];
@@ -515,6 +524,12 @@ __global__ __launch_bounds__(kNT) void k_bcg_scalars_s(Eng e) {
     return;
   }
   const double2 om = make_double2(ts.x / tt, ts.y / tt);
+  if (!(fabs(om.x) + fabs(om.y) < 1e30)) {
+    // omega outside the inner precision's range: keep the half step
+    S->omega = make_double2(0.0, 0.0);
+    S->status = kInnerLast;
+    return;
+  }
   S->omega = om;
   const double2 rho1 = csub(hs, cmul(om, ht));
   const double n2 = fmax(ss - (ts.x * ts.x + ts.y * ts.y) / tt, 0.0);
@@ -530,12 +545,15 @@ __global__ __launch_bounds__(kNT) void k_bcg_scalars_s(Eng e) {
 
 // after pass U: alpha of the next iteration; end of the last update; or the
 // decision of an FP64 residual round
-__global__ __launch_bounds__(kNT) void k_bcg_scalars_u(Eng e) {
-  __shared__ double red[4 * 4];
+__global__ __launch_bounds__(kSNT) void k_bcg_scalars_u(Eng e) {
+  __shared__ double red[kSNT / 64 * 4];
   Slot* S = &e.slots[blockIdx.x];
   const int status = ldc(&S->status);
   if (status == kInnerLast) {
-    if (threadIdx.x == 0) S->status = kInnerDone;
+    if (threadIdx.x == 0) {
+      if (ldc(&S->it_inner) == 1) S->discard = 0;  // pass U1 restarted d
+      S->status = kInnerDone;
+    }
     return;
   }
   const bool outer = (status == kOuterPending || status == kInnerDone);
@@ -552,6 +570,12 @@ __global__ __launch_bounds__(kNT) void k_bcg_scalars_u(Eng e) {
     if (rounds0 == 0) {
       bn2 = rn2;
       S->bn2 = rn2;
+    }
+    if (!isfinite(rn2) && rounds0 >= 1 && !ldc(&S->discard)) {
+      // the last inner round went non-finite: drop its correction d and
+      // take the residual of x64 alone in the next residual round
+      S->discard = 1;
+      return;
     }
     const int rounds = rounds0 + 1;
     S->rounds = rounds;
@@ -585,12 +609,23 @@ __global__ __launch_bounds__(kNT) void k_bcg_scalars_u(Eng e) {
     S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
     S->status = kInner;
   }
-  if (!finite2(hv) || !nonzero(hv) || !nonzero(rho)) {
-    // breakdown: the iterate is x64 + d as it stands
-    S->status = outer ? kFailBreakdown : kInnerDone;
+  const double2 al = (finite2(hv) && nonzero(hv) && nonzero(rho)) ? cdiv(rho, hv) : make_double2(NAN, NAN);
+  if (!(fabs(al.x) + fabs(al.y) < 1e30)) {
+    if (!outer) {
+      // breakdown inside the inner solve: restart from the FP64 residual
+      S->status = kInnerDone;
+    } else if (ldc(&S->rounds) >= 2) {
+      // no usable restart from a finite residual above the tolerance: the
+      // solve stops at its current iterate
+      S->status = kDone;
+      S->stagnated = 1;
+    } else {
+      S->status = kFailBreakdown;
+    }
     return;
   }
-  S->alpha = cdiv(rho, hv);
+  if (!outer && ldc(&S->it_inner) == 1) S->discard = 0;  // pass U1 restarted d
+  S->alpha = al;
 }
 
 int prep_vh_blocks() { return 256; }
@@ -665,19 +700,19 @@ void launch_fill_value(double* p, size_t n, double v, hipStream_t s) {
 template <typename T>
 void launch_bcg(const Eng& e, int grid, hipStream_t s) {
   if (sizeof(T) == 4) {
-    hipLaunchKernelGGL(k_bcg_outer_f32, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_outer_f32, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_u1_f32, dim3(grid), dim3(kNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_u2_f32, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_s_f32, dim3(grid), dim3(kNT), 0, s, e);
   } else {
-    hipLaunchKernelGGL(k_bcg_outer_f64, dim3(grid), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_outer_f64, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_u1_f64, dim3(grid), dim3(kNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_u2_f64, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kNT), 0, s, e);
+    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
     hipLaunchKernelGGL(k_bcg_s_f64, dim3(grid), dim3(kNT), 0, s, e);
   }
-  hipLaunchKernelGGL(k_bcg_scalars_s, dim3(e.B), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(k_bcg_scalars_s, dim3(e.B), dim3(kSNT), 0, s, e);
 }
 void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
                     double* hmax_part, hipStream_t s) {

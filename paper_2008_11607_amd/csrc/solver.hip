@@ -317,6 +317,7 @@ static int choose_slots(int requested, size_t max_points, double mean_nblk, size
     B = int(std::ceil(16384.0 / std::max(1.0, mean_nblk)));
     B = std::max(8, std::min(B, 1024));
   }
+  B = std::min(B, kMaxSlots);
   const size_t per_slot = max_points * (16 + nvec * inner_elem_bytes(precision));
   const size_t budget = size_t(24) << 30;
   B = int(std::max<size_t>(1, std::min<size_t>(size_t(B), budget / per_slot)));
@@ -527,6 +528,7 @@ struct Engine {
     const size_t items = size_t(z.B) * z.cap_blk;
     grid = int(std::max<size_t>(size_t(cus) * std::max(1, occ), items));
     grid = ((grid + 7) / 8) * 8;
+    e.grid_small = ((cus * 4 + 7) / 8) * 8;
   }
 
   template <typename T>

@@ -130,6 +130,12 @@ typedef struct rexii_report {
     int64_t kernel_launches;
     double kernel_ms;
     double kernel_bytes;
+    /* BiCGStab path with opts.profile = 1: HIP-event time of each kernel of
+     * the kernel_launches iteration steps, summed (ms): residual round,
+     * pass U1, pass U2, scalars after U, pass S, scalars after S; and the
+     * algorithmic bytes of the pass U1 launches */
+    double step_ms[6];
+    double u1_bytes;
 } rexii_report;
 
 /* Fill *opts with the defaults described above. */

@@ -236,16 +236,29 @@ __device__ __forceinline__ void store_block_sums(A (&v)[N], double* red, double*
 
 // Slot sums of N partials over nblk tiles by a block of kSNT threads: each
 // thread adds its tiles in index order, then DPP within each wavefront and
-// the kSNT/64 wavefront totals in fixed order (valid in thread 0).
+// the kSNT/64 wavefront totals in fixed order (valid in thread 0).  The
+// partials were written by the previous kernel on the stream, so plain
+// loads see them; a thread issues the loads of four tiles before adding.
 constexpr int kSNT = 512;
 template <int N>
 __device__ __forceinline__ void slot_sums_n(const double* pp, int nblk, double (&tot)[N], double* red) {
+  constexpr int kU = 4;
   double v[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kSNT) {
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += kU * kSNT) {
+    double t[kU][N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] += ldc(&pp[size_t(b) * kNDots + k]);
+    for (int u = 0; u < kU; ++u) {
+      const int b = b0 + u * kSNT;
+#pragma unroll
+      for (int k = 0; k < N; ++k) t[u][k] = (b < nblk) ? pp[size_t(b) * kNDots + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] += t[u][k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] = wave_total63(v[k]);
@@ -300,15 +313,15 @@ struct TileRegs {
   }
 };
 
-// Row-mapped tile with halo HALO, (kTY + 2 HALO) x (kTX + 2 HALO): thread
+// Row-mapped tile with halo HALO, (TH + 2 HALO) x (kTX + 2 HALO): thread
 // (tx, wave w) loads rows w, w + 4, ... at tile column tx + HALO (grid column
 // x0 + tx, the same for every row, while each row is uniform across the
-// wavefront), and threads 0 .. 2 HALO (kTY + 2 HALO) - 1 load one point of
+// wavefront), and threads 0 .. 2 HALO (TH + 2 HALO) - 1 load one point of
 // the 2 HALO side columns.  f(row_offset, column) returns the value of a
 // grid point (row_offset = wrapped row * nx).
-template <typename V, int HALO>
+template <typename V, int HALO, int TH = kTY>
 struct RowTile {
-  static constexpr int kH = kTY + 2 * HALO, kW = kTX + 2 * HALO;
+  static constexpr int kH = TH + 2 * HALO, kW = kTX + 2 * HALO;
   static constexpr int kRows = (kH + 3) / 4, kSide = 2 * HALO * kH;
   V mainv[kRows];
   V sidev;

@@ -37,7 +37,8 @@ namespace rexii {
 
 // Stencil tile: 64 x 16 points, 256 threads (64 x 4), 4 rows per thread.
 constexpr int kTX = 64;
-constexpr int kTY = 16;
+constexpr int kTY = 16;    // tile height of the COCG passes
+constexpr int kTYB = 32;   // tile height of the BiCGStab passes (fewer, larger work items)
 constexpr int kNT = 256;
 constexpr int kNDots = 9;   // pq(2) qr(2) qq(2) rr(2) |r|^2(1)
 constexpr int kMaxSlots = 1024;
@@ -60,6 +61,7 @@ struct Inst {
   double cx, cy;          // (nx/2)^2, (ny/2)^2
   double cxy;             // nx ny / 4 (cross term of the variable-depth operator)
   const double* H;        // depth field [ny][nx] (BiCGStab path) or nullptr
+  const void* Hin;        // the depth in the inner-iteration type (float or double)
   const double* eta0;     // [ny][nx]
   const double* D0;       // div(u0, v0) or nullptr
   const double* Z0;       // curl(u0, v0) or nullptr
@@ -95,6 +97,7 @@ struct Slot {
   double tol2;       // final relative tolerance^2 of this solve
   double cx, cy, cxy;  // stencil coefficients of the solve's problem
   const double* H;     // its depth field (BiCGStab path) or nullptr
+  const void* Hin;     // the same in the inner-iteration type
   const double* eta0;  // its right-hand side fields (see Inst)
   const double* D0;
   const double* Z0;
@@ -172,13 +175,16 @@ void launch_pass(const Eng& e, int grid, hipStream_t s);
 //   gamma = t f_c / z,  zeta = (z^2 + t^2 f_c^2) / (t^2 g),  sc = zeta / z,
 //   a1 = t m1, a2 = t m2, D_H = div(H (u0, v0)), Z_H = dx(H v0) - dy(H u0),
 // solved by BiCGStab (K is not complex-symmetric: C_H is antisymmetric).
+// One iteration step: residual round, passes U1 and U2, scalars, pass S,
+// scalars.  With ev (7 events) each kernel is bracketed for timing.
 template <typename T>
-void launch_bcg(const Eng& e, int grid, hipStream_t s);   // passes U and S with their scalar kernels
+void launch_bcg(const Eng& e, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
                     double* hmax_part, hipStream_t s);
 int prep_vh_blocks();
 void launch_hmax(const double* H, size_t n, int* flags, double* part, hipStream_t s);
 void launch_fill_value(double* p, size_t n, double v, hipStream_t s);
+void launch_to_f32(const double* p, float* q, size_t n, hipStream_t s);
 int bcg_occupancy(int mixed);
 
 void launch_pass_scalars(const Eng& e, hipStream_t s);

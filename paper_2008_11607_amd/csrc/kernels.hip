@@ -688,6 +688,7 @@ __device__ void assign_serial(Eng& e, int* working_out, int* uniform_out) {
         S->cy = ldc(&I->cy);
         S->cxy = ldc(&I->cxy);
         S->H = ldc_ptr(&I->H);
+        S->Hin = ldc_ptr(&I->Hin);
         S->eta0 = ldc_ptr(&I->eta0);
         S->D0 = ldc_ptr(&I->D0);
         S->Z0 = ldc_ptr(&I->Z0);

@@ -34,9 +34,9 @@
 
 namespace rexii {
 
-constexpr int kBW = kTX + 4, kBH = kTY + 4;   // tile with halo 2
-constexpr int kSW = kTX + 8, kSH = kTY + 8;   // grids at least this large take the cheap wrap
-constexpr int kHW = kTX + 2, kHH = kTY + 2;   // depth tile with halo 1
+constexpr int kBW = kTX + 4, kBH = kTYB + 4;   // tile with halo 2
+constexpr int kSW = kTX + 8, kSH = kTYB + 8;   // grids at least this large take the cheap wrap
+constexpr int kHW = kTX + 2, kHH = kTYB + 2;   // depth tile with halo 1
 
 // K phi at position (y, x) of a phi tile with row width PW; the same grid
 // point is (y + DH, x + DH) of the depth tile (row width HW).
@@ -72,7 +72,8 @@ __device__ __forceinline__ void cdot(double* acc, V a, V b) {
 struct BcgCtl {
   int status, par, rounds, it_inner, discard, nx, ny, tiles_x;
   double cx, cy, cxy;
-  const double* H;
+  const double* H;   // depth, FP64 (residual rounds)
+  const void* Hin;   // depth in the inner-iteration type (passes S, U1, U2)
   double2 alpha, beta, omega, gamma, zeta;
 };
 
@@ -90,6 +91,7 @@ __device__ __forceinline__ BcgCtl load_bctl(const Slot* S) {
   c.cy = ldu(&S->cy);
   c.cxy = ldu(&S->cxy);
   c.H = ldu_ptr(&S->H);
+  c.Hin = ldu_ptr(&S->Hin);
   c.alpha = ldu(&S->alpha);
   c.beta = ldu(&S->beta);
   c.omega = ldu(&S->omega);
@@ -120,28 +122,26 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const V alpha = mk<V>(c.alpha.x, c.alpha.y);
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2> sr;
+  RowTile<V, 2, kTYB> sr;
   sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
   });
-  RowTile<T, 1> hr;
-  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-    return T(c.H[g]);
-  });
-  V hv[kTY / 4];
+  const T* Hi = static_cast<const T*>(c.Hin);
+  RowTile<T, 1, kTYB> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
+  V hv[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j)
+  for (int j = 0; j < kTYB / 4; ++j)
     hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
   __syncthreads();  // LDS of the previous work item is free
   sr.store(ST);
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -179,22 +179,20 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const V omega = mk<V>(c.omega.x, c.omega.y);
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2> sr;
+  RowTile<V, 2, kTYB> sr;
   sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
   });
-  RowTile<T, 1> hr;
-  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-    return T(c.H[g]);
-  });
-  size_t gi[kTY / 4];
-  V pv[kTY / 4], vv[kTY / 4], dv[kTY / 4];
+  const T* Hi = static_cast<const T*>(c.Hin);
+  RowTile<T, 1, kTYB> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
+  size_t gi[kTYB / 4];
+  V pv[kTYB / 4], vv[kTYB / 4], dv[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     gi[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
     pv[j] = ps[gi[j]];
     vv[j] = vs[gi[j]];
@@ -205,7 +203,7 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -241,9 +239,9 @@ __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int s
   const bool first = c.it_inner == 1;
   const bool fold = first && c.rounds >= 2 && !c.discard;
   const V alpha = mk<V>(c.alpha.x, c.alpha.y), omega = mk<V>(c.omega.x, c.omega.y);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const int gx = x0 + tx, gy = y0 + ty + 4 * j;
     if (gx < nx && gy < ny) {
       const size_t g = size_t(gy) * nx + gx;
@@ -283,12 +281,12 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   const double* eta0 = ldu_ptr(&S->eta0);
   const double* D0 = ldu_ptr(&S->D0);
   const double* Z0 = ldu_ptr(&S->Z0);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
   // every load of the work item in one round: x = x64 + d (halo 2), the
   // depth (halo 1) and the right-hand side fields (interior)
-  RowTile<double2, 2> xr;
-  RowTile<double, 1> hr;
+  RowTile<double2, 2, kTYB> xr;
+  RowTile<double, 1, kTYB> hr;
   if (!zero_x) {
     xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
       const size_t g = ro + col;
@@ -302,9 +300,9 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
       return c.H[g];
     });
   }
-  double bre[kTY / 4], bdz[kTY / 4], bzz[kTY / 4];
+  double bre[kTYB / 4], bdz[kTYB / 4], bzz[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const size_t g = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
     bre[j] = eta0[g];
     if (D0) {
@@ -319,7 +317,7 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const int ly = ty + 4 * j;
     const int gx = x0 + tx, gy = y0 + ly;
     if (gx < nx && gy < ny) {
@@ -357,28 +355,26 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   const V* rh = reinterpret_cast<const V*>(e.rh) + base;
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2> pr;
+  RowTile<V, 2, kTYB> pr;
   pr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return pn[g];
   });
-  RowTile<T, 1> hr;
-  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-    return T(c.H[g]);
-  });
-  V hv[kTY / 4];
+  const T* Hi = static_cast<const T*>(c.Hin);
+  RowTile<T, 1, kTYB> hr;
+  hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
+  V hv[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j)
+  for (int j = 0; j < kTYB / 4; ++j)
     hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
   __syncthreads();  // LDS of the previous work item is free
   pr.store(PT);
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTY / 4; ++j) {
+  for (int j = 0; j < kTYB / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V v1 = kop<kBW, kHW, -1>(PT, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -487,7 +483,7 @@ __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
 
 __global__ __launch_bounds__(kNT) void k_bcg_s_f32(Eng e) { bcg_pass_s<float>(e); }
 __global__ __launch_bounds__(kNT) void k_bcg_s_f64(Eng e) { bcg_pass_s<double>(e); }
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_bcg_u1_f32(Eng e) { bcg_pass_u1<float>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f32(Eng e) { bcg_pass_u1<float>(e); }
 __global__ __launch_bounds__(kNT) void k_bcg_u1_f64(Eng e) { bcg_pass_u1<double>(e); }
 __global__ __launch_bounds__(kNT) void k_bcg_outer_f32(Eng e) { bcg_pass_outer<float>(e); }
 __global__ __launch_bounds__(kNT) void k_bcg_outer_f64(Eng e) { bcg_pass_outer<double>(e); }
@@ -693,26 +689,38 @@ __global__ void k_fill_value(double* p, size_t n, double v) {
 void launch_hmax(const double* H, size_t n, int* flags, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_hmax, dim3(prep_vh_blocks()), dim3(256), 0, s, H, n, flags, part);
 }
+__global__ void k_to_f32(const double* p, float* q, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    q[i] = float(p[i]);
+}
+void launch_to_f32(const double* p, float* q, size_t n, hipStream_t s) {
+  size_t bl = (n + 255) / 256;
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl))), dim3(256), 0, s, p, q, n);
+}
 void launch_fill_value(double* p, size_t n, double v, hipStream_t s) {
   size_t bl = (n + 255) / 256;
   hipLaunchKernelGGL(k_fill_value, dim3(unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl))), dim3(256), 0, s, p, n, v);
 }
 template <typename T>
-void launch_bcg(const Eng& e, int grid, hipStream_t s) {
-  if (sizeof(T) == 4) {
-    hipLaunchKernelGGL(k_bcg_outer_f32, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_u1_f32, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_u2_f32, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_s_f32, dim3(grid), dim3(kNT), 0, s, e);
-  } else {
-    hipLaunchKernelGGL(k_bcg_outer_f64, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_u1_f64, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_u2_f64, dim3(grid), dim3(kNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
-    hipLaunchKernelGGL(k_bcg_s_f64, dim3(grid), dim3(kNT), 0, s, e);
-  }
+void launch_bcg(const Eng& e, int grid, hipStream_t s, hipEvent_t* ev) {
+  const bool f32 = sizeof(T) == 4;
+  int k = 0;
+  auto mark = [&]() {
+    if (ev) (void)hipEventRecord(ev[k++], s);
+  };
+  mark();
+  hipLaunchKernelGGL(f32 ? k_bcg_outer_f32 : k_bcg_outer_f64, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
+  mark();
+  hipLaunchKernelGGL(f32 ? k_bcg_u1_f32 : k_bcg_u1_f64, dim3(grid), dim3(kNT), 0, s, e);
+  mark();
+  hipLaunchKernelGGL(f32 ? k_bcg_u2_f32 : k_bcg_u2_f64, dim3(grid), dim3(kNT), 0, s, e);
+  mark();
+  hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
+  mark();
+  hipLaunchKernelGGL(f32 ? k_bcg_s_f32 : k_bcg_s_f64, dim3(grid), dim3(kNT), 0, s, e);
+  mark();
   hipLaunchKernelGGL(k_bcg_scalars_s, dim3(e.B), dim3(kSNT), 0, s, e);
+  mark();
 }
 void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0, double* Z0, int* flags,
                     double* hmax_part, hipStream_t s) {
@@ -731,7 +739,7 @@ int bcg_occupancy(int mixed) {
   return m > 0 ? m : 1;
 }
 
-template void launch_bcg<float>(const Eng&, int, hipStream_t);
-template void launch_bcg<double>(const Eng&, int, hipStream_t);
+template void launch_bcg<float>(const Eng&, int, hipStream_t, hipEvent_t*);
+template void launch_bcg<double>(const Eng&, int, hipStream_t, hipEvent_t*);
 
 }  // namespace rexii

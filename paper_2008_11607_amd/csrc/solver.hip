@@ -125,10 +125,12 @@ struct Plan {
 struct GridGeo {
   int tiles_x, tiles_y, nblk;
 };
-static GridGeo make_geo(int nx, int ny) {
+// work items are kTX x kTY tiles (COCG) or kTX x kTYB tiles (BiCGStab)
+static GridGeo make_geo(int nx, int ny, int method) {
+  const int th = (method == 1) ? kTYB : kTY;
   GridGeo g;
   g.tiles_x = (nx + kTX - 1) / kTX;
-  g.tiles_y = (ny + kTY - 1) / kTY;
+  g.tiles_y = (ny + th - 1) / th;
   g.nblk = g.tiles_x * g.tiles_y;
   return g;
 }
@@ -334,6 +336,7 @@ struct Problem {
   double* DZ = nullptr;        // device div / curl of the initial velocity
   double* A = nullptr;         // device accumulators [3][ny][nx]
   const double* H = nullptr;   // device depth field (flux-form path)
+  const void* Hin = nullptr;   // the depth in the inner-iteration type
   size_t n() const { return size_t(pl.nx) * pl.ny; }
 };
 
@@ -348,19 +351,21 @@ static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_
   EngineSize z;
   size_t maxp = 0;
   double wsum = 0.0;
+  z.method = 0;
+  for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
   for (Problem* p : probs) {
     maxp = std::max(maxp, p->n());
-    const int nb = make_geo(p->pl.nx, p->pl.ny).nblk;
+    const int nb = make_geo(p->pl.nx, p->pl.ny, z.method).nblk;
     z.cap_blk = std::max(z.cap_blk, nb);
     z.S += int(p->pl.solves.size());
     wsum += double(nb) * double(p->pl.solves.size());
   }
-  const double mean_nblk = z.S > 0 ? wsum / z.S : double(std::max(1, z.cap_blk));
+  // mean tile count in units of kTX x kTY tiles
+  const double mean_nblk =
+      (z.S > 0 ? wsum / z.S : double(std::max(1, z.cap_blk))) * ((z.method == 1) ? double(kTYB) / kTY : 1.0);
   z.cap = int(maxp);
   z.ninst = int(probs.size());
   z.eb = inner_elem_bytes(precision);
-  z.method = 0;
-  for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
   z.nvec = z.method ? 8 : 5;
   z.B = choose_slots(requested_B, maxp, mean_nblk, size_t(z.S), precision, z.nvec);
   return z;
@@ -382,10 +387,11 @@ static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
   return b;
 }
 
-// D/Z, A, a small block, and a constant depth field when a constant-depth
-// problem runs through the flux-form path
+// D/Z, A, a small block, a constant depth field when a constant-depth
+// problem runs through the flux-form path, and an FP32 copy of the depth
+// for the mixed-precision inner iterations
 static size_t problem_bytes(const Problem& p) {
-  return al256(2 * p.n() * 8) + al256(3 * p.n() * 8) + al256((8 + 256) * 8) + al256(p.n() * 8);
+  return al256(2 * p.n() * 8) + al256(3 * p.n() * 8) + al256((8 + 256) * 8) + al256(p.n() * 8) + al256(p.n() * 4);
 }
 
 struct Engine {
@@ -404,8 +410,12 @@ struct Engine {
   std::vector<hipEvent_t> evs;
   int64_t launches = 0;
   double kernel_ms = 0.0;
+  static constexpr int kBcgEvents = 7;   // around the 6 kernels of a BiCGStab step
+  double step_ms[kBcgEvents - 1] = {};
+  double u1_bytes = 0.0;
   double pass_bytes = 0.0;
   std::vector<size_t> inst_points;
+  std::vector<char> inst_vel;
 
   explicit Engine(hipStream_t s) : st(s) {}
   ~Engine() {
@@ -457,10 +467,14 @@ struct Engine {
     // problem table
     std::vector<Inst> hinst(z.ninst);
     inst_points.resize(z.ninst);
-    for (int i = 0; i < z.ninst; ++i) inst_points[i] = probs[i]->n();
+    inst_vel.resize(z.ninst);
+    for (int i = 0; i < z.ninst; ++i) {
+      inst_points[i] = probs[i]->n();
+      inst_vel[i] = probs[i]->pl.has_vel ? 1 : 0;
+    }
     for (int i = 0; i < z.ninst; ++i) {
       const Plan& pl = probs[i]->pl;
-      const GridGeo g = make_geo(pl.nx, pl.ny);
+      const GridGeo g = make_geo(pl.nx, pl.ny, z.method);
       Inst I;
       I.nx = pl.nx;
       I.ny = pl.ny;
@@ -470,6 +484,7 @@ struct Engine {
       I.cy = 0.25 * double(pl.ny) * pl.ny;
       I.cxy = 0.25 * double(pl.nx) * pl.ny;
       I.H = probs[i]->H;
+      I.Hin = probs[i]->Hin;
       I.eta0 = probs[i]->f;
       I.D0 = pl.has_vel ? probs[i]->DZ : nullptr;
       I.Z0 = pl.has_vel ? probs[i]->DZ + probs[i]->n() : nullptr;
@@ -536,14 +551,14 @@ struct Engine {
     launch_retire(e, st);
     launch_assign(e, st);
     for (int i = 0; i < chunk; ++i) {
-      if (with_events) HIPCHK(hipEventRecord(evs[2 * i], st));
       if (z.method == 1) {
-        launch_bcg<T>(e, grid, st);
+        launch_bcg<T>(e, grid, st, with_events ? &evs[kBcgEvents * i] : nullptr);
       } else {
+        if (with_events) HIPCHK(hipEventRecord(evs[2 * i], st));
         launch_pass<T>(e, grid, st);
+        if (with_events) HIPCHK(hipEventRecord(evs[2 * i + 1], st));
+        launch_pass_scalars(e, st);
       }
-      if (with_events) HIPCHK(hipEventRecord(evs[2 * i + 1], st));
-      if (z.method == 0) launch_pass_scalars(e, st);
     }
     launch_count_finished(e, st);
     HIPCHK(hipMemcpyAsync(hcount, e.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -586,7 +601,7 @@ struct Engine {
       return double(ms);
     }
     if (profile) {
-      evs.resize(2 * chunk);
+      evs.resize((z.method == 1 ? kBcgEvents : 2) * chunk);
       for (hipEvent_t& ev : evs) HIPCHK(hipEventCreate(&ev));
     } else {
       build_graph<T>();
@@ -600,7 +615,16 @@ struct Engine {
         HIPCHK(hipStreamSynchronize(st));
         for (int i = 0; i < chunk; ++i) {
           float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+          if (z.method == 1) {
+            const hipEvent_t* ev = &evs[kBcgEvents * i];
+            for (int k = 0; k + 1 < kBcgEvents; ++k) {
+              HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+              step_ms[k] += ms;
+            }
+            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[kBcgEvents - 1]));
+          } else {
+            HIPCHK(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+          }
           kernel_ms += ms;
         }
         launches += chunk;
@@ -621,17 +645,27 @@ struct Engine {
 #endif
     // algorithmic bytes of all pass launches (per point of the solve's grid)
     pass_bytes = 0.0;
+    u1_bytes = 0.0;
     for (int j = 0; j < z.S; ++j) {
       const double pts = double(inst_points[solve_inst[j]]);
       if (z.method == 1) {
-        // BiCGStab iteration: pass S reads r, v, r_hat; pass U reads r, v,
-        // p, d, r_hat and writes d, r, p, v (12 complex values), each pass
-        // reads the FP64 depth; an FP64 round reads x64 (16 B), d, eta0 and
-        // the depth (8 B each) and writes r, r_hat, p, v
-        const double eb = double(z.eb);
-        const int R = stats[j].rounds;
-        pass_bytes += pts * (stats[j].it_total * (12.0 * eb + 16.0) + (16.0 + 4.0 * eb) +
-                             std::max(0, R - 1) * (32.0 + 5.0 * eb));
+        // BiCGStab iteration: pass U2 reads p' and r_hat and writes v;
+        // pass S reads r, v and r_hat; pass U1 reads r, v, p and d and
+        // writes d, r and p (13 complex values); each pass reads the depth
+        // in the inner type (hb).  Per inner solve, its first U1 reads no
+        // d and its last reads no depth and writes only d; every inner
+        // solve after the first starts by moving d into x64 (d read, x64
+        // read and write).  A residual round reads eta0 (and D0, Z0 with
+        // an initial velocity) and writes r, p and r_hat; after the first
+        // it also reads x64, d and the FP64 depth.
+        const double eb = double(z.eb), hb = (z.eb == 8) ? 4.0 : 8.0;
+        const double dz = inst_vel[solve_inst[j]] ? 16.0 : 0.0;
+        const int R = stats[j].rounds, solves_in = std::max(0, R - 1);
+        pass_bytes += pts * (stats[j].it_total * (13.0 * eb + 3.0 * hb) - solves_in * (3.0 * eb + hb) +
+                             std::max(0, R - 2) * (eb + 32.0) + (8.0 + dz + 3.0 * eb) +
+                             solves_in * (32.0 + dz + 4.0 * eb));
+        u1_bytes += pts * (stats[j].it_total * (7.0 * eb + hb) - solves_in * (3.0 * eb + hb) +
+                           std::max(0, R - 2) * (eb + 32.0));
       } else {
         // COCG: an inner step reads d, r, p and writes them (6 complex
         // values); a residual step reads x64 (16 B), d and eta0 (8 B) and
@@ -694,12 +728,17 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     rep->max_rel_residual = r.max_rel_res;
     rep->stagnated = r.stagnated;
     const double eb = double(inner_elem_bytes(pl.precision));
-    // one pass reads x, r, p and writes them back: 6 complex values per point
-    rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * 6.0 * eb;
+    // COCG: a pass reads x, r, p and writes them back (6 complex values per
+    // point); BiCGStab: an iteration moves 13 complex values and reads the
+    // depth three times
+    const double per_pt = en->z.method == 1 ? 13.0 * eb + 3.0 * (eb == 8.0 ? 4.0 : 8.0) : 6.0 * eb;
+    rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * per_pt;
     rep->slots = en->z.B;
     rep->kernel_launches = en->launches;
     rep->kernel_ms = en->kernel_ms;
     rep->kernel_bytes = en->pass_bytes;
+    for (int k = 0; k < 6; ++k) rep->step_ms[k] = en->step_ms[k];
+    rep->u1_bytes = en->u1_bytes;
   }
 }
 
@@ -849,6 +888,7 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
     pb.A = ar.take<double>(3 * n);
     double* hp = ar.take<double>(8 + prep_vh_blocks());
     double* hconst = ar.take<double>(n);
+    float* hf32 = ar.take<float>(n);
     launch_fill_zero(pb.A, 3 * n, jb.st);
     if (it.op->H_field) {
       pb.H = it.op->H_field;
@@ -863,6 +903,12 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
         // flux form: D_H = H0 div, Z_H = H0 curl
         launch_scale1(pb.DZ, 2 * n, it.op->H0, jb.st);
       }
+    }
+    pb.Hin = pb.H;
+    if (pb.H && jb.o.precision == REXII_PREC_MIXED) {
+      // the inner iterations read the depth in FP32
+      launch_to_f32(pb.H, hf32, n, jb.st);
+      pb.Hin = hf32;
     }
   }
   HIPCHK(hipGetLastError());

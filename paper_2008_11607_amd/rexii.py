@@ -52,10 +52,13 @@ class Report(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double),
                 ("stagnated", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
-                ("kernel_bytes", ctypes.c_double)]
+                ("kernel_bytes", ctypes.c_double), ("step_ms", ctypes.c_double * 6),
+                ("u1_bytes", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["step_ms"] = list(d["step_ms"])
+        return d
 
 
 EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",

@@ -404,32 +404,52 @@ __device__ __forceinline__ WorkHead load_work_head(const Eng& e) {
   return h;
 }
 
-// (slot, tile) of position pos: when every working slot has the same tile
-// count, the slot follows by one division (and, if every slot works, with no
-// load at all); else one load from the position table.
-__device__ __forceinline__ Item item_of(const Eng& e, int pos, const WorkHead& h) {
-  Item it;
-  if (h.un > 0) {
-    const int k = pos / h.un;
-    it.slot = h.ident ? k : ldu(&e.work[2 + k]);
-    it.tile = pos - k * h.un;
-    return it;
+// Work mapping.  A pass kernel's blocks take loop indices w = b, b + G, ...
+// (G a multiple of 8), and index w runs on XCD w % 8 (workgroups are dealt
+// to the XCDs in turn).  When every working slot has the same tile count
+// un, XCD x takes band x of every slot: the tiles x bs .. (x + 1) bs - 1
+// (bs = ceil(un / 8), row-major tiles, so a band is a run of tile rows whose
+// halo rows stay in that XCD's L2 except at the band edges).  Every XCD then
+// holds an equal share of every slot, whatever state each slot is in.  With
+// differing tile counts the position table is cut into 8 contiguous ranges.
+struct WorkMap {
+  WorkHead h;
+  int per;  // loop indices per XCD
+  int bs;   // band of tiles per slot and XCD (uniform case), else 0
+};
+__device__ __forceinline__ WorkMap load_work_map(const Eng& e) {
+  WorkMap m;
+  m.h = load_work_head(e);
+  if (m.h.un > 0) {
+    m.bs = (m.h.un + 7) >> 3;
+    m.per = (m.h.total / m.h.un) * m.bs;
+  } else {
+    m.bs = 0;
+    m.per = (m.h.total + 7) >> 3;
   }
+  return m;
+}
+// loop bound: indices 0 .. span - 1
+__device__ __forceinline__ int work_span(const WorkMap& m) { return 8 * m.per; }
+// (slot, tile) of loop index w; false when w maps to no item
+__device__ __forceinline__ bool work_item(const Eng& e, const WorkMap& m, int w, Item& it) {
+  const int x = w & 7, i = w >> 3;
+  if (m.bs > 0) {
+    const int k = i / m.bs;
+    const int t = x * m.bs + (i - k * m.bs);
+    if (t >= m.h.un) return false;
+    it.slot = m.h.ident ? k : ldu(&e.work[2 + k]);
+    it.tile = t;
+    return true;
+  }
+  const int pos = x * m.per + i;
+  if (pos >= m.h.total) return false;
   const unsigned long long v = uni(static_cast<unsigned long long>(__hip_atomic_load(
       reinterpret_cast<const unsigned long long*>(e.items + pos), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
   it.slot = int(v & 0xffffffffull);
   it.tile = int(v >> 32);
-  return it;
+  return true;
 }
-
-// XCD-major numbering: loop index w (block b handles w = b, b + G, ...)
-// runs on XCD w % 8 when G % 8 == 0; map it to position
-// (w % 8) * ceil(total / 8) + w / 8 so each XCD owns a contiguous range.
-#ifdef REXII_NO_XCD
-__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return w; }
-#else
-__device__ __forceinline__ int xcd_pos(int w, int per_xcd) { return (w & 7) * per_xcd + (w >> 3); }
-#endif
 
 }  // namespace rexii
 

@@ -451,13 +451,11 @@ template <typename T>
 __device__ __forceinline__ void cocg_pass(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[PassLds<T>::kBytes];
   __shared__ double red[4 * kNDots];
-  const WorkHead h = load_work_head(e);
-  const int total = h.total;
-  const int per = (total + 7) >> 3;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, h);
+  const WorkMap m = load_work_map(e);
+  const int span = work_span(m);
+  for (int w = blockIdx.x; w < span; w += gridDim.x) {
+    Item it;
+    if (!work_item(e, m, w, it)) continue;
     const SlotCtl c = load_ctl(&e.slots[it.slot]);
     if (c.status == kInner) {
       T a[kNDots];

@@ -388,13 +388,11 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_s(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
   __shared__ double red[4 * 8];
-  const WorkHead h = load_work_head(e);
-  const int total = h.total;
-  const int per = (total + 7) >> 3;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, h);
+  const WorkMap m = load_work_map(e);
+  const int span = work_span(m);
+  for (int w = blockIdx.x; w < span; w += gridDim.x) {
+    Item it;
+    if (!work_item(e, m, w, it)) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kInner) continue;
     double acc[8];
@@ -413,13 +411,11 @@ struct LdsU1 {
 template <typename T>
 __device__ __forceinline__ void bcg_pass_u1(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
-  const WorkHead h = load_work_head(e);
-  const int total = h.total;
-  const int per = (total + 7) >> 3;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, h);
+  const WorkMap m = load_work_map(e);
+  const int span = work_span(m);
+  for (int w = blockIdx.x; w < span; w += gridDim.x) {
+    Item it;
+    if (!work_item(e, m, w, it)) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status == kInner)
       bcg_u1_inner<T>(e, c, it.slot, it.tile, lds);
@@ -447,13 +443,11 @@ __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
   }
   __syncthreads();
   if (!any) return;
-  const WorkHead h = load_work_head(e);
-  const int total = h.total;
-  const int per = (total + 7) >> 3;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, h);
+  const WorkMap m = load_work_map(e);
+  const int span = work_span(m);
+  for (int w = blockIdx.x; w < span; w += gridDim.x) {
+    Item it;
+    if (!work_item(e, m, w, it)) continue;
     if (st[it.slot] != kOuterPending && st[it.slot] != kInnerDone) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     double acc[2] = {0.0, 0.0};
@@ -466,13 +460,11 @@ template <typename T>
 __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
   __shared__ double red[4 * 2];
-  const WorkHead h = load_work_head(e);
-  const int total = h.total;
-  const int per = (total + 7) >> 3;
-  for (int w = blockIdx.x; w < 8 * per; w += gridDim.x) {
-    const int pos = xcd_pos(w, per);
-    if (pos >= total) continue;
-    const Item it = item_of(e, pos, h);
+  const WorkMap m = load_work_map(e);
+  const int span = work_span(m);
+  for (int w = blockIdx.x; w < span; w += gridDim.x) {
+    Item it;
+    if (!work_item(e, m, w, it)) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kInner && c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};

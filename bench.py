@@ -43,22 +43,35 @@ def workload():
     return f, rho, TRHO / rho
 
 
-# HBM bytes per launch of k_pass_f32 on this workload (128 slots), from two
-# rocprofv3 counter runs (FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000, scales
-# from a 1 GiB copy); valid only for the kernel sources they were taken on.
-TRAFFIC = {"bytes_per_launch": 1513731604.9, "fetch_kib": 370955.06, "write_kib": 736361.16,
-           "sources_sha256": "67aa3bff4158fa358220f0b51bf3fa8a9a315b60717eb2425f7a5b4400f6cec2"}
-KERNEL_SOURCES = ["kernels.hip", "kernels.h", "device_util.h"]
+# HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0000,
+# WRITE_SIZE x 1.0000, scales from a 1 GiB copy): k_pass_f32 on the 512^2
+# workload (128 slots) and k_bcg_u1_f32 on the 2048^2 depth-field workload
+# (one state, 8 slots); valid only for the kernel sources they were taken on.
+TRAFFIC = {
+    "k_pass_f32": {"bytes_per_launch": 1554939095.5, "fetch_kib": 391076.15, "write_kib": 736361.63,
+                   "sources": ["kernels.hip", "kernels.h", "device_util.h"],
+                   "sources_sha256": "ba6e68286d0eab6292779c3f5c37ff14885cd8ac619d7031e1d6aee6a9e7457a"},
+    "k_bcg_u1_f32": {"bytes_per_launch": 1675776634.6, "fetch_kib": 510809.21, "write_kib": 614906.66,
+                     "sources": ["kernels_vh.hip", "kernels.h", "device_util.h"],
+                     "sources_sha256": "76613f81057819cfe44c945dc9732c08c786f4356b33268e4e22c3eccee9d3d8"},
+}
 
 
-def traffic_if_current():
-    """The counter-based traffic when the pass kernel's sources are unchanged, else None."""
+def sources_sha256(files):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2008_11607_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC["bytes_per_launch"] if h.hexdigest() == TRAFFIC["sources_sha256"] else None
+    return h.hexdigest()
+
+
+def traffic_if_current(kernel):
+    """The counter-based traffic of a kernel when its sources are unchanged, else None."""
+    t = TRAFFIC[kernel]
+    if t["sources_sha256"] is None or sources_sha256(t["sources"]) != t["sources_sha256"]:
+        return None
+    return t["bytes_per_launch"]
 
 
 def golden(name):
@@ -150,6 +163,9 @@ def run_varh2048(args):
     k_l = reps[0]["kernel_launches"]
     k_ms = reps[0]["kernel_ms"]
     k_b = reps[0]["kernel_bytes"]
+    step = reps[0]["step_ms"]
+    u1_ms, u1_b = step[1], reps[0]["u1_bytes"]
+    u1_gbs = (u1_b / k_l) / (u1_ms / k_l * 1e-3) / 1e9
     out = {"metric": METRIC, "value": len(fs) * D * D * P / el, "unit": "grid-pt·pole solves/s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": 1000 * el, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
@@ -159,11 +175,17 @@ def run_varh2048(args):
            "rel_l2_vs_oracle_samples": err, "w_energy_drift": wE,
            "krylov": {"total_iters": sum(r["total_iters"] for r in reps), "max_iters": max(r["max_iters"] for r in reps),
                       "not_converged": sum(r["not_converged"] for r in reps), "stagnated": sum(r["stagnated"] for r in reps)},
-           "roofline": {"bound": "hbm", "kernel": "BiCGStab iteration (k_bcg_outer, k_bcg_u1, k_bcg_u2, k_bcg_s + scalars)",
-                        "achieved": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "avg_launch_ms": k_ms / k_l, "launches": k_l, "alg_bytes_per_launch": k_b / k_l,
-                        "kernel_time_share": k_ms * 1e-3 / el}}
+           "roofline": {"bound": "hbm", "kernel": "k_bcg_u1_f32", "achieved": u1_gbs, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": u1_gbs / HBM_PEAK_GBS, "traffic": traffic_if_current("k_bcg_u1_f32"),
+                        "avg_launch_ms": u1_ms / k_l, "launches": k_l, "alg_bytes_per_launch": u1_b / k_l,
+                        "kernel_time_share": u1_ms * 1e-3 / el},
+           "iteration": {"kernels": "k_bcg_outer, k_bcg_u1, k_bcg_u2, k_bcg_scalars_u, k_bcg_s, k_bcg_scalars_s",
+                         "achieved_gbs": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9,
+                         "frac": (k_b / k_l) / (k_ms / k_l * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes_per_step": k_b / k_l, "avg_step_ms": k_ms / k_l, "steps": k_l,
+                         "ms_by_kernel": dict(zip(["outer", "u1", "u2", "scalars_u", "s", "scalars_s"],
+                                                  [round(x, 1) for x in step])),
+                         "time_share": k_ms * 1e-3 / el}}
     if not args.no_fp64:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -314,7 +336,7 @@ def main():
                    "pole_tol": reps[0]["pole_tol"], "max_rel_residual": reps[0]["max_rel_residual"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass_f32", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_if_current(), "avg_launch_ms": k_ms / k_l, "launches": k_l,
+                     "traffic": traffic_if_current("k_pass_f32"), "avg_launch_ms": k_ms / k_l, "launches": k_l,
                      "alg_bytes_per_launch": k_b / k_l,
                      "kernel_time_share": k_ms * 1e-3 / el},
     }

@@ -575,22 +575,66 @@ __device__ __forceinline__ bool finished(int st) {
   return st == kDone || st == kFailMaxIter || st == kFailBreakdown;
 }
 
+// Exclusive prefix sum of one int per thread over a block of kSchedNT
+// threads (4 wavefronts); *total receives the block total.
+constexpr int kSchedNT = 256;
+constexpr int kSchedPer = kMaxSlots / kSchedNT;  // slots per thread
+__device__ __forceinline__ int block_scan_excl(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();  // sh free
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  int off = 0;
+  for (int k = 0; k < wid; ++k) off += sh[k];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  return off + x - v;
+}
+
+// Finished slots, in index order, into list[0 .. *n) (whole block).
+__device__ __forceinline__ void finished_slots(const Eng& e, int* list, int* sh, int* n) {
+  int st[kSchedPer];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j) {
+    const int s = threadIdx.x * kSchedPer + j;
+    st[j] = (s < e.B) ? ldc(&e.slots[s].status) : kIdle;
+    cnt += finished(st[j]) ? 1 : 0;
+  }
+  int pos = block_scan_excl(cnt, sh, n);
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j)
+    if (finished(st[j])) list[pos++] = threadIdx.x * kSchedPer + j;
+  __syncthreads();
+}
+
 // Finished slots: A[inst] += Re(c_j x64) (or copy x64 out), then x64 = 0.
-// Each point walks the slots in index order.
-__global__ void k_retire(Eng e) {
+// Each point walks the finished slots in index order.
+__global__ __launch_bounds__(kSchedNT) void k_retire(Eng e) {
   if (ldc(&e.counter[3]) == 0) return;  // nothing finished in the previous chunk
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < e.cap; i += gridDim.x * blockDim.x) {
-    for (int s = 0; s < e.B; ++s) {
-      const Slot* S = &e.slots[s];
-      if (!finished(ldc(&S->status))) continue;
-      const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
-      const int n = I.nx * I.ny;
-      if (i >= n) continue;
+  __shared__ int list[kMaxSlots];
+  __shared__ int sh[4];
+  int nfin = 0;
+  finished_slots(e, list, sh, &nfin);
+  for (int q = 0; q < nfin; ++q) {
+    const int s = list[q];
+    const Slot* S = &e.slots[s];
+    const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
+    const int n = I.nx * I.ny;
+    // the last inner correction d is still to be added (once the solve has
+    // run an inner round)
+    const bool add_d = ldc(&S->rounds) >= 2 && ldc(&S->discard) == 0;
+    const int sv = ldc(&S->solve);
+    const double2 c0 = ldc(&e.solves[sv].c0), c1 = ldc(&e.solves[sv].c1), c2 = ldc(&e.solves[sv].c2);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
       double2* xp = e.x64 + size_t(s) * e.cap + i;
       double2 x = *xp;
-      // the last inner correction d is still to be added (once the solve
-      // has run an inner round)
-      if (ldc(&S->rounds) >= 2 && ldc(&S->discard) == 0) {
+      if (add_d) {
         if (e.d_is_f32) {
           const float2 dv = reinterpret_cast<const float2*>(e.d)[size_t(s) * e.cap + i];
           x.x += double(dv.x);
@@ -601,9 +645,7 @@ __global__ void k_retire(Eng e) {
           x.y += dv.y;
         }
       }
-      const int sv = ldc(&S->solve);
       if (e.yout) e.yout[size_t(sv) * e.cap + i] = x;
-      const double2 c0 = ldc(&e.solves[sv].c0), c1 = ldc(&e.solves[sv].c1), c2 = ldc(&e.solves[sv].c2);
       I.A[i] += c0.x * x.x - c0.y * x.y;
       I.A[n + i] += c1.x * x.x - c1.y * x.y;
       I.A[2 * n + i] += c2.x * x.x - c2.y * x.y;
@@ -612,115 +654,166 @@ __global__ void k_retire(Eng e) {
   }
 }
 
-__device__ void assign_serial(Eng& e, int* working_out, int* uniform_out);
-
-// Thread 0: record finished solves, hand out the next ones in queue order,
-// rebuild the tile table of working slots and the host-visible counts.  Then
-// the whole block writes the (slot, tile) table of the work positions when
-// the working slots' tile counts differ.
-__global__ __launch_bounds__(256) void k_assign(Eng e) {
-  __shared__ int sh_working, sh_uniform;
-  if (threadIdx.x == 0) assign_serial(e, &sh_working, &sh_uniform);
-  __syncthreads();
-  if (sh_uniform > 0) return;
-  for (int k = 0; k < sh_working; ++k) {
-    const int s = e.work[2 + k];
-    const int start = e.tile_start[s];
-    const int nb = e.slots[s].nblk;
-    for (int t = threadIdx.x; t < nb; t += blockDim.x) e.items[start + t] = make_int2(s, t);
-  }
+// Next solve of the queue into slot s.
+__device__ __forceinline__ void assign_solve(Eng& e, int s, int next) {
+  Slot* S = &e.slots[s];
+  const SolveDev* D = &e.solves[next];
+  const int dinst = ldc(&D->inst);
+  S->zeta = ldc(&D->zeta);
+  S->a1 = ldc(&D->a1);
+  S->a2 = ldc(&D->a2);
+  S->gamma = ldc(&D->gamma);
+  S->sc = ldc(&D->sc);
+  S->omega = make_double2(0.0, 0.0);
+  S->tol2 = ldc(&D->tol2);
+  S->rr = S->alpha = S->beta = make_double2(0.0, 0.0);
+  S->bn2 = S->rn2 = S->prev_rn2 = S->in_tol2 = 0.0;
+  S->status = kOuterPending;
+  S->parity = 0;
+  S->prime = 0;
+  S->it_total = S->it_inner = S->rounds = 0;
+  S->solve = next;
+  S->inst = dinst;
+  const Inst* I = &e.inst[dinst];
+  S->nx = ldc(&I->nx);
+  S->ny = ldc(&I->ny);
+  S->tiles_x = ldc(&I->tiles_x);
+  S->nblk = ldc(&I->nblk);
+  S->cx = ldc(&I->cx);
+  S->cy = ldc(&I->cy);
+  S->cxy = ldc(&I->cxy);
+  S->H = ldc_ptr(&I->H);
+  S->Hin = ldc_ptr(&I->Hin);
+  S->eta0 = ldc_ptr(&I->eta0);
+  S->D0 = ldc_ptr(&I->D0);
+  S->Z0 = ldc_ptr(&I->Z0);
+  S->stagnated = 0;
+  S->discard = 0;
 }
 
-__device__ void assign_serial(Eng& e, int* working_out, int* uniform_out) {
-  int next = ldc(e.next);
-  int working = 0;
-  int acc = 0;
-  int uniform = 0;
+// One block: record finished solves, hand out the next ones in queue order
+// (the k-th idle slot in index order takes queue entry next + k), rebuild
+// the work list (working slots in index order, their first tile positions,
+// the common tile count if any) and the host-visible counts; then write
+// the (slot, tile) table of the work positions when tile counts differ.
+// Every slot is handled by its own thread; the orders are those of a
+// sequential walk over the slots.
+__global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
+  __shared__ int sh[4];
+  __shared__ int s_nb[kMaxSlots];
+  __shared__ int s_ts[kMaxSlots];
+  __shared__ int s_min, s_max;
+  const int next0 = ldc(e.next);
 #ifdef REXII_DEBUG_CHECKS
-  {
+  if (threadIdx.x == 0) {
     int fin = 0;
     for (int s = 0; s < e.B; ++s) fin += finished(ldc(&e.slots[s].status)) ? 1 : 0;
     if (fin != ldc(&e.counter[3])) atomicAdd(&e.dbg[1], 1);
     if (fin > 0 && ldc(&e.counter[3]) == 0) atomicAdd(&e.dbg[2], 1);
   }
+  __syncthreads();
 #endif
-  for (int s = 0; s < e.B; ++s) {
+  if (threadIdx.x == 0) {
+    s_min = 1 << 30;
+    s_max = 0;
+  }
+  int st[kSchedPer];
+  int nidle = 0;
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j) {
+    const int s = threadIdx.x * kSchedPer + j;
+    st[j] = -1;  // no such slot
+    if (s >= e.B) continue;
     Slot* S = &e.slots[s];
-    int status = ldc(&S->status);
-    if (finished(status)) {
-      SolveStat& st = e.stats[ldc(&S->solve)];
-      st.rn2 = ldc(&S->rn2);
-      st.bn2 = ldc(&S->bn2);
-      st.it_total = ldc(&S->it_total);
-      st.rounds = ldc(&S->rounds);
-      st.status = status;
-      st.stagnated = ldc(&S->stagnated);
-      status = kIdle;
+    st[j] = ldc(&S->status);
+    if (finished(st[j])) {
+      SolveStat& ss = e.stats[ldc(&S->solve)];
+      ss.rn2 = ldc(&S->rn2);
+      ss.bn2 = ldc(&S->bn2);
+      ss.it_total = ldc(&S->it_total);
+      ss.rounds = ldc(&S->rounds);
+      ss.status = st[j];
+      ss.stagnated = ldc(&S->stagnated);
+      st[j] = kIdle;
       S->status = kIdle;
     }
-    if (status == kIdle && next < e.S) {
-      const SolveDev* D = &e.solves[next];
-      const int dinst = ldc(&D->inst);
-      S->zeta = ldc(&D->zeta);
-      S->a1 = ldc(&D->a1);
-      S->a2 = ldc(&D->a2);
-      S->gamma = ldc(&D->gamma);
-      S->sc = ldc(&D->sc);
-      S->omega = make_double2(0.0, 0.0);
-      S->tol2 = ldc(&D->tol2);
-      S->rr = S->alpha = S->beta = make_double2(0.0, 0.0);
-      S->bn2 = S->rn2 = S->prev_rn2 = S->in_tol2 = 0.0;
-      S->status = kOuterPending;
-      S->parity = 0;
-      S->prime = 0;
-      S->it_total = S->it_inner = S->rounds = 0;
-      S->solve = next;
-      S->inst = dinst;
-      {
-        const Inst* I = &e.inst[dinst];
-        S->nx = ldc(&I->nx);
-        S->ny = ldc(&I->ny);
-        S->tiles_x = ldc(&I->tiles_x);
-        S->nblk = ldc(&I->nblk);
-        S->cx = ldc(&I->cx);
-        S->cy = ldc(&I->cy);
-        S->cxy = ldc(&I->cxy);
-        S->H = ldc_ptr(&I->H);
-        S->Hin = ldc_ptr(&I->Hin);
-        S->eta0 = ldc_ptr(&I->eta0);
-        S->D0 = ldc_ptr(&I->D0);
-        S->Z0 = ldc_ptr(&I->Z0);
+    nidle += (st[j] == kIdle) ? 1 : 0;
+  }
+  int total_idle = 0;
+  int rank = block_scan_excl(nidle, sh, &total_idle);
+  int nwork = 0, ntiles = 0;
+  int nb[kSchedPer];
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j) {
+    const int s = threadIdx.x * kSchedPer + j;
+    nb[j] = 0;
+    if (st[j] < 0) continue;
+    if (st[j] == kIdle) {
+      const int q = next0 + rank++;
+      if (q < e.S) {
+        assign_solve(e, s, q);
+        st[j] = kOuterPending;
+        nb[j] = ldc(&e.inst[ldc(&e.solves[q].inst)].nblk);
       }
-      S->stagnated = 0;
-      S->discard = 0;
-      status = kOuterPending;
-      ++next;
+    } else {
+      nb[j] = ldc(&e.inst[ldc(&e.slots[s].inst)].nblk);
     }
-    e.tile_start[s] = acc;
-    if (status != kIdle) {
-      const int nb = ldc(&e.inst[ldc(&S->inst)].nblk);
-      acc += nb;
-      e.work[2 + working] = s;
-      uniform = (working == 0) ? nb : (uniform == nb ? nb : 0);
-      ++working;
+    if (st[j] != kIdle) {
+      ++nwork;
+      ntiles += nb[j];
     }
   }
-  e.tile_start[e.B] = acc;
-  e.work[0] = acc;
-  e.work[1] = uniform | ((working == e.B && uniform > 0) ? kWorkIdentity : 0);
-  *e.next = next;
-  e.counter[0] = working + (next < e.S ? 1 : 0);
-  e.counter[1] = next;
-  *working_out = working;
-  *uniform_out = uniform;
+  const int next = min(next0 + total_idle, e.S);
+  int working = 0, total = 0;
+  int wpos = block_scan_excl(nwork, sh, &working);
+  int tpos = block_scan_excl(ntiles, sh, &total);
+  int lmin = 1 << 30, lmax = 0;
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j) {
+    const int s = threadIdx.x * kSchedPer + j;
+    if (st[j] < 0) continue;
+    e.tile_start[s] = tpos;
+    s_ts[s] = tpos;
+    s_nb[s] = (st[j] != kIdle) ? nb[j] : 0;
+    if (st[j] != kIdle) {
+      e.work[2 + wpos++] = s;
+      tpos += nb[j];
+      lmin = min(lmin, nb[j]);
+      lmax = max(lmax, nb[j]);
+    }
+  }
+  atomicMin(&s_min, lmin);
+  atomicMax(&s_max, lmax);
+  __syncthreads();
+  const int uniform = (working > 0 && s_min == s_max) ? s_max : 0;
+  if (threadIdx.x == 0) {
+    e.tile_start[e.B] = total;
+    e.work[0] = total;
+    e.work[1] = uniform | ((working == e.B && uniform > 0) ? kWorkIdentity : 0);
+    *e.next = next;
+    e.counter[0] = working + (next < e.S ? 1 : 0);
+    e.counter[1] = next;
+  }
+  if (uniform > 0) return;
+  for (int s = 0; s < e.B; ++s) {
+    const int n = s_nb[s];
+    const int start = s_ts[s];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) e.items[start + t] = make_int2(s, t);
+  }
 }
 
 // Count of slots that finished during the chunk (read by the next retire).
-__global__ void k_count_finished(Eng e) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__global__ __launch_bounds__(kSchedNT) void k_count_finished(Eng e) {
+  __shared__ int sh[4];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kSchedPer; ++j) {
+    const int s = threadIdx.x * kSchedPer + j;
+    if (s < e.B) cnt += finished(ldc(&e.slots[s].status)) ? 1 : 0;
+  }
   int fin = 0;
-  for (int s = 0; s < e.B; ++s) fin += finished(ldc(&e.slots[s].status)) ? 1 : 0;
-  e.counter[3] = fin;
+  (void)block_scan_excl(cnt, sh, &fin);
+  if (threadIdx.x == 0) e.counter[3] = fin;
 }
 
 // ---------------------------------------------------------------------------
@@ -912,13 +1005,13 @@ void launch_pass_scalars(const Eng& e, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_scalars, dim3(e.B), dim3(kSNT), 0, s, e);
 }
 void launch_retire(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(256), 0, s, e);
+  hipLaunchKernelGGL(k_retire, dim3(flat_blocks(size_t(e.cap))), dim3(kSchedNT), 0, s, e);
 }
 void launch_assign(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_assign, dim3(1), dim3(256), 0, s, e);
+  hipLaunchKernelGGL(k_assign, dim3(1), dim3(kSchedNT), 0, s, e);
 }
 void launch_count_finished(const Eng& e, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_finished, dim3(1), dim3(64), 0, s, e);
+  hipLaunchKernelGGL(k_count_finished, dim3(1), dim3(kSchedNT), 0, s, e);
 }
 void launch_fill_zero(double* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(flat_blocks(n)), dim3(256), 0, s, p, n);

@@ -387,8 +387,9 @@ struct Item {
 
 constexpr int kWorkIdentity = 1 << 30;
 
-// Head of the work list: item count, common tile count, identity flag (one
-// 8-byte coherent load).
+// Head of the work list (one 8-byte coherent load): list length (the
+// working tiles when they share one tile count un, else the length of the 8
+// band lists together), un (0 when counts differ), identity flag.
 struct WorkHead {
   int total, un;
   bool ident;
@@ -411,7 +412,8 @@ __device__ __forceinline__ WorkHead load_work_head(const Eng& e) {
 // (bs = ceil(un / 8), row-major tiles, so a band is a run of tile rows whose
 // halo rows stay in that XCD's L2 except at the band edges).  Every XCD then
 // holds an equal share of every slot, whatever state each slot is in.  With
-// differing tile counts the position table is cut into 8 contiguous ranges.
+// differing tile counts the assignment kernel writes the same bands as 8
+// lists of (slot, tile) entries of equal length, list x for XCD x.
 struct WorkMap {
   WorkHead h;
   int per;  // loop indices per XCD
@@ -425,7 +427,7 @@ __device__ __forceinline__ WorkMap load_work_map(const Eng& e) {
     m.per = (m.h.total / m.h.un) * m.bs;
   } else {
     m.bs = 0;
-    m.per = (m.h.total + 7) >> 3;
+    m.per = m.h.total >> 3;  // 8 band lists of equal length
   }
   return m;
 }
@@ -442,13 +444,12 @@ __device__ __forceinline__ bool work_item(const Eng& e, const WorkMap& m, int w,
     it.tile = t;
     return true;
   }
-  const int pos = x * m.per + i;
-  if (pos >= m.h.total) return false;
+  const size_t pos = size_t(x) * m.per + i;
   const unsigned long long v = uni(static_cast<unsigned long long>(__hip_atomic_load(
       reinterpret_cast<const unsigned long long*>(e.items + pos), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
   it.slot = int(v & 0xffffffffull);
   it.tile = int(v >> 32);
-  return true;
+  return it.slot >= 0;
 }
 
 }  // namespace rexii

@@ -132,13 +132,12 @@ struct Eng {
   const SolveDev* solves;// [S]
   SolveStat* stats;      // [S]
   int* next;             // [1] next solve to hand out
-  int* tile_start;       // [B + 1] exclusive prefix of tiles of working slots
   int* work;             // [B + 2]: [0] work items (tiles of working slots),
                          // [1] their common tile count (0 if they differ;
                          // bit 30 set when every slot works, so the list is
                          // 0, 1, ..., B-1), [2..] working slot indices
   int* counter;          // [4] host-visible counts
-  int2* items;           // [B * cap_blk] (slot, tile) of each work position
+  int2* items;           // [B * (cap_blk + 7)] (slot, tile): 8 band lists when tile counts differ
                          // (filled when the working slots' tile counts differ)
   double* part;          // [B][cap_blk][kNDots]
   double2* x64;          // [B][cap]

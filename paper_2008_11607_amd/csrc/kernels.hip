@@ -693,15 +693,16 @@ __device__ __forceinline__ void assign_solve(Eng& e, int s, int next) {
 
 // One block: record finished solves, hand out the next ones in queue order
 // (the k-th idle slot in index order takes queue entry next + k), rebuild
-// the work list (working slots in index order, their first tile positions,
-// the common tile count if any) and the host-visible counts; then write
-// the (slot, tile) table of the work positions when tile counts differ.
+// the work list (working slots in index order, the common tile count if
+// any) and the host-visible counts; then, when tile counts differ, write
+// the (slot, tile) table of the work positions as 8 band lists (one per
+// XCD).
 // Every slot is handled by its own thread; the orders are those of a
 // sequential walk over the slots.
 __global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
   __shared__ int sh[4];
   __shared__ int s_nb[kMaxSlots];
-  __shared__ int s_ts[kMaxSlots];
+  __shared__ int s_bo[kMaxSlots];
   __shared__ int s_min, s_max;
   const int next0 = ldc(e.next);
 #ifdef REXII_DEBUG_CHECKS
@@ -741,7 +742,7 @@ __global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
   }
   int total_idle = 0;
   int rank = block_scan_excl(nidle, sh, &total_idle);
-  int nwork = 0, ntiles = 0;
+  int nwork = 0, ntiles = 0, nband = 0;
   int nb[kSchedPer];
 #pragma unroll
   for (int j = 0; j < kSchedPer; ++j) {
@@ -761,23 +762,24 @@ __global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
     if (st[j] != kIdle) {
       ++nwork;
       ntiles += nb[j];
+      nband += (nb[j] + 7) >> 3;
     }
   }
   const int next = min(next0 + total_idle, e.S);
-  int working = 0, total = 0;
+  int working = 0, total = 0, per = 0;
   int wpos = block_scan_excl(nwork, sh, &working);
-  int tpos = block_scan_excl(ntiles, sh, &total);
+  (void)block_scan_excl(ntiles, sh, &total);
+  int bpos = block_scan_excl(nband, sh, &per);
   int lmin = 1 << 30, lmax = 0;
 #pragma unroll
   for (int j = 0; j < kSchedPer; ++j) {
     const int s = threadIdx.x * kSchedPer + j;
     if (st[j] < 0) continue;
-    e.tile_start[s] = tpos;
-    s_ts[s] = tpos;
+    s_bo[s] = bpos;
     s_nb[s] = (st[j] != kIdle) ? nb[j] : 0;
     if (st[j] != kIdle) {
       e.work[2 + wpos++] = s;
-      tpos += nb[j];
+      bpos += (nb[j] + 7) >> 3;
       lmin = min(lmin, nb[j]);
       lmax = max(lmax, nb[j]);
     }
@@ -787,18 +789,25 @@ __global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
   __syncthreads();
   const int uniform = (working > 0 && s_min == s_max) ? s_max : 0;
   if (threadIdx.x == 0) {
-    e.tile_start[e.B] = total;
-    e.work[0] = total;
+    // list length: the working tiles, or 8 band lists of per entries each
+    e.work[0] = (uniform > 0) ? total : 8 * per;
     e.work[1] = uniform | ((working == e.B && uniform > 0) ? kWorkIdentity : 0);
     *e.next = next;
     e.counter[0] = working + (next < e.S ? 1 : 0);
     e.counter[1] = next;
   }
   if (uniform > 0) return;
+  // band lists: list x holds band x of every working slot in slot order
+  // (tiles x bs .. x bs + bs - 1, bs = ceil(nb / 8)); positions past a
+  // slot's last tile hold slot -1
   for (int s = 0; s < e.B; ++s) {
     const int n = s_nb[s];
-    const int start = s_ts[s];
-    for (int t = threadIdx.x; t < n; t += blockDim.x) e.items[start + t] = make_int2(s, t);
+    if (n == 0) continue;
+    const int bs = (n + 7) >> 3, bo = s_bo[s];
+    for (int k = threadIdx.x; k < 8 * bs; k += blockDim.x) {
+      const int x = k / bs, j = k - x * bs, t = x * bs + j;
+      e.items[size_t(x) * per + bo + j] = (t < n) ? make_int2(s, t) : make_int2(-1, -1);
+    }
   }
 }
 

@@ -350,7 +350,7 @@ struct EngineSize {
 static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_B, int precision) {
   EngineSize z;
   size_t maxp = 0;
-  double wsum = 0.0;
+  int min_nb = 0;
   z.method = 0;
   for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
   for (Problem* p : probs) {
@@ -358,11 +358,12 @@ static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_
     const int nb = make_geo(p->pl.nx, p->pl.ny, z.method).nblk;
     z.cap_blk = std::max(z.cap_blk, nb);
     z.S += int(p->pl.solves.size());
-    wsum += double(nb) * double(p->pl.solves.size());
+    min_nb = (min_nb == 0) ? nb : std::min(min_nb, nb);
   }
-  // mean tile count in units of kTX x kTY tiles
-  const double mean_nblk =
-      (z.S > 0 ? wsum / z.S : double(std::max(1, z.cap_blk))) * ((z.method == 1) ? double(kTYB) / kTY : 1.0);
+  // the smallest problem's tile count, in units of kTX x kTY tiles: slots
+  // enough to fill the GPU while only the smallest problems are left (the
+  // queue runs the most expensive solves first); memory caps the count
+  const double mean_nblk = double(std::max(1, min_nb)) * ((z.method == 1) ? double(kTYB) / kTY : 1.0);
   z.cap = int(maxp);
   z.ninst = int(probs.size());
   z.eb = inner_elem_bytes(precision);
@@ -377,9 +378,9 @@ static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
   size_t b = 0;
   b += al256(z.B * sizeof(Slot)) + al256(z.ninst * sizeof(Inst));
   b += al256(z.S * sizeof(SolveDev)) + al256(z.S * sizeof(SolveStat));
-  b += al256(sizeof(int)) + al256((z.B + 1) * sizeof(int)) + al256((z.B + 2) * sizeof(int)) + al256(4 * sizeof(int));
+  b += al256(sizeof(int)) + al256((z.B + 2) * sizeof(int)) + al256(4 * sizeof(int));
   b += al256(size_t(z.B) * z.cap_blk * kNDots * sizeof(double));
-  b += al256(size_t(z.B) * z.cap_blk * sizeof(int2));
+  b += al256(size_t(z.B) * (z.cap_blk + 7) * sizeof(int2));
   b += al256(size_t(z.B) * z.cap * 16);
   b += size_t(z.nvec) * al256(size_t(z.B) * z.cap * z.eb);
   if (keep_solutions) b += al256(size_t(z.S) * z.cap * 16);
@@ -445,10 +446,9 @@ struct Engine {
     e.solves = dsol;
     e.stats = ar.take<SolveStat>(z.S);
     e.next = ar.take<int>(1);
-    e.tile_start = ar.take<int>(z.B + 1);
     e.work = ar.take<int>(z.B + 2);
     e.counter = ar.take<int>(4);
-    e.items = ar.take<int2>(size_t(z.B) * z.cap_blk);
+    e.items = ar.take<int2>(size_t(z.B) * (z.cap_blk + 7));   // 8 band lists of sum ceil(nb / 8) entries
     e.part = ar.take<double>(size_t(z.B) * z.cap_blk * kNDots);
     e.x64 = ar.take<double2>(size_t(z.B) * z.cap);
     e.d = ar.take<char>(size_t(z.B) * z.cap * z.eb);
@@ -526,7 +526,6 @@ struct Engine {
     // zero: slots (all idle), queue head, tile table, counters, x64
     launch_fill_zero(reinterpret_cast<double*>(e.slots), z.B * sizeof(Slot) / 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.next), 1, st);  // 8 bytes inside its 256-byte block
-    launch_fill_zero(reinterpret_cast<double*>(e.tile_start), (size_t(z.B + 1) * 4 + 7) / 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.work), (size_t(z.B + 2) * 4 + 7) / 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.counter), 2, st);
     launch_fill_zero(reinterpret_cast<double*>(e.dbg), 8, st);
@@ -1023,10 +1022,23 @@ static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o
       maxp = std::max(maxp, pb.n());
     }
   }
-  const int cands[] = {8, 16, 24, 32, 48, 64, 96, 128};
+  // candidates up to twice the default count (at least 128)
+  int hb = 0;
+  {
+    std::vector<Problem> pbs(items.size());
+    std::vector<Problem*> ptrs;
+    for (size_t i = 0; i < items.size(); ++i) {
+      if (items[i].skip || sizing_plan(items[i], o, pbs[i]) != REXII_OK) continue;
+      ptrs.push_back(&pbs[i]);
+    }
+    if (!ptrs.empty()) hb = engine_size(ptrs, 0, o.precision).B;
+  }
+  const int cap_b = std::max(128, 2 * hb);
+  const int cands[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
   int best = 0;
   double best_rate = 0.0;
   for (int B : cands) {
+    if (B > cap_b || B > kMaxSlots) break;
     if (size_t(B) * 2 > nsolves && B != cands[0]) break;  // keep the queue longer than the slots
     Job jb;
     jb.st = st;

@@ -132,10 +132,10 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const T* Hi = static_cast<const T*>(c.Hin);
   RowTile<T, 1, kTYB> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
   V hv[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j)
-    hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
+  for (int j = 0; j < kTYB / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
   __syncthreads();  // LDS of the previous work item is free
   sr.store(ST);
   hr.store(Hs);
@@ -189,14 +189,17 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const T* Hi = static_cast<const T*>(c.Hin);
   RowTile<T, 1, kTYB> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
-  size_t gi[kTYB / 4];
+  // rows are wavefront-uniform: row offsets in scalar registers, one
+  // column offset per thread
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
+  size_t ro[kTYB / 4];
   V pv[kTYB / 4], vv[kTYB / 4], dv[kTYB / 4];
 #pragma unroll
   for (int j = 0; j < kTYB / 4; ++j) {
-    gi[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
-    pv[j] = ps[gi[j]];
-    vv[j] = vs[gi[j]];
-    if (!first) dv[j] = nt_load(&d[gi[j]]);
+    ro[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx);
+    pv[j] = (ps + ro[j])[col];
+    vv[j] = (vs + ro[j])[col];
+    if (!first) dv[j] = nt_load(&(d + ro[j])[col]);
   }
   __syncthreads();  // LDS of the previous work item is free
   sr.store(ST);
@@ -213,13 +216,13 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
       const V upd = cadd(cmul(alpha, pv[j]), cmul(omega, sv));
       if (fold) {
         // once per round: the previous round's correction moves into x64
-        const V dold = d[gi[j]];
-        const double2 xo = x64[gi[j]];
-        x64[gi[j]] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
+        const V dold = (d + ro[j])[col];
+        const double2 xo = (x64 + ro[j])[col];
+        (x64 + ro[j])[col] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
       }
-      nt_store(first ? upd : cadd(dv[j], upd), &d[gi[j]]);
-      rd[gi[j]] = r1;
-      pd[gi[j]] = p1;
+      nt_store(first ? upd : cadd(dv[j], upd), &(d + ro[j])[col]);
+      (rd + ro[j])[col] = r1;
+      (pd + ro[j])[col] = p1;
     }
   }
 }
@@ -244,15 +247,15 @@ __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int s
   for (int j = 0; j < kTYB / 4; ++j) {
     const int gx = x0 + tx, gy = y0 + ty + 4 * j;
     if (gx < nx && gy < ny) {
-      const size_t g = size_t(gy) * nx + gx;
-      const V s = csub(rs[g], cmul(alpha, vs[g]));
-      const V upd = cadd(cmul(alpha, ps[g]), cmul(omega, s));
-      const V dold = d[g];
+      const size_t ro = size_t(gy) * size_t(nx);
+      const V s = csub((rs + ro)[gx], cmul(alpha, (vs + ro)[gx]));
+      const V upd = cadd(cmul(alpha, (ps + ro)[gx]), cmul(omega, s));
+      const V dold = (d + ro)[gx];
       if (fold) {
-        const double2 xo = x64[g];
-        x64[g] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
+        const double2 xo = (x64 + ro)[gx];
+        (x64 + ro)[gx] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
       }
-      d[g] = first ? upd : cadd(dold, upd);
+      (d + ro)[gx] = first ? upd : cadd(dold, upd);
     }
   }
 }
@@ -300,14 +303,15 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
       return c.H[g];
     });
   }
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
   double bre[kTYB / 4], bdz[kTYB / 4], bzz[kTYB / 4];
 #pragma unroll
   for (int j = 0; j < kTYB / 4; ++j) {
-    const size_t g = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
-    bre[j] = eta0[g];
+    const size_t ro = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx);
+    bre[j] = (eta0 + ro)[col];
     if (D0) {
-      bdz[j] = D0[g];
-      bzz[j] = Z0[g];
+      bdz[j] = (D0 + ro)[col];
+      bzz[j] = (Z0 + ro)[col];
     }
   }
   __syncthreads();  // LDS of the previous work item is free
@@ -321,7 +325,7 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
     const int ly = ty + 4 * j;
     const int gx = x0 + tx, gy = y0 + ly;
     if (gx < nx && gy < ny) {
-      const size_t g = size_t(gy) * nx + gx;
+      const size_t ro = size_t(gy) * size_t(nx);
       double2 bv = make_double2(bre[j], 0.0);
       if (D0) {
         bv.x += a1.x * bdz[j] + a2.x * bzz[j];
@@ -330,9 +334,9 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
       double2 rv = cmul(sc, bv);
       if (!zero_x) rv = csub(rv, kop<kBW, kHW, -1>(XT, Hs, ly + 2, tx + 2, c.cx, c.cy, c.cxy, c.gamma, c.zeta));
       const V rt = mk<V>(rv.x, rv.y);
-      rd[g] = rt;
-      pd[g] = rt;
-      rh[g] = rt;
+      (rd + ro)[gx] = rt;
+      (pd + ro)[gx] = rt;
+      (rh + ro)[gx] = rt;
       acc[0] += rv.x * rv.x + rv.y * rv.y;
       acc[1] += double(rt.x) * rt.x + double(rt.y) * rt.y;
     }
@@ -365,10 +369,10 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   const T* Hi = static_cast<const T*>(c.Hin);
   RowTile<T, 1, kTYB> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
+  const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
   V hv[kTYB / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j)
-    hv[j] = rh[size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big)];
+  for (int j = 0; j < kTYB / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
   __syncthreads();  // LDS of the previous work item is free
   pr.store(PT);
   hr.store(Hs);
@@ -378,7 +382,7 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V v1 = kop<kBW, kHW, -1>(PT, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
-      vd[size_t(y0 + ly) * nx + x0 + tx] = v1;
+      (vd + size_t(y0 + ly) * size_t(nx))[x0 + tx] = v1;
       cdot(acc, hv[j], v1);
     }
   }

@@ -331,9 +331,16 @@ struct RowTile {
     const int tx = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
+    // row offsets first (scalar, with the wrap's branches), then the loads
+    // in straight-line code, so that every load is issued before the first
+    // value is used (when the tile height is a multiple of 4 no row test
+    // is needed: w < 4)
+    size_t ro[kRows];
+#pragma unroll
+    for (int m = 0; m < kRows; ++m) ro[m] = size_t(wrapc(y0 - HALO + w + 4 * m, ny, big)) * size_t(nx);
 #pragma unroll
     for (int m = 0; m < kRows; ++m) {
-      if (w + 4 * m < kH) mainv[m] = f(size_t(wrapc(y0 - HALO + w + 4 * m, ny, big)) * size_t(nx), col);
+      if (kH % 4 == 0 || w + 4 * m < kH) mainv[m] = f(ro[m], col);
     }
     sly = int(threadIdx.x) / (2 * HALO);
     const int c = int(threadIdx.x) - sly * 2 * HALO;
@@ -346,7 +353,7 @@ struct RowTile {
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
 #pragma unroll
     for (int m = 0; m < kRows; ++m) {
-      if (w + 4 * m < kH) lds[(w + 4 * m) * kW + tx + HALO] = mainv[m];
+      if (kH % 4 == 0 || w + 4 * m < kH) lds[(w + 4 * m) * kW + tx + HALO] = mainv[m];
     }
     if (int(threadIdx.x) < kSide) lds[sly * kW + slx] = sidev;
   }

@@ -124,11 +124,9 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2, kTYB> sr;
-  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-    return csub(rs[g], cmul(alpha, vs[g]));
-  });
+  // pure loads first, then the tile whose values are formed as they
+  // arrive (s = r - alpha v), so that every load is in flight before the
+  // first wait
   const T* Hi = static_cast<const T*>(c.Hin);
   RowTile<T, 1, kTYB> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
@@ -136,6 +134,11 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   V hv[kTYB / 4];
 #pragma unroll
   for (int j = 0; j < kTYB / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
+  RowTile<V, 2, kTYB> sr;
+  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
+    return csub(rs[g], cmul(alpha, vs[g]));
+  });
   __syncthreads();  // LDS of the previous work item is free
   sr.store(ST);
   hr.store(Hs);
@@ -181,16 +184,12 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2, kTYB> sr;
-  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-    return csub(rs[g], cmul(alpha, vs[g]));
-  });
+  // pure loads first (depth tile, p, v, d; rows are wavefront-uniform, so
+  // row offsets sit in scalar registers and one column offset serves every
+  // load), then the tile formed as it arrives (s = r - alpha v)
   const T* Hi = static_cast<const T*>(c.Hin);
   RowTile<T, 1, kTYB> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
-  // rows are wavefront-uniform: row offsets in scalar registers, one
-  // column offset per thread
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
   size_t ro[kTYB / 4];
   V pv[kTYB / 4], vv[kTYB / 4], dv[kTYB / 4];
@@ -201,6 +200,11 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
     vv[j] = (vs + ro[j])[col];
     if (!first) dv[j] = nt_load(&(d + ro[j])[col]);
   }
+  RowTile<V, 2, kTYB> sr;
+  sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+    const size_t g = ro + col;
+    return csub(rs[g], cmul(alpha, vs[g]));
+  });
   __syncthreads();  // LDS of the previous work item is free
   sr.store(ST);
   hr.store(Hs);
@@ -286,23 +290,9 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   const double* Z0 = ldu_ptr(&S->Z0);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
-  // every load of the work item in one round: x = x64 + d (halo 2), the
-  // depth (halo 1) and the right-hand side fields (interior)
-  RowTile<double2, 2, kTYB> xr;
-  RowTile<double, 1, kTYB> hr;
-  if (!zero_x) {
-    xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-      const size_t g = ro + col;
-      const double2 xv = x64[g];
-      if (!use_d) return xv;
-      const V dv = d[g];
-      return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
-    });
-    hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-    const size_t g = ro + col;
-      return c.H[g];
-    });
-  }
+  // every load of the work item in one round: the right-hand side fields
+  // (interior) and the depth (halo 1) first, then x = x64 + d (halo 2),
+  // formed as it arrives (d is read even when discarded, then not used)
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
   double bre[kTYB / 4], bdz[kTYB / 4], bzz[kTYB / 4];
 #pragma unroll
@@ -313,6 +303,18 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
       bdz[j] = (D0 + ro)[col];
       bzz[j] = (Z0 + ro)[col];
     }
+  }
+  RowTile<double2, 2, kTYB> xr;
+  RowTile<double, 1, kTYB> hr;
+  if (!zero_x) {
+    hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return c.H[ro + col]; });
+    xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
+      const size_t g = ro + col;
+      const double2 xv = x64[g];
+      const V dv = d[g];
+      // a select, not a product: a discarded d may hold non-finite values
+      return use_d ? make_double2(xv.x + double(dv.x), xv.y + double(dv.y)) : xv;
+    });
   }
   __syncthreads();  // LDS of the previous work item is free
   if (!zero_x) {

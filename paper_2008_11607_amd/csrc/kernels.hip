@@ -371,13 +371,8 @@ __device__ __forceinline__ void cocg_residual(const Eng& e, const SlotCtl& c, in
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kPW) && (ny >= kPH);
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
-  TileRegs<double2, kNH, kNW> xr;
-  if (!zero_x) xr.fetch([&](int ly, int lx) {
-    const unsigned g = unsigned(wrapc(y0 - 2 + ly, ny, big)) * unsigned(nx) + unsigned(wrapc(x0 - 2 + lx, nx, big));
-    const V dv = d[g];
-    const double2 xv = x64[g];
-    return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
-  });
+  // the right-hand side fields first (pure loads), then x = x64 + d with
+  // halo 2, formed as it arrives: every load is issued before the first wait
   double bv[kTY / 4], dz[kTY / 4], zz[kTY / 4];
   size_t ro[kTY / 4];
 #pragma unroll
@@ -389,6 +384,13 @@ __device__ __forceinline__ void cocg_residual(const Eng& e, const SlotCtl& c, in
       zz[j] = (Z0 + ro[j])[col];
     }
   }
+  RowTile<double2, 2> xr;
+  if (!zero_x) xr.fetch(x0, y0, nx, ny, big, [&](size_t rofs, unsigned cx_) {
+    const size_t g = rofs + cx_;
+    const V dv = d[g];
+    const double2 xv = x64[g];
+    return make_double2(xv.x + double(dv.x), xv.y + double(dv.y));
+  });
   __syncthreads();  // LDS of the previous work item is free
   if (!zero_x) xr.store(XT);
   __syncthreads();

@@ -4,6 +4,8 @@
 #ifndef REXII_DEVICE_UTIL_H
 #define REXII_DEVICE_UTIL_H
 
+#include <cstddef>
+
 #include "kernels.h"
 
 namespace rexii {
@@ -118,6 +120,39 @@ template <typename X>
 __device__ __forceinline__ X ldu(const X* p) { return uni(ldc(p)); }
 template <typename P>
 __device__ __forceinline__ P* ldu_ptr(P* const* p) { return uni(ldc_ptr(p)); }
+
+// A slot record read by one vector load per wavefront: lane k loads the k-th
+// 8-byte word (a lane-dependent address, so the load never goes through the
+// scalar cache; the record was written by an earlier launch), and fields
+// are moved to scalar registers by readlane.  One request per cache line
+// instead of one per field keeps the record's lines from becoming a hot
+// spot when thousands of blocks read the same slot.
+constexpr int kSlotWords = int(sizeof(Slot) / 8);
+static_assert(sizeof(Slot) % 8 == 0 && kSlotWords <= 64, "slot record must fit one wavefront load");
+struct SlotWords {
+  unsigned long long w;
+  __device__ __forceinline__ explicit SlotWords(const Slot* S) {
+    const int lane = int(threadIdx.x & 63);
+    w = (lane < kSlotWords) ? reinterpret_cast<const unsigned long long*>(S)[lane] : 0ull;
+  }
+  __device__ __forceinline__ unsigned lo(int k) const {
+    return unsigned(__builtin_amdgcn_readlane(int(unsigned(w)), k));
+  }
+  __device__ __forceinline__ unsigned hi(int k) const {
+    return unsigned(__builtin_amdgcn_readlane(int(unsigned(w >> 32)), k));
+  }
+  __device__ __forceinline__ unsigned long long u64(int off) const {
+    return (static_cast<unsigned long long>(hi(off / 8)) << 32) | lo(off / 8);
+  }
+  __device__ __forceinline__ int i32(int off) const { return int((off % 8) ? hi(off / 8) : lo(off / 8)); }
+  __device__ __forceinline__ double f64(int off) const { return __longlong_as_double((long long)u64(off)); }
+  __device__ __forceinline__ double2 c64(int off) const { return make_double2(f64(off), f64(off + 8)); }
+  template <typename P>
+  __device__ __forceinline__ P* ptr(int off) const {
+    return reinterpret_cast<P*>(u64(off));
+  }
+};
+#define SLOT_OFF(f) int(offsetof(Slot, f))
 
 // Problem and solve tables are uploaded once per call into reused workspace
 // addresses: read them the same way.

@@ -69,19 +69,20 @@ struct SlotCtl {
 };
 
 __device__ __forceinline__ SlotCtl load_ctl(const Slot* S) {
+  const SlotWords sw(S);
   SlotCtl c;
-  c.status = ldu(&S->status);
-  c.par = ldu(&S->parity);
-  c.rounds = ldu(&S->rounds);
-  c.it_inner = ldu(&S->it_inner);
-  c.nx = ldu(&S->nx);
-  c.ny = ldu(&S->ny);
-  c.tiles_x = ldu(&S->tiles_x);
-  c.cx = ldu(&S->cx);
-  c.cy = ldu(&S->cy);
-  c.alpha = ldu(&S->alpha);
-  c.beta = ldu(&S->beta);
-  c.zeta = ldu(&S->zeta);
+  c.status = sw.i32(SLOT_OFF(status));
+  c.par = sw.i32(SLOT_OFF(parity));
+  c.rounds = sw.i32(SLOT_OFF(rounds));
+  c.it_inner = sw.i32(SLOT_OFF(it_inner));
+  c.nx = sw.i32(SLOT_OFF(nx));
+  c.ny = sw.i32(SLOT_OFF(ny));
+  c.tiles_x = sw.i32(SLOT_OFF(tiles_x));
+  c.cx = sw.f64(SLOT_OFF(cx));
+  c.cy = sw.f64(SLOT_OFF(cy));
+  c.alpha = sw.c64(SLOT_OFF(alpha));
+  c.beta = sw.c64(SLOT_OFF(beta));
+  c.zeta = sw.c64(SLOT_OFF(zeta));
   return c;
 }
 
@@ -362,12 +363,13 @@ __device__ __forceinline__ void cocg_residual(const Eng& e, const SlotCtl& c, in
   V* rc = reinterpret_cast<V*>(c.par ? e.r1 : e.r0) + base;
   V* pc = reinterpret_cast<V*>(c.par ? e.p1 : e.p0) + base;
   const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
-  // right-hand side b = eta0 + a1 D0 + a2 Z0
-  const Slot* S = &e.slots[slot];
-  const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2);
-  const double* eta0 = ldu_ptr(&S->eta0);
-  const double* D0 = ldu_ptr(&S->D0);
-  const double* Z0 = ldu_ptr(&S->Z0);
+  // right-hand side b = eta0 + a1 D0 + a2 Z0 (a second read of the slot
+  // record: the fields are needed only here)
+  const SlotWords sw(&e.slots[slot]);
+  const double2 a1 = sw.c64(SLOT_OFF(a1)), a2 = sw.c64(SLOT_OFF(a2));
+  const double* eta0 = sw.ptr<const double>(SLOT_OFF(eta0));
+  const double* D0 = sw.ptr<const double>(SLOT_OFF(D0));
+  const double* Z0 = sw.ptr<const double>(SLOT_OFF(Z0));
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kPW) && (ny >= kPH);
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));

@@ -68,7 +68,7 @@ __device__ __forceinline__ void cdot(double* acc, V a, V b) {
   acc[1] += double(a.x) * b.y - double(a.y) * b.x;
 }
 
-// Control fields of a slot, read in one round of coherent loads.
+// Control fields of a slot, from one wavefront load of its record.
 struct BcgCtl {
   int status, par, rounds, it_inner, discard, nx, ny, tiles_x;
   double cx, cy, cxy;
@@ -78,25 +78,26 @@ struct BcgCtl {
 };
 
 __device__ __forceinline__ BcgCtl load_bctl(const Slot* S) {
+  const SlotWords sw(S);
   BcgCtl c;
-  c.status = ldu(&S->status);
-  c.par = ldu(&S->parity);
-  c.rounds = ldu(&S->rounds);
-  c.it_inner = ldu(&S->it_inner);
-  c.discard = ldu(&S->discard);
-  c.nx = ldu(&S->nx);
-  c.ny = ldu(&S->ny);
-  c.tiles_x = ldu(&S->tiles_x);
-  c.cx = ldu(&S->cx);
-  c.cy = ldu(&S->cy);
-  c.cxy = ldu(&S->cxy);
-  c.H = ldu_ptr(&S->H);
-  c.Hin = ldu_ptr(&S->Hin);
-  c.alpha = ldu(&S->alpha);
-  c.beta = ldu(&S->beta);
-  c.omega = ldu(&S->omega);
-  c.gamma = ldu(&S->gamma);
-  c.zeta = ldu(&S->zeta);
+  c.status = sw.i32(SLOT_OFF(status));
+  c.par = sw.i32(SLOT_OFF(parity));
+  c.rounds = sw.i32(SLOT_OFF(rounds));
+  c.it_inner = sw.i32(SLOT_OFF(it_inner));
+  c.discard = sw.i32(SLOT_OFF(discard));
+  c.nx = sw.i32(SLOT_OFF(nx));
+  c.ny = sw.i32(SLOT_OFF(ny));
+  c.tiles_x = sw.i32(SLOT_OFF(tiles_x));
+  c.cx = sw.f64(SLOT_OFF(cx));
+  c.cy = sw.f64(SLOT_OFF(cy));
+  c.cxy = sw.f64(SLOT_OFF(cxy));
+  c.H = sw.ptr<const double>(SLOT_OFF(H));
+  c.Hin = sw.ptr<const void>(SLOT_OFF(Hin));
+  c.alpha = sw.c64(SLOT_OFF(alpha));
+  c.beta = sw.c64(SLOT_OFF(beta));
+  c.omega = sw.c64(SLOT_OFF(omega));
+  c.gamma = sw.c64(SLOT_OFF(gamma));
+  c.zeta = sw.c64(SLOT_OFF(zeta));
   return c;
 }
 
@@ -283,11 +284,11 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   V* rh = reinterpret_cast<V*>(e.rh) + base;
   const bool zero_x = c.rounds == 0;  // fresh solve: x = 0, d holds nothing
   const bool use_d = !c.discard;   // else the iterate is x64 alone
-  const Slot* S = &e.slots[slot];
-  const double2 a1 = ldu(&S->a1), a2 = ldu(&S->a2), sc = ldu(&S->sc);
-  const double* eta0 = ldu_ptr(&S->eta0);
-  const double* D0 = ldu_ptr(&S->D0);
-  const double* Z0 = ldu_ptr(&S->Z0);
+  const SlotWords sw(&e.slots[slot]);  // right-hand side fields, needed only here
+  const double2 a1 = sw.c64(SLOT_OFF(a1)), a2 = sw.c64(SLOT_OFF(a2)), sc = sw.c64(SLOT_OFF(sc));
+  const double* eta0 = sw.ptr<const double>(SLOT_OFF(eta0));
+  const double* D0 = sw.ptr<const double>(SLOT_OFF(D0));
+  const double* Z0 = sw.ptr<const double>(SLOT_OFF(Z0));
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
   const bool big = (nx >= kSW) && (ny >= kSH);
   // every load of the work item in one round: the right-hand side fields

@@ -377,10 +377,16 @@ struct RowTile {
     for (int m = 0; m < kRows; ++m) {
       if (kH % 4 == 0 || w + 4 * m < kH) mainv[m] = f(ro[m], col);
     }
-    sly = int(threadIdx.x) / (2 * HALO);
-    const int c = int(threadIdx.x) - sly * 2 * HALO;
+    // the side coordinates are formed here, not hoisted out of a caller's
+    // work-item loop (where they would occupy registers across every code
+    // path of a pass and can be spilled): the empty asm makes the thread
+    // index opaque to loop-invariant code motion
+    int tid = int(threadIdx.x);
+    asm volatile("" : "+v"(tid));
+    sly = tid / (2 * HALO);
+    const int c = tid - sly * 2 * HALO;
     slx = (c < HALO) ? c : kTX + c;
-    if (int(threadIdx.x) < kSide)
+    if (tid < kSide)
       sidev = f(size_t(wrapc(y0 - HALO + sly, ny, big)) * size_t(nx), unsigned(wrapc(x0 - HALO + slx, nx, big)));
   }
   __device__ __forceinline__ void store(V* lds) const {

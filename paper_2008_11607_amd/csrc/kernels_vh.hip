@@ -305,17 +305,25 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
       bzz[j] = (Z0 + ro)[col];
     }
   }
+  // x64 and d as two tiles of pure loads, added in registers once all have
+  // been issued (the block runs at two per CU for its LDS: registers are
+  // not what limits it)
   RowTile<double2, 2, kTYB> xr;
+  RowTile<V, 2, kTYB> dr;
   RowTile<double, 1, kTYB> hr;
   if (!zero_x) {
     hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return c.H[ro + col]; });
-    xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
-      const size_t g = ro + col;
-      const double2 xv = x64[g];
-      const V dv = d[g];
-      // a select, not a product: a discarded d may hold non-finite values
-      return use_d ? make_double2(xv.x + double(dv.x), xv.y + double(dv.y)) : xv;
-    });
+    xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return x64[ro + col]; });
+    dr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return d[ro + col]; });
+    if (use_d) {  // a discarded d may hold non-finite values: not added
+#pragma unroll
+      for (int m = 0; m < RowTile<double2, 2, kTYB>::kRows; ++m) {
+        xr.mainv[m].x += double(dr.mainv[m].x);
+        xr.mainv[m].y += double(dr.mainv[m].y);
+      }
+      xr.sidev.x += double(dr.sidev.x);
+      xr.sidev.y += double(dr.sidev.y);
+    }
   }
   __syncthreads();  // LDS of the previous work item is free
   if (!zero_x) {

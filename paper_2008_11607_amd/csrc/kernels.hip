@@ -292,12 +292,17 @@ __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int s
   const bool pside = threadIdx.x < 8 * kPH;
   const int ply = threadIdx.x >> 3, pc8 = threadIdx.x & 7;
   const int plx = (pc8 < 4) ? pc8 : kTX + pc8;
-  V pside_v;
+  V pside_v, pside_w;
   if (pside) pside_v = ps[row_off(y0 - 4 + ply) + unsigned(wrapc(x0 - 4 + plx, nx, big))];
+  // taller tiles: the side columns need a second element for some threads
+  constexpr int kPSide2 = 8 * kPH - kNT;
+  if (kPSide2 > 0 && int(threadIdx.x) < kPSide2)
+    pside_w = ps[row_off(y0 - 4 + ply + kNT / 8) + unsigned(wrapc(x0 - 4 + plx, nx, big))];
   __syncthreads();  // LDS of the previous work item is free
 #pragma unroll
   for (int m = 0; m < kPH / 4; ++m) PT[(w + 4 * m) * kPW + tx + 4] = pm[m];
   if (pside) PT[ply * kPW + plx] = pside_v;
+  if (kPSide2 > 0 && int(threadIdx.x) < kPSide2) PT[(ply + kNT / 8) * kPW + plx] = pside_w;
   __syncthreads();
   // interior: rows w + 4j, column tx
   V rn[kTY / 4], pn[kTY / 4];

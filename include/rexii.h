@@ -103,6 +103,11 @@ typedef struct rexii_opts {
                                HIP events around each (fills the kernel
                                timing fields of the report); 0: replay them
                                from a HIP graph.  Default 0                */
+    int32_t tile_rows;      /* BiCGStab path: rows of a 64-column work tile,
+                               16 or 32; 0 -> 32 in MIXED, 16 in FP64, or
+                               chosen together with the slot count when
+                               pole_batch < 0.  The COCG path always uses
+                               16.  Other values: REXII_ERR_INVALID_ARG    */
 } rexii_opts;
 
 typedef struct rexii_report {
@@ -136,6 +141,8 @@ typedef struct rexii_report {
      * algorithmic bytes of the pass U1 launches */
     double step_ms[6];
     double u1_bytes;
+    int32_t tile_rows;       /* rows of the work tiles the engine ran with   */
+    int32_t reserved;
 } rexii_report;
 
 /* Fill *opts with the defaults described above. */

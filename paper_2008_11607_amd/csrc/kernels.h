@@ -38,7 +38,7 @@ namespace rexii {
 // Stencil tile: 64 x 16 points, 256 threads (64 x 4), 4 rows per thread.
 constexpr int kTX = 64;
 constexpr int kTY = 16;    // tile height of the COCG passes
-constexpr int kTYB = 32;   // tile height of the BiCGStab passes (fewer, larger work items)
+constexpr int kTYB = 32;   // default tile height of the BiCGStab passes (16 also built)
 constexpr int kNT = 256;
 constexpr int kNDots = 9;   // pq(2) qr(2) qq(2) rr(2) |r|^2(1)
 constexpr int kMaxSlots = 1024;
@@ -127,6 +127,7 @@ struct Eng {
   int method;            // 0: COCG on the constant-depth Helmholtz; 1: BiCGStab (flux form)
   int d_is_f32;          // inner precision of d, r, p (1: FP32, 0: FP64)
   int grid_small;        // persistent grid of kernels that mostly find no work
+  int th;                // rows of a work tile (kTY, or 16 / 32 on the BiCGStab path)
   Slot* slots;           // [B]
   const Inst* inst;      // [ninst]
   const SolveDev* solves;// [S]
@@ -184,7 +185,7 @@ int prep_vh_blocks();
 void launch_hmax(const double* H, size_t n, int* flags, double* part, hipStream_t s);
 void launch_fill_value(double* p, size_t n, double v, hipStream_t s);
 void launch_to_f32(const double* p, float* q, size_t n, hipStream_t s);
-int bcg_occupancy(int mixed);
+int bcg_occupancy(int mixed, int th);
 
 void launch_pass_scalars(const Eng& e, hipStream_t s);
 void launch_retire(const Eng& e, hipStream_t s);

@@ -34,9 +34,12 @@
 
 namespace rexii {
 
-constexpr int kBW = kTX + 4, kBH = kTYB + 4;   // tile with halo 2
-constexpr int kSW = kTX + 8, kSH = kTYB + 8;   // grids at least this large take the cheap wrap
-constexpr int kHW = kTX + 2, kHH = kTYB + 2;   // depth tile with halo 1
+// Tiles of kTX x TH points (TH = 16 or 32 rows, chosen per engine): row
+// widths of the halo-2 tile, of the depth tile (halo 1), and the grid size
+// from which the cheap periodic wrap is exact
+constexpr int kBW = kTX + 4;   // tile with halo 2: TH + 4 rows
+constexpr int kHW = kTX + 2;   // depth tile with halo 1: TH + 2 rows
+constexpr int kSW = kTX + 8;   // with TH + 8 rows
 
 // K phi at position (y, x) of a phi tile with row width PW; the same grid
 // point is (y + DH, x + DH) of the depth tile (row width HW).
@@ -102,18 +105,18 @@ __device__ __forceinline__ BcgCtl load_bctl(const Slot* S) {
 }
 
 // ---- pass S ----------------------------------------------------------------
-template <typename T>
+template <typename T, int TH>
 struct LdsS {
   using V = typename C2<T>::t;
-  static constexpr size_t kBytes = sizeof(V) * kBH * kBW + sizeof(T) * kHH * kHW;
+  static constexpr size_t kBytes = sizeof(V) * (TH + 4) * kBW + sizeof(T) * (TH + 2) * kHW;
 };
 
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
                                       double (&acc)[8]) {
   using V = typename C2<T>::t;
   V* ST = reinterpret_cast<V*>(lds);
-  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * (TH + 4) * kBW);
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
@@ -123,19 +126,19 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   const V alpha = mk<V>(c.alpha.x, c.alpha.y);
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
-  const bool big = (nx >= kSW) && (ny >= kSH);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * TH;
+  const bool big = (nx >= kSW) && (ny >= (TH + 8));
   // pure loads first, then the tile whose values are formed as they
   // arrive (s = r - alpha v), so that every load is in flight before the
   // first wait
   const T* Hi = static_cast<const T*>(c.Hin);
-  RowTile<T, 1, kTYB> hr;
+  RowTile<T, 1, TH> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
-  V hv[kTYB / 4];
+  V hv[TH / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
-  RowTile<V, 2, kTYB> sr;
+  for (int j = 0; j < TH / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
+  RowTile<V, 2, TH> sr;
   sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
@@ -145,7 +148,7 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -162,11 +165,11 @@ __device__ __forceinline__ void bcg_s(const Eng& e, const BcgCtl& c, int slot, i
 // ---- pass U1: updates ------------------------------------------------------
 // Inner step: s = r - alpha v (tile + halo 2), t = K s, then on the tile
 // d += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v).
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds) {
   using V = typename C2<T>::t;
   V* ST = reinterpret_cast<V*>(lds);
-  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * (TH + 4) * kBW);
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
@@ -183,25 +186,25 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   const V omega = mk<V>(c.omega.x, c.omega.y);
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
-  const bool big = (nx >= kSW) && (ny >= kSH);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * TH;
+  const bool big = (nx >= kSW) && (ny >= (TH + 8));
   // pure loads first (depth tile, p, v, d; rows are wavefront-uniform, so
   // row offsets sit in scalar registers and one column offset serves every
   // load), then the tile formed as it arrives (s = r - alpha v)
   const T* Hi = static_cast<const T*>(c.Hin);
-  RowTile<T, 1, kTYB> hr;
+  RowTile<T, 1, TH> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
-  size_t ro[kTYB / 4];
-  V pv[kTYB / 4], vv[kTYB / 4], dv[kTYB / 4];
+  size_t ro[TH / 4];
+  V pv[TH / 4], vv[TH / 4], dv[TH / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     ro[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx);
     pv[j] = (ps + ro[j])[col];
     vv[j] = (vs + ro[j])[col];
     if (!first) dv[j] = nt_load(&(d + ro[j])[col]);
   }
-  RowTile<V, 2, kTYB> sr;
+  RowTile<V, 2, TH> sr;
   sr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return csub(rs[g], cmul(alpha, vs[g]));
@@ -211,7 +214,7 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V t = kop<kBW, kHW, -1>(ST, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -233,7 +236,7 @@ __device__ __forceinline__ void bcg_u1_inner(const Eng& e, const BcgCtl& c, int 
 }
 
 // last update of an inner solve (no halo): d += alpha p + omega (r - alpha v)
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int slot, int tile) {
   using V = typename C2<T>::t;
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -247,9 +250,9 @@ __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int s
   const bool first = c.it_inner == 1;
   const bool fold = first && c.rounds >= 2 && !c.discard;
   const V alpha = mk<V>(c.alpha.x, c.alpha.y), omega = mk<V>(c.omega.x, c.omega.y);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * TH;
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const int gx = x0 + tx, gy = y0 + ty + 4 * j;
     if (gx < nx && gy < ny) {
       const size_t ro = size_t(gy) * size_t(nx);
@@ -268,12 +271,12 @@ __device__ __forceinline__ void bcg_u1_last(const Eng& e, const BcgCtl& c, int s
 // FP64 residual round: with x = x64 + d (0 for a fresh solve) on tile +
 // halo 2, r64 = sc (eta0 + a1 D_H + a2 Z_H) - K x on the tile;
 // r = r_hat = p = (T) r64; partials |r64|^2 (index 2) and |r|^2 (index 3).
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
                                              double (&acc)[2]) {
   using V = typename C2<T>::t;
   double2* XT = reinterpret_cast<double2*>(lds);
-  double* Hs = reinterpret_cast<double*>(lds + sizeof(double2) * kBH * kBW);
+  double* Hs = reinterpret_cast<double*>(lds + sizeof(double2) * (TH + 4) * kBW);
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
@@ -289,15 +292,15 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   const double* eta0 = sw.ptr<const double>(SLOT_OFF(eta0));
   const double* D0 = sw.ptr<const double>(SLOT_OFF(D0));
   const double* Z0 = sw.ptr<const double>(SLOT_OFF(Z0));
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
-  const bool big = (nx >= kSW) && (ny >= kSH);
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * TH;
+  const bool big = (nx >= kSW) && (ny >= (TH + 8));
   // every load of the work item in one round: the right-hand side fields
   // (interior) and the depth (halo 1) first, then x = x64 + d (halo 2),
   // formed as it arrives (d is read even when discarded, then not used)
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
-  double bre[kTYB / 4], bdz[kTYB / 4], bzz[kTYB / 4];
+  double bre[TH / 4], bdz[TH / 4], bzz[TH / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const size_t ro = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx);
     bre[j] = (eta0 + ro)[col];
     if (D0) {
@@ -308,16 +311,16 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   // x64 and d as two tiles of pure loads, added in registers once all have
   // been issued (the block runs at two per CU for its LDS: registers are
   // not what limits it)
-  RowTile<double2, 2, kTYB> xr;
-  RowTile<V, 2, kTYB> dr;
-  RowTile<double, 1, kTYB> hr;
+  RowTile<double2, 2, TH> xr;
+  RowTile<V, 2, TH> dr;
+  RowTile<double, 1, TH> hr;
   if (!zero_x) {
     hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return c.H[ro + col]; });
     xr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return x64[ro + col]; });
     dr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return d[ro + col]; });
     if (use_d) {  // a discarded d may hold non-finite values: not added
 #pragma unroll
-      for (int m = 0; m < RowTile<double2, 2, kTYB>::kRows; ++m) {
+      for (int m = 0; m < RowTile<double2, 2, TH>::kRows; ++m) {
         xr.mainv[m].x += double(dr.mainv[m].x);
         xr.mainv[m].y += double(dr.mainv[m].y);
       }
@@ -332,7 +335,7 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const int ly = ty + 4 * j;
     const int gx = x0 + tx, gy = y0 + ly;
     if (gx < nx && gy < ny) {
@@ -355,12 +358,12 @@ __device__ __forceinline__ void bcg_u1_outer(const Eng& e, const BcgCtl& c, int 
 }
 
 // ---- pass U2: v' = K p' and <r_hat, v'> -------------------------------------
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, int tile, unsigned char* lds,
                                        double (&acc)[2]) {
   using V = typename C2<T>::t;
   V* PT = reinterpret_cast<V*>(lds);
-  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * kBH * kBW);
+  T* Hs = reinterpret_cast<T*>(lds + sizeof(V) * (TH + 4) * kBW);
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nx = c.nx, ny = c.ny;
   const size_t base = size_t(slot) * e.cap;
@@ -370,26 +373,26 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   const V* rh = reinterpret_cast<const V*>(e.rh) + base;
   const V gamma = mk<V>(c.gamma.x, c.gamma.y), zeta = mk<V>(c.zeta.x, c.zeta.y);
   const T cx = T(c.cx), cy = T(c.cy), cxy = T(c.cxy);
-  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTYB;
-  const bool big = (nx >= kSW) && (ny >= kSH);
-  RowTile<V, 2, kTYB> pr;
+  const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * TH;
+  const bool big = (nx >= kSW) && (ny >= (TH + 8));
+  RowTile<V, 2, TH> pr;
   pr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) {
     const size_t g = ro + col;
     return pn[g];
   });
   const T* Hi = static_cast<const T*>(c.Hin);
-  RowTile<T, 1, kTYB> hr;
+  RowTile<T, 1, TH> hr;
   hr.fetch(x0, y0, nx, ny, big, [&](size_t ro, unsigned col) { return Hi[ro + col]; });
   const unsigned col = unsigned(wrapc(x0 + tx, nx, big));
-  V hv[kTYB / 4];
+  V hv[TH / 4];
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
+  for (int j = 0; j < TH / 4; ++j) hv[j] = (rh + size_t(wrapc(y0 + ty + 4 * j, ny, big)) * size_t(nx))[col];
   __syncthreads();  // LDS of the previous work item is free
   pr.store(PT);
   hr.store(Hs);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTYB / 4; ++j) {
+  for (int j = 0; j < TH / 4; ++j) {
     const int ly = ty + 4 * j;
     if (x0 + tx < nx && y0 + ly < ny) {
       const V v1 = kop<kBW, kHW, -1>(PT, Hs, ly + 2, tx + 2, cx, cy, cxy, gamma, zeta);
@@ -399,9 +402,9 @@ __device__ __forceinline__ void bcg_u2(const Eng& e, const BcgCtl& c, int slot, 
   }
 }
 
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_pass_s(const Eng& e) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T, TH>::kBytes];
   __shared__ double red[4 * 8];
   const WorkMap m = load_work_map(e);
   const int span = work_span(m);
@@ -413,19 +416,19 @@ __device__ __forceinline__ void bcg_pass_s(const Eng& e) {
     double acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-    bcg_s<T>(e, c, it.slot, it.tile, lds, acc);
+    bcg_s<T, TH>(e, c, it.slot, it.tile, lds, acc);
     store_block_sums<8>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 
-template <typename T>
+template <typename T, int TH>
 struct LdsU1 {
-  static constexpr size_t kX = sizeof(double2) * kBH * kBW + sizeof(double) * kHH * kHW;  // residual round
+  static constexpr size_t kX = sizeof(double2) * (TH + 4) * kBW + sizeof(double) * (TH + 2) * kHW;  // residual round
 };
 
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_pass_u1(const Eng& e) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T, TH>::kBytes];
   const WorkMap m = load_work_map(e);
   const int span = work_span(m);
   for (int w = blockIdx.x; w < span; w += gridDim.x) {
@@ -433,17 +436,17 @@ __device__ __forceinline__ void bcg_pass_u1(const Eng& e) {
     if (!work_item(e, m, w, it)) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status == kInner)
-      bcg_u1_inner<T>(e, c, it.slot, it.tile, lds);
+      bcg_u1_inner<T, TH>(e, c, it.slot, it.tile, lds);
     else if (c.status == kInnerLast)
-      bcg_u1_last<T>(e, c, it.slot, it.tile);
+      bcg_u1_last<T, TH>(e, c, it.slot, it.tile);
   }
 }
 
 // the FP64 residual rounds (a kernel of their own: sharing pass U1 would
 // raise its register count for a step that runs once per round)
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsU1<T>::kX];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsU1<T, TH>::kX];
   __shared__ double red[4 * 2];
   __shared__ int st[kMaxSlots];
   __shared__ int any;
@@ -466,14 +469,14 @@ __device__ __forceinline__ void bcg_pass_outer(const Eng& e) {
     if (st[it.slot] != kOuterPending && st[it.slot] != kInnerDone) continue;
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     double acc[2] = {0.0, 0.0};
-    bcg_u1_outer<T>(e, c, it.slot, it.tile, lds, acc);
+    bcg_u1_outer<T, TH>(e, c, it.slot, it.tile, lds, acc);
     store_block_sums<2, 2>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 
-template <typename T>
+template <typename T, int TH>
 __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsS<T, TH>::kBytes];
   __shared__ double red[4 * 2];
   const WorkMap m = load_work_map(e);
   const int span = work_span(m);
@@ -483,19 +486,28 @@ __device__ __forceinline__ void bcg_pass_u2(const Eng& e) {
     const BcgCtl c = load_bctl(&e.slots[it.slot]);
     if (c.status != kInner && c.status != kOuterPending && c.status != kInnerDone) continue;
     double acc[2] = {0.0, 0.0};
-    bcg_u2<T>(e, c, it.slot, it.tile, lds, acc);
+    bcg_u2<T, TH>(e, c, it.slot, it.tile, lds, acc);
     store_block_sums<2>(acc, red, item_part(e, it.slot, it.tile));
   }
 }
 
-__global__ __launch_bounds__(kNT) void k_bcg_s_f32(Eng e) { bcg_pass_s<float>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_s_f64(Eng e) { bcg_pass_s<double>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_u1_f32(Eng e) { bcg_pass_u1<float>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_u1_f64(Eng e) { bcg_pass_u1<double>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_outer_f32(Eng e) { bcg_pass_outer<float>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_outer_f64(Eng e) { bcg_pass_outer<double>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_u2_f32(Eng e) { bcg_pass_u2<float>(e); }
-__global__ __launch_bounds__(kNT) void k_bcg_u2_f64(Eng e) { bcg_pass_u2<double>(e); }
+// 64 x 32 tiles (the default) and 64 x 16 tiles (suffix _h16)
+__global__ __launch_bounds__(kNT) void k_bcg_s_f32(Eng e) { bcg_pass_s<float, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_s_f64(Eng e) { bcg_pass_s<double, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f32(Eng e) { bcg_pass_u1<float, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f64(Eng e) { bcg_pass_u1<double, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f32(Eng e) { bcg_pass_outer<float, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f64(Eng e) { bcg_pass_outer<double, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f32(Eng e) { bcg_pass_u2<float, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f64(Eng e) { bcg_pass_u2<double, 32>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_s_f32_h16(Eng e) { bcg_pass_s<float, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_s_f64_h16(Eng e) { bcg_pass_s<double, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f32_h16(Eng e) { bcg_pass_u1<float, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u1_f64_h16(Eng e) { bcg_pass_u1<double, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f32_h16(Eng e) { bcg_pass_outer<float, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_outer_f64_h16(Eng e) { bcg_pass_outer<double, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f32_h16(Eng e) { bcg_pass_u2<float, 16>(e); }
+__global__ __launch_bounds__(kNT) void k_bcg_u2_f64_h16(Eng e) { bcg_pass_u2<double, 16>(e); }
 
 // ---- scalar kernels (one block per slot, partials in tile order) -----------
 template <int N>
@@ -710,21 +722,26 @@ void launch_fill_value(double* p, size_t n, double v, hipStream_t s) {
 }
 template <typename T>
 void launch_bcg(const Eng& e, int grid, hipStream_t s, hipEvent_t* ev) {
-  const bool f32 = sizeof(T) == 4;
+  const bool f32 = sizeof(T) == 4, h16 = e.th == 16;
+  using K = void (*)(Eng);
+  const K outer = f32 ? (h16 ? k_bcg_outer_f32_h16 : k_bcg_outer_f32) : (h16 ? k_bcg_outer_f64_h16 : k_bcg_outer_f64);
+  const K u1 = f32 ? (h16 ? k_bcg_u1_f32_h16 : k_bcg_u1_f32) : (h16 ? k_bcg_u1_f64_h16 : k_bcg_u1_f64);
+  const K u2 = f32 ? (h16 ? k_bcg_u2_f32_h16 : k_bcg_u2_f32) : (h16 ? k_bcg_u2_f64_h16 : k_bcg_u2_f64);
+  const K sp = f32 ? (h16 ? k_bcg_s_f32_h16 : k_bcg_s_f32) : (h16 ? k_bcg_s_f64_h16 : k_bcg_s_f64);
   int k = 0;
   auto mark = [&]() {
     if (ev) (void)hipEventRecord(ev[k++], s);
   };
   mark();
-  hipLaunchKernelGGL(f32 ? k_bcg_outer_f32 : k_bcg_outer_f64, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(outer, dim3(std::min(grid, e.grid_small)), dim3(kNT), 0, s, e);
   mark();
-  hipLaunchKernelGGL(f32 ? k_bcg_u1_f32 : k_bcg_u1_f64, dim3(grid), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(u1, dim3(grid), dim3(kNT), 0, s, e);
   mark();
-  hipLaunchKernelGGL(f32 ? k_bcg_u2_f32 : k_bcg_u2_f64, dim3(grid), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(u2, dim3(grid), dim3(kNT), 0, s, e);
   mark();
   hipLaunchKernelGGL(k_bcg_scalars_u, dim3(e.B), dim3(kSNT), 0, s, e);
   mark();
-  hipLaunchKernelGGL(f32 ? k_bcg_s_f32 : k_bcg_s_f64, dim3(grid), dim3(kNT), 0, s, e);
+  hipLaunchKernelGGL(sp, dim3(grid), dim3(kNT), 0, s, e);
   mark();
   hipLaunchKernelGGL(k_bcg_scalars_s, dim3(e.B), dim3(kSNT), 0, s, e);
   mark();
@@ -733,14 +750,15 @@ void launch_prep_vh(const double* f, const double* H, int nx, int ny, double* D0
                     double* hmax_part, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_vh, dim3(prep_vh_blocks()), dim3(256), 0, s, f, H, nx, ny, D0, Z0, flags, hmax_part);
 }
-int bcg_occupancy(int mixed) {
+int bcg_occupancy(int mixed, int th) {
+  const bool h16 = th == 16;
   int a = 0, b = 0;
   if (mixed) {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_u1_f32, kNT, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_s_f32, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, h16 ? k_bcg_u1_f32_h16 : k_bcg_u1_f32, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, h16 ? k_bcg_s_f32_h16 : k_bcg_s_f32, kNT, 0);
   } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_bcg_u1_f64, kNT, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bcg_s_f64, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, h16 ? k_bcg_u1_f64_h16 : k_bcg_u1_f64, kNT, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, h16 ? k_bcg_s_f64_h16 : k_bcg_s_f64, kNT, 0);
   }
   const int m = a < b ? a : b;
   return m > 0 ? m : 1;

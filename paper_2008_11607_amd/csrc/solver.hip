@@ -125,9 +125,8 @@ struct Plan {
 struct GridGeo {
   int tiles_x, tiles_y, nblk;
 };
-// work items are kTX x kTY tiles (COCG) or kTX x kTYB tiles (BiCGStab)
-static GridGeo make_geo(int nx, int ny, int method) {
-  const int th = (method == 1) ? kTYB : kTY;
+// work items are kTX x th tiles (th = kTY for COCG; 16 or 32 for BiCGStab)
+static GridGeo make_geo(int nx, int ny, int th) {
   GridGeo g;
   g.tiles_x = (nx + kTX - 1) / kTX;
   g.tiles_y = (ny + th - 1) / th;
@@ -193,6 +192,8 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   pl.paired = (o.pair_conjugate != 0) && div_free && !pl.bicg;
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
+  if (o.tile_rows != 0 && o.tile_rows != 16 && o.tile_rows != 32)
+    return set_error(REXII_ERR_INVALID_ARG, "tile_rows must be 0, 16 or 32");
   if (o.precision != REXII_PREC_FP64 && o.precision != REXII_PREC_MIXED)
     return set_error(REXII_ERR_INVALID_ARG, "unknown precision");
   if (op->H_field && !(hmax > 0.0)) return set_error(REXII_ERR_INVALID_ARG, "variable depth needs max H > 0");
@@ -343,19 +344,26 @@ struct Problem {
 struct EngineSize {
   int B = 1, cap = 0, cap_blk = 0, S = 0, ninst = 0;
   int method = 0;   // 0 COCG, 1 BiCGStab
+  int th = kTY;     // rows of a work tile
   int nvec = 5;     // inner-precision vectors per slot
   size_t eb = 16;
 };
 
-static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_B, int precision) {
+static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_B, int precision,
+                              int tile_rows) {
   EngineSize z;
   size_t maxp = 0;
   int min_nb = 0;
   z.method = 0;
   for (Problem* p : probs) z.method = std::max(z.method, p->pl.bicg ? 1 : 0);
+  // BiCGStab default tile: 64 x 32 in mixed precision, 64 x 16 in FP64 (its
+  // FP64 tiles need twice the LDS and registers; measured at 2048^2: 32 rows
+  // 7% faster in mixed precision, 16 rows 7% faster in FP64)
+  const int th_default = (precision == REXII_PREC_MIXED) ? kTYB : 16;
+  z.th = (z.method == 1) ? ((tile_rows == 16 || tile_rows == 32) ? tile_rows : th_default) : kTY;
   for (Problem* p : probs) {
     maxp = std::max(maxp, p->n());
-    const int nb = make_geo(p->pl.nx, p->pl.ny, z.method).nblk;
+    const int nb = make_geo(p->pl.nx, p->pl.ny, z.th).nblk;
     z.cap_blk = std::max(z.cap_blk, nb);
     z.S += int(p->pl.solves.size());
     min_nb = (min_nb == 0) ? nb : std::min(min_nb, nb);
@@ -363,7 +371,7 @@ static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_
   // the smallest problem's tile count, in units of kTX x kTY tiles: slots
   // enough to fill the GPU while only the smallest problems are left (the
   // queue runs the most expensive solves first); memory caps the count
-  const double mean_nblk = double(std::max(1, min_nb)) * ((z.method == 1) ? double(kTYB) / kTY : 1.0);
+  const double mean_nblk = double(std::max(1, min_nb)) * double(z.th) / kTY;
   z.cap = int(maxp);
   z.ninst = int(probs.size());
   z.eb = inner_elem_bytes(precision);
@@ -434,6 +442,7 @@ struct Engine {
     e.B = z.B;
     e.S = z.S;
     e.method = z.method;
+    e.th = z.th;
     e.d_is_f32 = (prec == REXII_PREC_MIXED) ? 1 : 0;
     e.cap = z.cap;
     e.cap_blk = z.cap_blk;
@@ -474,7 +483,7 @@ struct Engine {
     }
     for (int i = 0; i < z.ninst; ++i) {
       const Plan& pl = probs[i]->pl;
-      const GridGeo g = make_geo(pl.nx, pl.ny, z.method);
+      const GridGeo g = make_geo(pl.nx, pl.ny, z.th);
       Inst I;
       I.nx = pl.nx;
       I.ny = pl.ny;
@@ -535,7 +544,7 @@ struct Engine {
     int dev = 0, cus = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int occ = (z.method == 1) ? bcg_occupancy(precision == REXII_PREC_MIXED ? 1 : 0)
+    const int occ = (z.method == 1) ? bcg_occupancy(precision == REXII_PREC_MIXED ? 1 : 0, z.th)
                                     : pass_occupancy(precision == REXII_PREC_MIXED ? 1 : 0);
     // one work item (slot, tile) per block when every slot is live; never
     // fewer blocks than fill the chip
@@ -733,6 +742,7 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     const double per_pt = en->z.method == 1 ? 13.0 * eb + 3.0 * (eb == 8.0 ? 4.0 : 8.0) : 6.0 * eb;
     rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * per_pt;
     rep->slots = en->z.B;
+    rep->tile_rows = en->z.th;
     rep->kernel_launches = en->launches;
     rep->kernel_ms = en->kernel_ms;
     rep->kernel_bytes = en->pass_bytes;
@@ -839,7 +849,7 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
     ptrs.push_back(&pbs[i]);
     b += problem_bytes(pbs[i]);
   }
-  if (!ptrs.empty()) b += engine_bytes(engine_size(ptrs, o.pole_batch, o.precision), keep);
+  if (!ptrs.empty()) b += engine_bytes(engine_size(ptrs, o.pole_batch, o.precision, o.tile_rows), keep);
   *bytes = b;
   return REXII_OK;
 }
@@ -934,7 +944,7 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
     jb.ptrs.push_back(&jb.pbs[i]);
   }
   if (jb.ptrs.empty()) return 0.0;
-  const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision);
+  const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision, jb.o.tile_rows);
   jb.en = new Engine(jb.st);
   jb.en->setup(ar, jb.ptrs, z, jb.o.precision, jb.o.max_iter,
                (jb.o.precision == REXII_PREC_MIXED) ? jb.o.inner_tol : 0.0,
@@ -973,11 +983,13 @@ static std::string tune_key(const std::vector<JobItem>& items, const rexii_opts&
   }
   const int method = (depth || o.method == 1) ? 1 : 0;
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "nx=%d ny=%d prec=%d method=%d cus=%d", nx, ny, o.precision, method, cus);
+  std::snprintf(buf, sizeof(buf), "nx=%d ny=%d prec=%d method=%d rows=%d cus=%d", nx, ny, o.precision, method,
+                o.tile_rows, cus);
   return buf;
 }
 
-static int tune_lookup(const std::string& key) {
+// Cached choice for key: slot count and tile rows (0 if none).
+static int tune_lookup(const std::string& key, int* th) {
   FILE* fp = std::fopen(tune_cache_path().c_str(), "r");
   if (!fp) return 0;
   char line[256];
@@ -985,13 +997,16 @@ static int tune_lookup(const std::string& key) {
   while (std::fgets(line, sizeof(line), fp)) {
     std::string l(line);
     const size_t bar = l.find(" | B=");
-    if (bar != std::string::npos && l.substr(0, bar) == key) best = std::atoi(l.c_str() + bar + 5);
+    if (bar != std::string::npos && l.substr(0, bar) == key) {
+      best = std::atoi(l.c_str() + bar + 5);
+      const size_t tp = l.find(" T=", bar);
+      *th = (tp != std::string::npos) ? std::atoi(l.c_str() + tp + 3) : 0;
+    }
   }
   std::fclose(fp);
   return best;
 }
-
-static void tune_store(const std::string& key, int B, double rate) {
+static void tune_store(const std::string& key, int B, int th, double rate) {
   const std::string path = tune_cache_path();
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
@@ -1000,18 +1015,24 @@ static void tune_store(const std::string& key, int B, double rate) {
   }
   FILE* fp = std::fopen(path.c_str(), "a");
   if (!fp) return;
-  std::fprintf(fp, "%s | B=%d rate=%.4e\n", key.c_str(), B, rate);
+  std::fprintf(fp, "%s | B=%d T=%d rate=%.4e\n", key.c_str(), B, th, rate);
   std::fclose(fp);
 }
 
-static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o, hipStream_t st) {
+// Slot count and (BiCGStab path, when o.tile_rows == 0) tile rows: every
+// candidate runs four graph chunks of the real problems; the best rate of
+// grid points advanced per second wins and is cached.  Returns the slot
+// count (0 on failure) and the tile rows in *th.
+static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o, hipStream_t st, int* th) {
   int dev = 0, cus = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const std::string key = tune_key(items, o, cus);
-  const int cached = tune_lookup(key);
+  *th = 0;
+  const int cached = tune_lookup(key, th);
   if (cached > 0) return cached;
   size_t nsolves = 0, maxp = 0;
+  bool depth = false;
   {
     std::vector<JobItem> its = items;
     for (JobItem& it : its) {
@@ -1020,55 +1041,68 @@ static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o
       if (sizing_plan(it, o, pb) != REXII_OK) return 0;
       nsolves += pb.pl.solves.size();
       maxp = std::max(maxp, pb.n());
+      depth = depth || it.op->H_field != nullptr;
     }
   }
-  // candidates up to twice the default count (at least 128)
-  int hb = 0;
-  {
-    std::vector<Problem> pbs(items.size());
-    std::vector<Problem*> ptrs;
-    for (size_t i = 0; i < items.size(); ++i) {
-      if (items[i].skip || sizing_plan(items[i], o, pbs[i]) != REXII_OK) continue;
-      ptrs.push_back(&pbs[i]);
-    }
-    if (!ptrs.empty()) hb = engine_size(ptrs, 0, o.precision).B;
-  }
-  const int cap_b = std::max(128, 2 * hb);
+  const bool bicg = depth || o.method == 1;
+  std::vector<int> ths;
+  if (bicg && o.tile_rows == 0)
+    ths = {32, 16};
+  else
+    ths = {bicg ? o.tile_rows : 0};  // 0: the engine's default
   const int cands[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
-  int best = 0;
+  int best = 0, best_th = 0;
   double best_rate = 0.0;
-  for (int B : cands) {
-    if (B > cap_b || B > kMaxSlots) break;
-    if (size_t(B) * 2 > nsolves && B != cands[0]) break;  // keep the queue longer than the slots
-    Job jb;
-    jb.st = st;
-    jb.o = o;
-    jb.o.pole_batch = B;
-    jb.o.profile = 0;
-    jb.items = items;
-    for (JobItem& it : jb.items) {
-      it.u = nullptr;
-      it.rep = nullptr;
+  for (int t : ths) {
+    rexii_opts ot = o;
+    ot.tile_rows = bicg ? t : 0;
+    // candidates up to twice the default count (at least 128)
+    int hb = 0;
+    {
+      std::vector<Problem> pbs(items.size());
+      std::vector<Problem*> ptrs;
+      for (size_t i = 0; i < items.size(); ++i) {
+        if (items[i].skip || sizing_plan(items[i], ot, pbs[i]) != REXII_OK) continue;
+        ptrs.push_back(&pbs[i]);
+      }
+      if (!ptrs.empty()) hb = engine_size(ptrs, 0, ot.precision, ot.tile_rows).B;
     }
-    size_t need = 0;
-    if (job_bytes(jb.items, jb.o, false, 0, &need) != REXII_OK) break;
-    Arena ar(nullptr, 0);
-    try {
-      ar.reserve_own(need + 4096);
-    } catch (const HipError&) {
-      break;  // out of memory: larger counts will not fit either
-    }
-    const int chunks = 4;
-    const double ms = run_job(jb, ar, chunks);
-    if (!(ms > 0.0)) continue;
-    const int chunk = jb.en ? jb.en->chunk : 16;
-    const double rate = double(B) * double(maxp) * chunk * (chunks - 1) / (ms * 1e-3);
-    if (rate > best_rate) {
-      best_rate = rate;
-      best = B;
+    const int cap_b = std::max(128, 2 * hb);
+    for (int B : cands) {
+      if (B > cap_b || B > kMaxSlots) break;
+      if (size_t(B) * 2 > nsolves && B != cands[0]) break;  // keep the queue longer than the slots
+      Job jb;
+      jb.st = st;
+      jb.o = ot;
+      jb.o.pole_batch = B;
+      jb.o.profile = 0;
+      jb.items = items;
+      for (JobItem& it : jb.items) {
+        it.u = nullptr;
+        it.rep = nullptr;
+      }
+      size_t need = 0;
+      if (job_bytes(jb.items, jb.o, false, 0, &need) != REXII_OK) break;
+      Arena ar(nullptr, 0);
+      try {
+        ar.reserve_own(need + 4096);
+      } catch (const HipError&) {
+        break;  // out of memory: larger counts will not fit either
+      }
+      const int chunks = 4;
+      const double ms = run_job(jb, ar, chunks);
+      if (!(ms > 0.0)) continue;
+      const int chunk = jb.en ? jb.en->chunk : 16;
+      const double rate = double(B) * double(maxp) * chunk * (chunks - 1) / (ms * 1e-3);
+      if (rate > best_rate) {
+        best_rate = rate;
+        best = B;
+        best_th = jb.en ? jb.en->z.th : t;
+      }
     }
   }
-  if (best > 0) tune_store(key, best, best_rate);
+  if (best > 0) tune_store(key, best, best_th, best_rate);
+  *th = best_th;
   return best;
 }
 
@@ -1164,9 +1198,12 @@ static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts
     rexii_opts osz = jb.o;
     if (any_depth_field) osz.method = 1;
     if (jb.o.pole_batch < 0) {
-      const int B = autotune_slots(jb.items, osz, st);
+      int th = 0;
+      const int B = autotune_slots(jb.items, osz, st, &th);
       jb.o.pole_batch = (B > 0) ? B : 0;
+      if (jb.o.tile_rows == 0 && (th == 16 || th == 32) && osz.method == 1) jb.o.tile_rows = th;
       osz.pole_batch = jb.o.pole_batch;
+      osz.tile_rows = jb.o.tile_rows;
     }
     size_t need = 0;
     rexii_status s0 = job_bytes(jb.items, osz, jb.keep, 0, &need);

@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("m0", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("pole_batch", ctypes.c_int32), ("pair_conjugate", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("method", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("method", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -53,7 +54,7 @@ class Report(ctypes.Structure):
                 ("stagnated", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
                 ("kernel_bytes", ctypes.c_double), ("step_ms", ctypes.c_double * 6),
-                ("u1_bytes", ctypes.c_double)]
+                ("u1_bytes", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,7 +111,8 @@ def _check(st, report=None):
 
 
 def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=None,
-              pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None, method=None):
+              pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None, method=None,
+              tile_rows=None):
     o = Opts()
     load().rexii_default_opts(ctypes.byref(o))
     if h is not None:
@@ -139,6 +141,8 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
         o.profile = int(profile)
     if method is not None:
         o.method = {"auto": 0, "cocg": 0, "bicgstab": 1}.get(method, method)
+    if tile_rows is not None:
+        o.tile_rows = int(tile_rows)
     return o
 
 

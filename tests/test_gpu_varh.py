@@ -131,3 +131,44 @@ def test_varh_2048_vs_oracle_samples(rx, case2048, precision, tol, bar):
     # W-energy of the whole field (the oracle's value is conserved to 1e-14)
     op = lrsw.LRSW(g["D"], g["D"], fc=g["f_c"], Hfield=Hf)
     assert abs(varh.w_energy(op, un) / g["w_energy_f"] - 1.0) <= 10 * bar
+
+
+# ---- work-tile height of the BiCGStab passes (16 or 32 rows) ---------------
+@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-10, 1e-10), ("mixed", 1e-6, 1e-6)])
+def test_varh_tile_rows(rx, rows, precision, tol, bar):
+    """72 rows: a ragged last tile for both heights (2 x 32 + 8, 4 x 16 + 8)."""
+    nx, ny = 96, 72
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, fc=20.0, Hfield=Hf)
+    t = 60.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=6, seed=52, velocity=True)
+    u, rep = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf), precision=precision, tol=tol, tile_rows=rows)
+    assert rep["tile_rows"] == rows and rep["not_converged"] == 0
+    assert em.rel_l2(u.cpu().numpy(), varh.chebyshev_expm(op, f, t)) <= bar
+
+
+def test_varh_tile_rows_invalid(rx):
+    Hf = inputs.variable_depth(32)
+    f = inputs.gaussian_bumps(32, nbumps=1, seed=1)
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(_dev(f), 0.1, fc=20.0, Hfield=_dev(Hf), tile_rows=24)
+    assert e.value.status == -1
+
+
+def test_varh_autotune_picks_tile(rx, tmp_path, monkeypatch):
+    """pole_batch < 0 tunes slots and tile rows together; the choice is cached."""
+    monkeypatch.setenv("REXII_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    D = 128
+    Hf = inputs.variable_depth(D)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = 40.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(D, nbumps=4, seed=53)
+    u, rep = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf), precision="mixed", pole_batch=-1)
+    assert rep["tile_rows"] in (16, 32) and rep["slots"] >= 1
+    cache = (tmp_path / "tune.txt").read_text()
+    assert f"T={rep['tile_rows']}" in cache and f"B={rep['slots']}" in cache
+    u2, rep2 = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf), precision="mixed", pole_batch=-1)
+    assert (rep2["tile_rows"], rep2["slots"]) == (rep["tile_rows"], rep["slots"])
+    ref = varh.chebyshev_expm(op, f, t)
+    assert em.rel_l2(u.cpu().numpy(), ref) <= 1e-6 and em.rel_l2(u2.cpu().numpy(), ref) <= 1e-6

@@ -118,8 +118,6 @@ __device__ __forceinline__ P* uni(P* v) {
 }
 template <typename X>
 __device__ __forceinline__ X ldu(const X* p) { return uni(ldc(p)); }
-template <typename P>
-__device__ __forceinline__ P* ldu_ptr(P* const* p) { return uni(ldc_ptr(p)); }
 
 // A slot record read by one vector load per wavefront: lane k loads the k-th
 // 8-byte word (a lane-dependent address, so the load never goes through the
@@ -184,10 +182,6 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 // Either form, chosen once per tile (block-uniform): the single-step form
 // is exact when the tile with its halo is no larger than the grid.
 __device__ __forceinline__ int wrapc(int i, int n, bool big) { return big ? wrap1(i, n) : wrap(i, n); }
-// The same with the choice fixed at compile time (pass kernels are
-// instantiated for both and pick one per work item).
-template <bool BIG>
-__device__ __forceinline__ int wrp(int i, int n) { return BIG ? wrap1(i, n) : wrap(i, n); }
 
 // ---------------------------------------------------------------------------
 // deterministic reductions (256 threads = 4 wavefronts of 64)
@@ -399,32 +393,6 @@ struct RowTile {
     if (int(threadIdx.x) < kSide) lds[sly * kW + slx] = sidev;
   }
 };
-
-// The same staging straight into LDS in PARTS rounds of loads (fewer live
-// registers, one memory round trip per round); call between barriers.
-template <typename V, int TH, int TW, int PARTS, typename F>
-__device__ __forceinline__ void stage_tile(V* lds, F f) {
-  constexpr int kN = TH * TW;
-  constexpr int kPer = (kN + kNT - 1) / kNT;
-  constexpr int kStep = (kPer + PARTS - 1) / PARTS;
-#pragma unroll
-  for (int m0 = 0; m0 < kPer; m0 += kStep) {
-    V v[kStep];
-#pragma unroll
-    for (int m = 0; m < kStep; ++m) {
-      const int k = threadIdx.x + (m0 + m) * kNT;
-      if (m0 + m < kPer && k < kN) {
-        const int ly = k / TW;
-        v[m] = f(ly, k - ly * TW);
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kStep; ++m) {
-      const int k = threadIdx.x + (m0 + m) * kNT;
-      if (m0 + m < kPer && k < kN) lds[k] = v[m];
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // work items (slot, tile)

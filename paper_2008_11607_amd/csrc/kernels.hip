@@ -61,7 +61,7 @@ constexpr int kPW = kTX + 8, kPH = kTY + 8;   // tile with halo 4
 constexpr int kNW = kTX + 4, kNH = kTY + 4;   // tile with halo 2
 
 
-// Control fields of a slot, read in one round of coherent loads.
+// Control fields of a slot, from one wavefront load of its record.
 struct SlotCtl {
   int status, par, rounds, it_inner, nx, ny, tiles_x;
   double cx, cy;

@@ -218,16 +218,11 @@ def run_varh2048(args):
     print(json.dumps(out), flush=True)
 
 
-def run_batched(args):
-    """Heterogeneous batch: 16 states (seeds 300..315) on grids drawn from
-    {128, 256, 512}^2 and t rho from U[50, 500] (a reduced form of 64 states on
-    up to 1024^2 with t rho up to 2000), mixed precision; one batched call
-    against one call per state (the oracle parity of batched calls is in the
-    tests)."""
+def _batch_vs_plain(spec, warm=True):
+    """One batched call against one plain call per state (mixed precision):
+    (states, sizes, work, seconds batched, seconds plain, max rel diff, not converged)."""
     import torch
     from paper_2008_11607_amd import inputs, rexii
-    spec = inputs.batched_instances(count=args.rhs if args.rhs > 8 else 16, seed0=300, sizes=(128, 256, 512),
-                                    trho_range=(50.0, 500.0))
     fs, ts, sizes = [], [], []
     for s_ in spec:
         f = inputs.gaussian_bumps(s_["D"], nbumps=16, seed=s_["seed"])
@@ -235,7 +230,8 @@ def run_batched(args):
         ts.append(s_["trho"] / rexii.rho(s_["D"], s_["D"], fc=FC))
         sizes.append(s_["D"])
     opts = dict(fc=FC, precision="mixed", tol=1e-6)
-    rexii.apply_batched(fs[:2], ts[:2], **opts)  # warm-up
+    if warm:
+        rexii.apply_batched(fs[:2], ts[:2], **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     us, reps = rexii.apply_batched(fs, ts, **opts)
@@ -247,15 +243,34 @@ def run_batched(args):
     ep = time.perf_counter() - t1
     work = sum(n * n * r["P"] for n, r in zip(sizes, reps))
     diffs = [float(torch.linalg.norm(u - v) / torch.linalg.norm(v)) for u, v in zip(us, plain)]
+    return fs, sizes, work, eb, ep, max(diffs), sum(r["not_converged"] for r in reps), reps[0]["slots"]
+
+
+def run_batched(args):
+    """Heterogeneous batch: 16 states (seeds 300..315) on grids drawn from
+    {128, 256, 512}^2 and t rho from U[50, 500] (a reduced form of 64 states on
+    up to 1024^2 with t rho up to 2000), mixed precision; one batched call
+    against one call per state (the oracle parity of batched calls is in the
+    tests).  Also 64 small states (128^2, t rho from U[50, 200], seeds
+    400..463), where one state alone cannot fill the GPU."""
+    from paper_2008_11607_amd import inputs
+    spec = inputs.batched_instances(count=args.rhs if args.rhs > 8 else 16, seed0=300, sizes=(128, 256, 512),
+                                    trho_range=(50.0, 500.0))
+    fs, sizes, work, eb, ep, dmax, nc, slots = _batch_vs_plain(spec)
+    small = inputs.batched_instances(count=64, seed0=400, sizes=(128,), trho_range=(50.0, 200.0))
+    _, _, work_s, eb_s, ep_s, dmax_s, nc_s, slots_s = _batch_vs_plain(small, warm=False)
     print(json.dumps({"metric": METRIC, "value": work / eb, "unit": "grid-pt·pole solves/s", "n_gpus": 1, "steps": 1,
                       "warmup": 1, "ms_per_step": 1000 * eb, "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
                       "config": {"workload": f"lrsw-fd-batched-{len(fs)}-mixed-grids-128-512-trho50-500",
                                  "states": len(fs), "grids": sorted(set(sizes)),
-                                 "precision": "mixed", "tol": 1e-6},
+                                 "precision": "mixed", "tol": 1e-6, "slots": slots},
                       "plain_calls_value": work / ep, "speedup_vs_plain_calls": ep / eb,
-                      "max_rel_l2_batched_vs_plain": max(diffs),
-                      "not_converged": sum(r["not_converged"] for r in reps)}), flush=True)
+                      "max_rel_l2_batched_vs_plain": dmax, "not_converged": nc,
+                      "small_states": {"workload": "64 states, 128^2, t rho U[50, 200]", "value": work_s / eb_s,
+                                       "ms": 1000 * eb_s, "plain_calls_value": work_s / ep_s,
+                                       "speedup_vs_plain_calls": ep_s / eb_s, "slots": slots_s,
+                                       "max_rel_l2_batched_vs_plain": dmax_s, "not_converged": nc_s}}), flush=True)
 
 
 def main():

@@ -67,3 +67,22 @@ def test_autotuned_slots(rx, tmp_path, monkeypatch):
     assert r2["slots"] == r1["slots"]
     assert bool((u1 == u2).all())
     assert em.rel_l2(u1.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
+def test_batched_many_slots(rx):
+    """Several hundred slots (each scheduler thread owns up to four): the
+    batch agrees with the oracle and with one call per problem."""
+    shapes = [(32, 32, 160.0), (48, 40, 220.0), (40, 48, 120.0), (64, 32, 260.0), (32, 56, 200.0)]
+    fs, ts, ops = [], [], []
+    for i, (nx, ny, trho) in enumerate(shapes):
+        op = lrsw.LRSW(nx, ny, fc=10.0)
+        fs.append(inputs.gaussian_bumps(nx, ny, nbumps=4, seed=500 + i, velocity=(i % 2 == 1)))
+        ts.append(trho / lrsw.rho(op))
+        ops.append(op)
+    us, reps = rx.apply_batched([_dev(f) for f in fs], ts, fc=10.0, pole_batch=1024)
+    assert reps[0]["slots"] > 256
+    for f, t, op, u, rep in zip(fs, ts, ops, us, reps):
+        assert rep["not_converged"] == 0
+        assert em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10
+    u1, _ = rx.apply(_dev(fs[3]), ts[3], fc=10.0)
+    assert em.rel_l2(us[3].cpu().numpy(), u1.cpu().numpy()) <= 1e-9

@@ -121,12 +121,14 @@ typedef struct rexii_report {
     double h, t, rho;
     double kappa_sum;        /* sum |alpha_k t| / |h mu|: amplification of
                                per-pole errors in the weighted sum          */
-    double pole_tol;         /* relative residual each solve is driven to   */
+    double pole_tol;         /* tightest relative residual a solve is driven
+                               to: solve s gets tol / (S a_s), a_s the sum
+                               of its poles' |w_k| / |h mu| (capped 1e-2)   */
     double max_rel_residual; /* largest final FP64 relative residual        */
     double seconds;          /* host wall time of the call                  */
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
     int32_t stagnated;       /* solves stopped at their FP64 residual floor
-                               (above pole_tol; counted as converged)       */
+                               (above their tolerance; counted as converged)       */
     int32_t slots;           /* concurrent solves the engine ran with        */
     /* with opts.profile = 1: launches and summed HIP-event time of the COCG
      * pass kernel, and the algorithmic bytes of those launches (a pass reads

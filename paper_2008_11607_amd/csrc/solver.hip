@@ -98,6 +98,7 @@ struct SolveDesc {
   cd c0, c1, c2;       // accumulation weights (A_j += Re(c_j y))
   cd inv_sigma, m1, m2;
   double cost;         // expected relative Krylov cost (for scheduling)
+  double tol = 0.0;    // relative residual this solve is driven to
   int pole;            // first pole index this solve serves
 };
 
@@ -299,6 +300,27 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
       s.cost = cheb_cost(s.zeta, lmax, pl.pole_tol);
       s.pole = k;
       pl.solves.push_back(s);
+    }
+  }
+  // Per-solve tolerances.  With a_s = (sum of |w_k| over the poles solve s
+  // serves) / |h mu|, the error of the weighted sum is at most
+  // sum_s a_s eps_s ||f|| (each resolvent has norm <= 1/|h mu|, A being
+  // skew), so any eps_s with sum_s a_s eps_s <= tol meets tol.  The uniform
+  // choice eps_s = tol / kappa_sum (kappa_sum = sum_s a_s) over-solves the
+  // light poles (the two poles of a term differ ~160-fold in weight); an
+  // equal share of the bound, eps_s = tol / (S a_s), minimises the total
+  // digits sum_s log(1/eps_s) (Krylov work is about linear in digits),
+  // capped at 1e-2.
+  {
+    const double hmu = std::abs(pl.h * mu());
+    const double S = double(pl.solves.size());
+    pl.pole_tol = 1.0;
+    for (SolveDesc& sd : pl.solves) {
+      double a = std::abs(pl.w[sd.pole]) / hmu;
+      if (pl.paired) a += std::abs(pl.w[sd.pole + 1]) / hmu;
+      sd.tol = (a > 0.0) ? std::min(pl.tol / (S * a), 1e-2) : 1e-2;
+      pl.pole_tol = std::min(pl.pole_tol, sd.tol);
+      sd.cost = cheb_cost(pl.bicg ? sd.zeta / pl.hmax : sd.zeta, lmax, sd.tol);
     }
   }
   // most expensive first (longest-processing-time order for the slot queue)
@@ -524,7 +546,7 @@ struct Engine {
       D.c2 = to_d2(d.c2);
       D.gamma = to_d2(d.gamma);
       D.sc = to_d2(d.sc);
-      D.tol2 = pl.pole_tol * pl.pole_tol;
+      D.tol2 = d.tol * d.tol;
       D.inst = q[j].inst;
       hs[j] = D;
       solve_inst[j] = q[j].inst;
@@ -760,6 +782,7 @@ static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>
     const cd zk = shifts[k];
     const cd den = zk * zk + t * t * fc * fc;
     SolveDesc s;
+    s.tol = tol;  // explicit shifts: every solve to the caller's tolerance
     s.m1 = -zk / den;
     s.m2 = -t * fc / den;
     if (pl.bicg) {

@@ -101,6 +101,18 @@ def test_apply_mixed(rx, nx, trho):
     assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-6
 
 
+def test_per_solve_tolerances_mixed_unpaired(rx):
+    """Unpaired solves (initial velocity) in mixed precision: each solve gets
+    tol / (S a_s), so the light pole of a term runs to a looser residual than
+    the heavy one, and the sum still meets tol."""
+    op, rho, t, f = _case(128, 96, 300.0, nbumps=8, seed=12, velocity=True)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision="mixed", tol=1e-6)
+    assert rep["solves"] == rep["P"] and rep["not_converged"] == 0
+    assert rep["pole_tol"] <= 1e-6 / rep["kappa_sum"]          # the heavy solves are tighter ...
+    assert rep["max_rel_residual"] > 10 * 1e-6 / rep["kappa_sum"]  # ... the light ones looser
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-6
+
+
 def test_deterministic(rx):
     op, rho, t, f = _case(64, 64, 100.0, nbumps=3, seed=4)
     fd = _dev(f)

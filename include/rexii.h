@@ -122,8 +122,10 @@ typedef struct rexii_report {
     double kappa_sum;        /* sum |alpha_k t| / |h mu|: amplification of
                                per-pole errors in the weighted sum          */
     double pole_tol;         /* tightest relative residual a solve is driven
-                               to: solve s gets tol / (S a_s), a_s the sum
-                               of its poles' |w_k| / |h mu| (capped 1e-2)   */
+                               to: solve s gets tol c_s / (a_s sum_j c_j),
+                               a_s the sum of its poles' |w_k| / |h mu|,
+                               c_s its estimated iterations per e-fold
+                               (capped at 1e-2)                             */
     double max_rel_residual; /* largest final FP64 relative residual        */
     double seconds;          /* host wall time of the call                  */
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */

@@ -313,12 +313,26 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   // capped at 1e-2.
   {
     const double hmu = std::abs(pl.h * mu());
-    const double S = double(pl.solves.size());
+    // iterations per e-fold of each solve (Chebyshev estimate), clamped to
+    // [1/4, 4] x the median so that one badly estimated solve cannot take
+    // the budget of the others
+    std::vector<double> c(pl.solves.size());
+    for (size_t i = 0; i < c.size(); ++i)
+      c[i] = cheb_cost(pl.bicg ? pl.solves[i].zeta / pl.hmax : pl.solves[i].zeta, lmax, 2.0 / M_E);
+    std::vector<double> cs = c;
+    std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
+    const double cmed = cs.empty() ? 1.0 : std::min(cs[cs.size() / 2], 1e6);
+    double csum = 0.0;
+    for (double& ci : c) {
+      ci = std::min(std::max(ci, 0.25 * cmed), 4.0 * cmed);
+      csum += ci;
+    }
     pl.pole_tol = 1.0;
-    for (SolveDesc& sd : pl.solves) {
+    for (size_t i = 0; i < c.size(); ++i) {
+      SolveDesc& sd = pl.solves[i];
       double a = std::abs(pl.w[sd.pole]) / hmu;
       if (pl.paired) a += std::abs(pl.w[sd.pole + 1]) / hmu;
-      sd.tol = (a > 0.0) ? std::min(pl.tol / (S * a), 1e-2) : 1e-2;
+      sd.tol = (a > 0.0) ? std::min(pl.tol * c[i] / (a * csum), 1e-2) : 1e-2;
       pl.pole_tol = std::min(pl.pole_tol, sd.tol);
       sd.cost = cheb_cost(pl.bicg ? sd.zeta / pl.hmax : sd.zeta, lmax, sd.tol);
     }

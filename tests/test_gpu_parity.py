@@ -103,8 +103,9 @@ def test_apply_mixed(rx, nx, trho):
 
 def test_per_solve_tolerances_mixed_unpaired(rx):
     """Unpaired solves (initial velocity) in mixed precision: each solve gets
-    tol / (S a_s), so the light pole of a term runs to a looser residual than
-    the heavy one, and the sum still meets tol."""
+    its share of the error bound (tol c_s / (a_s sum c)), so the light pole of
+    a term runs to a looser residual than the heavy one, and the sum still
+    meets tol."""
     op, rho, t, f = _case(128, 96, 300.0, nbumps=8, seed=12, velocity=True)
     u, rep = rx.apply(_dev(f), t, fc=10.0, precision="mixed", tol=1e-6)
     assert rep["solves"] == rep["P"] and rep["not_converged"] == 0

@@ -313,7 +313,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the pole-sharded multi-GPU "
-              "form is a design, not part of this build.", file=sys.stderr)
+              "form is described in the design notes and not implemented.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "varh2048":

@@ -5,7 +5,7 @@ Test infrastructure only (see the oracle package docstring).
 
 The paper's operator (Sec. 4) acts on f = (eta, u, v) as
     A f = (-d_x u - d_y v,  -d_x eta + v,  -d_y eta - u)
-with spectral derivatives and unit Coriolis parameter.  This build keeps the
+with spectral derivatives and unit Coriolis parameter.  This module keeps the
 same sign pattern, with gravity g, depth H (constant, or a field in flux
 form) and Coriolis parameter f_c:
     A f = (-dx(H u) - dy(H v),  -g dx eta + f_c v,  -g dy eta - f_c u),

@@ -1,4 +1,4 @@
-// Host driver of the REXII shifted-solve path and the C ABI entry points.
+// Host side of the REXII shifted-solve path and the C ABI entry points.
 //
 // One call of rexii_apply:
 //   1. rho and the pole set (coeffs.cpp; eq. matrixAccuracyBound);
@@ -1209,7 +1209,7 @@ static rexii_status on_private_stream(hipStream_t caller, F&& body) {
   return st;
 }
 
-// Common driver of apply / batched / shifted_solve.
+// Common path of apply / batched / shifted_solve.
 static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts_in, void* ws, size_t ws_bytes,
                               hipStream_t stream) {
   const auto t0 = std::chrono::steady_clock::now();

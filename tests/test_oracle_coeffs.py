@@ -161,5 +161,5 @@ def test_pole_structure_and_counts():
     z = c["z"]
     assert np.allclose(z[0::2].real, h * MU) and np.allclose(z[1::2].real, -h * MU)
     assert np.allclose(z[1::2], -np.conj(z[0::2]))
-    # kappa_sum grows with t rho (survey values 2.3e2 at t rho = 100).
+    # kappa_sum grows with t rho (about 2.3e2 at t rho = 100).
     assert 200.0 < c["kappa_sum"] < 260.0

@@ -84,15 +84,29 @@ void poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w) 
   z.resize(2 * (N + 1));
   w.resize(2 * (N + 1));
   const double eh2 = std::exp(h * h);
+  // Where the window is the full k = -L..L, b_{n-k} = e^{h^2} e^{-inh} e^{ikh}
+  // makes the k-sum a fixed factor: c_{j,n} = h e^{h^2} e^{-inh} S_j.
+  complex<double> S1(0.0, 0.0), S2(0.0, 0.0);
+  for (int k = -kL; k <= kL; ++k) {
+    const complex<double> e = std::polar(1.0, static_cast<double>(k) * h);
+    S1 += a_re(k) * e;
+    S2 += a_im(k) * e;
+  }
   for (int n = 0; n <= N; ++n) {
     // c_{1,n}, c_{2,n}: k from L1(n) = max(-L, n-M) to L2(n) = min(L, n+M)
     complex<double> c1(0.0, 0.0), c2(0.0, 0.0);
     const int k1 = std::max(-kL, n - M), k2 = std::min(kL, n + M);
-    for (int k = k1; k <= k2; ++k) {
-      const double m = static_cast<double>(n - k);
-      const complex<double> bm = std::polar(eh2, -m * h);  // e^{h^2} e^{-imh}
-      c1 += a_re(k) * bm;
-      c2 += a_im(k) * bm;
+    if (k1 == -kL && k2 == kL) {
+      const complex<double> e = std::polar(eh2, -static_cast<double>(n) * h);
+      c1 = e * S1;
+      c2 = e * S2;
+    } else {
+      for (int k = k1; k <= k2; ++k) {
+        const double m = static_cast<double>(n - k);
+        const complex<double> bm = std::polar(eh2, -m * h);  // e^{h^2} e^{-imh}
+        c1 += a_re(k) * bm;
+        c2 += a_im(k) * bm;
+      }
     }
     c1 *= h;
     c2 *= h;

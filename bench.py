@@ -51,6 +51,8 @@ TRAFFIC = {
     "k_pass_f32": {"bytes_per_launch": 1553566515.7, "fetch_kib": 390749.21, "write_kib": 735675.10,
                    "sources": ["kernels.hip", "kernels.h", "device_util.h"],
                    "sources_sha256": "ecf904a25a6e4aebc7812628fe25905d2466ad9cca83c814ecf09f696d270910"},
+    "k_mode_filter": {"bytes_per_launch": None, "sources": ["kernels_fft.hip", "kernels_fft.h"],
+                      "sources_sha256": None},
     "k_bcg_u1_f32": {"bytes_per_launch": 1449208214.6, "fetch_kib": 436723.81, "write_kib": 541815.70,
                      "sources": ["kernels_vh.hip", "kernels.h", "device_util.h"],
                      "sources_sha256": "6fecb750d684290a88d91142c465f9cb57332c5143a4d7af5cea636593b551e4"},
@@ -93,7 +95,7 @@ def w_energy(u, H, g=1.0):
     return float(g * np.sum(u[0] ** 2) + np.sum(H * (u[1] ** 2 + u[2] ** 2)))
 
 
-def cpu_baseline(f, t, budget_s=12.0):
+def cpu_baseline(f, t, budget_s=12.0, tol=1e-6):
     """The oracle's per-mode REXII (one batched 3x3 solve per pole over all
     D^2 Fourier modes, numpy), on the leading poles of the same pole set
     until the time budget is spent."""
@@ -101,7 +103,7 @@ def cpu_baseline(f, t, budget_s=12.0):
     from oracle import lrsw
     from oracle import rexii_modes as rm
     op = lrsw.LRSW(D, D, fc=FC)
-    c = oc.api_coeffs(t, lrsw.rho(op), h=0.5, tol=1e-6)
+    c = oc.api_coeffs(t, lrsw.rho(op), h=0.5, tol=tol)
     done = 0
     t0 = time.perf_counter()
     step = 8
@@ -290,6 +292,85 @@ def run_batched(args):
                                        "max_rel_l2_batched_vs_plain": dmax_s, "not_converged": nc_s}}), flush=True)
 
 
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic FP64 flops of the mode kernel: per (term, mode) s = a + theta^2
+# (1), d = s^2 + b^2 (2), 1/d (1), the two accumulations (A s + B)/d (8); per
+# mode the symbol and the two products with t A(k) and the combination (84)
+FLOPS_PER_TERM_MODE = 12
+FLOPS_PER_MODE = 84
+
+
+def _fourier_case(D, fc, trho, nbumps, seed, gold_name, steps, warmup):
+    import torch
+    from paper_2008_11607_amd import inputs
+    from paper_2008_11607_amd import rexii
+    f = inputs.gaussian_bumps(D, nbumps=nbumps, seed=seed)
+    rho = rexii.rho(D, D, fc=fc)
+    t = trho / rho
+    gold = golden(gold_name)
+    assert abs(gold["t"] - t) <= 1e-12 * t, "workload differs from the stored oracle values"
+    fd = torch.from_numpy(f).cuda()
+    u = torch.empty_like(fd)
+    opts = dict(fc=fc, tol=1e-10, profile=1)
+    ws = torch.empty(rexii.fourier_workspace_size(D, D, t, fc=fc, tol=1e-10), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        rexii.apply_fourier(fd, t, out=u, workspace=ws, **opts)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, rep = rexii.apply_fourier(fd, t, out=u, workspace=ws, **opts)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    P, nterm = reps[0]["P"], reps[0]["solves"]
+    nm = (D // 2 + 1) * D
+    k_ms = sum(r["kernel_ms"] for r in reps) / steps
+    flops = nm * (nterm * FLOPS_PER_TERM_MODE + FLOPS_PER_MODE)
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    step_ms = [sum(r["step_ms"][k] for r in reps) / steps for k in range(4)]
+    return {"D": D, "t_rho": trho, "f_c": fc, "P": P, "terms": nterm, "el": el, "ms": 1000.0 * el / steps,
+            "value": D * D * P / (el / steps), "rel_l2_vs_oracle": sampled_rel_l2(u, gold),
+            "roofline": {"bound": "alu", "kernel": "k_mode_filter", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                         "traffic": traffic_if_current("k_mode_filter"),
+                         "avg_launch_ms": k_ms, "launches": steps, "alg_flops_per_launch": flops,
+                         "waves_per_block": reps[0]["slots"],
+                         "kernel_time_share": k_ms * steps * 1e-3 / el},
+            "ms_by_stage": {"copy_check": step_ms[0], "fft_forward": step_ms[1], "mode_filter": step_ms[2],
+                            "fft_inverse": step_ms[3]},
+            "hbm_gbs_alg": sum(r["alg_bytes"] for r in reps) / el / 1e9}
+
+
+def run_fourier(args):
+    """Fourier-space REXII (constant depth, FP64): the 512^2 t rho = 1000
+    workload of the headline line, and a 2048^2 t rho = 5000 constant-depth
+    workload (f_c = 20)."""
+    steps = max(args.steps, 20)
+    c = _fourier_case(D, FC, TRHO, NBUMPS, SEED, "lrsw512_trho1000.json", steps, max(args.warmup, 3))
+    big = _fourier_case(2048, 20.0, 5000.0, 16, 5, "lrsw2048_trho5000.json", max(args.steps, 5),
+                        max(args.warmup, 1))
+    out = {
+        "metric": METRIC, "value": c["value"], "unit": "grid-pt·pole solves/s", "n_gpus": 1,
+        "steps": steps, "warmup": max(args.warmup, 3), "ms_per_step": c["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "lrsw-fd-512x512-trho1000-16bumps-fourier", "D": D, "t_rho": TRHO, "f_c": FC,
+                   "method": "Fourier-space REXII: rocFFT real transforms, per-mode closed-form pole sum (FP64)",
+                   "tol": 1e-10, "P": c["P"], "terms": c["terms"], "h": 0.5},
+        "rel_l2_vs_oracle": c["rel_l2_vs_oracle"],
+        "hbm_gbs_alg": c["hbm_gbs_alg"],
+        "roofline": c["roofline"],
+        "ms_by_stage": c["ms_by_stage"],
+        "large": {k: big[k] for k in ("D", "t_rho", "f_c", "P", "terms", "ms", "value", "rel_l2_vs_oracle",
+                                      "roofline", "ms_by_stage")},
+    }
+    out["large"]["workload"] = "lrsw-fd-2048x2048-fc20-trho5000-16bumps-fourier"
+    if not args.no_cpu:
+        f, _, t = workload()
+        out["cpu_baseline"] = cpu_baseline(f, t, tol=1e-10)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,9 +380,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--slots", type=int, default=-1,
                     help="concurrent solves; -1 (default) autotunes on the first call and caches the choice")
-    ap.add_argument("--workload", default="lrsw512", choices=["lrsw512", "varh2048", "batched"],
+    ap.add_argument("--workload", default="lrsw512", choices=["lrsw512", "varh2048", "batched", "fourier"],
                     help="lrsw512 (default): the headline line; varh2048: 2048^2 variable depth; "
-                         "batched: heterogeneous batch against plain calls")
+                         "batched: heterogeneous batch against plain calls; fourier: the Fourier-space "
+                         "path (constant depth) on the 512^2 workload and a 2048^2 one")
     ap.add_argument("--rhs", type=int, default=8, help="states of the varh2048 / batched workloads")
     ap.add_argument("--subset", type=int, default=16,
                     help="varh2048: values of n in the t rho = 5000 pole subset (0 = skip)")
@@ -321,6 +403,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "fourier":
+        run_fourier(args)
         return
 
     import torch

@@ -213,6 +213,46 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
                                  void* workspace, size_t ws_bytes, hipStream_t stream,
                                  rexii_report* rep);
 
+/* Fourier-space REXII for a constant depth, the way the paper evaluates its
+ * own test problem (Sec. 4: FFT, the pole sum per Fourier mode, inverse FFT).
+ * Each mode's 3x3 symbol A_hat(k) has eigenvalues 0 and +-i omega(k), so
+ * r(t A_hat) = c0 I + c1 t A_hat + c2 (t A_hat)^2 with c0, c1, c2 the
+ * interpolation coefficients of r(x) = sum_k w_k / (x - z_k) on
+ * {0, +-i t omega} (Theorem 1, eq. teorem); the real part of the REXII sum
+ * (eq. modifiedRexiMatrixReducedSum) is a quadratic with the real parts of
+ * those coefficients, applied to the half spectrum of a real FFT.  Same
+ * poles, weights and result as rexii_apply with exact shifted solves; no
+ * iterations.  All arithmetic FP64 (opts.precision is ignored).
+ *   derivative: REXII_DERIV_CENTRED, the operator of rexii_apply, symbol
+ *     s = n sin(2 pi k / n); or REXII_DERIV_SPECTRAL, Fourier differentiation
+ *     on the unit square, s = 2 pi k for signed k with the Nyquist mode's
+ *     derivative 0 (the paper's discretisation).
+ *   op->H_field must be NULL.  opts: h, tol, m0 and rho as for rexii_apply
+ *     (rho <= 0: the exact maximum of omega over the modes); other fields
+ *     ignored except profile.  f, u: device [3][ny][nx], not overlapping.
+ *   Workspace: rexii_fourier_workspace_size() bytes (half spectra
+ *     [3][ny][nx/2+1] complex128, the term table, the FFT work buffer), or
+ *     NULL to let the library allocate.  FFT plans are created on first use
+ *     per device and grid and kept until the process ends.
+ *   Report: P, M, N, m0, h, t, rho, kappa_sum; solves = terms of the per-mode
+ *     sum (two poles of one n share a denominator); slots = waves per block
+ *     of the mode kernel; alg_bytes = algorithmic HBM bytes of the path;
+ *     kernel_bytes = those of the mode kernel (96 per half-spectrum mode).
+ *     With opts.profile = 1: step_ms[0..3] = copy and finiteness check,
+ *     forward FFT, mode kernel, inverse FFT (HIP events, ms); kernel_ms =
+ *     step_ms[2], kernel_launches = 1.
+ * Errors: INVALID_ARG (also for a depth field or an unknown derivative),
+ * NONFINITE (u is written anyway), OOM, HIP (including rocFFT failures),
+ * WORKSPACE. */
+enum { REXII_DERIV_CENTRED = 0, REXII_DERIV_SPECTRAL = 1 };
+
+rexii_status rexii_fourier_workspace_size(const rexii_swe_op* op, const rexii_opts* opts, double t,
+                                          int32_t derivative, size_t* bytes);
+
+rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double* u, double t,
+                                 int32_t derivative, const rexii_opts* opts, void* workspace,
+                                 size_t ws_bytes, hipStream_t stream, rexii_report* rep);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* rexii_last_error(void);
 

@@ -7,13 +7,15 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librexii.so")
 
-SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "solver.hip"]
+SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "solver.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# rocFFT for the Fourier-space path
+LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose=False):
@@ -21,7 +23,7 @@ def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include")] + \
-          [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+          [os.path.join(CSRC, s) for s in SOURCES] + LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

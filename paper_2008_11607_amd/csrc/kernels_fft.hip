@@ -1,0 +1,268 @@
+// Fourier-space REXII for a constant depth (the paper solves its test
+// problem this way, per Fourier mode, Sec. 4).
+//
+// After a 2D FFT of (eta, u, v), mode k carries the 3 x 3 symbol
+//   A(k) = [[0, -i H s_x, -i H s_y], [-i g s_x, 0, f_c], [-i g s_y, -f_c, 0]],
+// with s = n sin(2 pi k / n) for centred differences, or s = 2 pi k (signed
+// k, the odd derivative of the Nyquist mode taken as 0) for Fourier
+// differentiation.  Its eigenvalues are 0 and +-i omega,
+// omega^2 = f_c^2 + g H (s_x^2 + s_y^2), so for X = t A(k) and theta = t omega
+// any function r of X is the quadratic that interpolates r on {0, +-i theta}
+// (Theorem 1 of the paper, matrix functions through the eigenvalues):
+//   r(X) = c0 I + c1 X + c2 X^2.
+// For one pole, r(x) = w / (x - z), the Newton divided differences on the
+// nodes (0, i theta, -i theta) are w/(-z), w/(z (i theta - z)) and
+// -w/(z (z^2 + theta^2)), which give
+//   c1 = -w / (z^2 + theta^2),  c2 = (-w / z) / (z^2 + theta^2).
+// The result must be real (eq. modifiedRexiMatrixReducedSum takes the real
+// part); since A(-k) = conj(A(k)) and F(-k) = conj(F(k)) for a real state,
+// the real part in physical space is, per mode, the same quadratic with
+// Re c0, Re c1, Re c2.  So the half spectrum of a real-to-complex FFT is
+// filtered with real coefficients and a complex-to-real FFT returns u.
+//
+// Per term of the sum the filter needs Re(c1) and Re(c2) at theta^2:
+// with z^2 = a + i b and s = a + theta^2,
+//   Re(-w e) = -(w_r s + w_i b) / (s^2 + b^2),  e = 1/(z^2 + theta^2),
+// and the two poles of one term of the reduced sum have equal a and b^2
+// (z_2 = -conj(z_1)), so they share the denominator s^2 + b^2 and are
+// merged into one table entry (a, b^2, A1, B1, A2, B2):
+//   Re c1 += (A1 s + B1) / (s^2 + b^2),  Re c2 += (A2 s + B2) / (s^2 + b^2).
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "kernels.h"
+#include "kernels_fft.h"
+#include "rexii_internal.h"
+
+namespace rexii {
+
+constexpr int kModeWaves = 16;  // most waves (term slices) per block
+constexpr int kTermDoubles = 6;
+
+// 1/x to full FP64 precision: hardware reciprocal estimate and two
+// Newton-Raphson steps r <- r + r (1 - x r) (each squares the relative error).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// s * s + b with b read from a scalar register (one VOP3 instruction; the
+// compiler otherwise copies b into vector registers for a VOP2 fmac).
+__device__ __forceinline__ double sq_plus(double s, double b) {
+  double d;
+  asm("v_fma_f64 %0, %1, %1, %2" : "=v"(d) : "v"(s), "s"(b));
+  return d;
+}
+
+// s for wavenumber index k of an axis of n points (see file comment).
+__device__ __forceinline__ double axis_symbol(int k, int n, int deriv) {
+  if (deriv == 0) return double(n) * sinpi(double(2 * k) / double(n));
+  const int ks = (2 * k == n) ? 0 : (2 * k < n ? k : k - n);
+  return 2.0 * M_PI * double(ks);
+}
+
+// F: [3][ny][nxh] half spectra (nxh = nx/2 + 1), filtered in place:
+// F <- scale (c0 F + C1 X F + C2 X^2 F), X = t A(k).  tab: nterm entries of
+// kTermDoubles.  Block: 64 modes (one per lane) x nw waves; wave w sums the
+// terms of slice w, the slices are added in wave order (through
+// (nw - 1) x 1 KB of dynamic LDS), and wave 0 applies the filter.
+__global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __restrict__ F, int nx, int ny, int deriv,
+                                                                 double t, double g, double H, double fc, double c0,
+                                                                 double scale, const double* __restrict__ tab,
+                                                                 int nterm) {
+  extern __shared__ double red[];  // [nw - 1][2][64] partial sums of waves 1..nw-1
+  const int nxh = nx / 2 + 1;
+  const int nm = nxh * ny;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int nw = int(blockDim.x >> 6);
+  const int m = int(blockIdx.x) * 64 + lane;
+  const bool live = m < nm;
+  const int kx = live ? m % nxh : 0, ky = live ? m / nxh : 0;
+  const double sx = axis_symbol(kx, nx, deriv), sy = axis_symbol(ky, ny, deriv);
+  const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
+
+  const int per = (nterm + nw - 1) / nw;
+  const int lo = min(nterm, w * per), hi = min(nterm, lo + per);
+  // (A s + B) / d is accumulated as (s/d) A + (1/d) B: one scalar (table)
+  // operand per FMA, and four independent chains.  Two terms share one
+  // reciprocal, 1/d1 = d2/(d1 d2) (d >= b^2 > 0 and d >= a^2 > 0 for the
+  // n = 0 term, so the product neither underflows nor overflows).
+  double c1a = 0.0, c1b = 0.0, c2a = 0.0, c2b = 0.0;
+  auto one = [&](const double* q, double i1) {
+    const double e1 = i1 * (q[0] + th2);
+    c1a = fma(e1, q[2], c1a);
+    c1b = fma(i1, q[3], c1b);
+    c2a = fma(e1, q[4], c2a);
+    c2b = fma(i1, q[5], c2b);
+  };
+  auto pair = [&](const double* q) {
+    const double s1 = q[0] + th2, s2 = q[kTermDoubles] + th2;
+    const double d1 = sq_plus(s1, q[1]), d2 = sq_plus(s2, q[kTermDoubles + 1]);
+    const double r = recip(d1 * d2);
+    one(q, r * d2);
+    one(q + kTermDoubles, r * d1);
+  };
+  int j = lo;
+  for (; j + 3 < hi; j += 4) {  // unrolled by hand: the loads of two pairs issue together
+    const double* q = tab + size_t(j) * kTermDoubles;
+    pair(q);
+    pair(q + 2 * kTermDoubles);
+  }
+  if (j + 1 < hi) {
+    pair(tab + size_t(j) * kTermDoubles);
+    j += 2;
+  }
+  if (j < hi) {
+    const double* q = tab + size_t(j) * kTermDoubles;
+    const double s1 = q[0] + th2;
+    one(q, recip(fma(s1, s1, q[1])));
+  }
+  double c1 = c1a + c1b, c2 = c2a + c2b;
+  if (nw > 1) {
+    if (w > 0) {
+      red[(w - 1) * 128 + lane] = c1;
+      red[(w - 1) * 128 + 64 + lane] = c2;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int v = 1; v < nw; ++v) {
+      c1 += red[(v - 1) * 128 + lane];
+      c2 += red[(v - 1) * 128 + 64 + lane];
+    }
+  }
+  if (!live) return;
+
+  double2 f[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) f[c] = F[size_t(c) * nm + m];
+  // X v with X = t A(k); -i a (x + i y) = (a y, -a x)
+  const double hx = t * H * sx, hy = t * H * sy, gx = t * g * sx, gy = t * g * sy, tf = t * fc;
+  auto apply = [&](const double2 (&v)[3], double2 (&o)[3]) {
+    o[0] = make_double2(hx * v[1].y + hy * v[2].y, -(hx * v[1].x + hy * v[2].x));
+    o[1] = make_double2(gx * v[0].y + tf * v[2].x, -gx * v[0].x + tf * v[2].y);
+    o[2] = make_double2(gy * v[0].y - tf * v[1].x, -gy * v[0].x - tf * v[1].y);
+  };
+  double2 x1[3], x2[3];
+  apply(f, x1);
+  apply(x1, x2);
+  const double a0 = scale * c0, a1 = scale * c1, a2 = scale * c2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    F[size_t(c) * nm + m] = make_double2(a0 * f[c].x + a1 * x1[c].x + a2 * x2[c].x,
+                                         a0 * f[c].y + a1 * x1[c].y + a2 * x2[c].y);
+}
+
+// u = f, flag[0] = 1 if any value is not finite.
+__global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ u, size_t n, int* flag) {
+  bool bad = false;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double v = f[i];
+    u[i] = v;
+    bad = bad || !isfinite(v);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// Waves per block: 8 (measured best at 512^2 and 2048^2 with 2000-10000
+// terms), fewer when a wave would get under 64 terms.
+int mode_filter_waves(int nx, int ny, int nterm) {
+  (void)nx;
+  (void)ny;
+  int nw = 1;
+  while (nw < 8 && nterm >= 128 * nw) nw *= 2;
+  return nw;
+}
+
+void launch_mode_filter(double2* F, int nx, int ny, int deriv, double t, double g, double H, double fc, double c0,
+                        double scale, const double* tab, int nterm, int nw, hipStream_t s) {
+  const long nm = long(nx / 2 + 1) * ny;
+  const size_t lds = size_t(nw - 1) * 128 * sizeof(double);
+  hipLaunchKernelGGL(k_mode_filter, dim3(unsigned((nm + 63) / 64)), dim3(64 * nw), lds, s, F, nx, ny, deriv, t, g,
+                     H, fc, c0, scale, tab, nterm);
+}
+
+void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s) {
+  size_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_copy_check, dim3(unsigned(b)), dim3(256), 0, s, f, u, n, flag);
+}
+
+// ---------------------------------------------------------------------------
+// rocFFT plans: batch of 3 real 2D transforms, [3][ny][nx] real <->
+// [3][ny][nx/2+1] complex, not in place, FP64.  Cached per (device, nx, ny)
+// for the life of the process.
+// ---------------------------------------------------------------------------
+namespace {
+struct FftPair {
+  rocfft_plan fwd = nullptr, inv = nullptr;
+  size_t work = 0;
+};
+std::mutex g_fft_mu;
+std::map<std::tuple<int, int, int>, FftPair> g_fft;
+bool g_fft_setup = false;
+
+std::string fft_msg(const char* what, rocfft_status s) { return std::string(what) + " failed (rocfft status " + std::to_string(int(s)) + ")"; }
+}  // namespace
+
+rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(REXII_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_fft_mu);
+  if (!g_fft_setup) {
+    const rocfft_status s = rocfft_setup();
+    if (s != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_setup", s));
+    g_fft_setup = true;
+  }
+  const auto key = std::make_tuple(dev, nx, ny);
+  auto it = g_fft.find(key);
+  if (it == g_fft.end()) {
+    FftPair p;
+    const size_t len[2] = {size_t(nx), size_t(ny)};  // fastest dimension first
+    rocfft_status s = rocfft_plan_create(&p.fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                                         rocfft_precision_double, 2, len, 3, nullptr);
+    if (s != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_plan_create (forward)", s));
+    s = rocfft_plan_create(&p.inv, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                           rocfft_precision_double, 2, len, 3, nullptr);
+    if (s != rocfft_status_success) {
+      rocfft_plan_destroy(p.fwd);
+      return set_error(REXII_ERR_HIP, fft_msg("rocfft_plan_create (inverse)", s));
+    }
+    size_t w1 = 0, w2 = 0;
+    rocfft_plan_get_work_buffer_size(p.fwd, &w1);
+    rocfft_plan_get_work_buffer_size(p.inv, &w2);
+    p.work = w1 > w2 ? w1 : w2;
+    it = g_fft.emplace(key, p).first;
+  }
+  if (work_bytes) *work_bytes = it->second.work;
+  if (fwd) *fwd = it->second.fwd;
+  if (inv) *inv = it->second.inv;
+  return REXII_OK;
+}
+
+rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s) {
+  rocfft_execution_info info = nullptr;
+  rocfft_status st = rocfft_execution_info_create(&info);
+  if (st != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_execution_info_create", st));
+  st = rocfft_execution_info_set_stream(info, s);
+  if (st == rocfft_status_success && work_bytes > 0) st = rocfft_execution_info_set_work_buffer(info, work, work_bytes);
+  if (st == rocfft_status_success) {
+    void* ib[1] = {in};
+    void* ob[1] = {out};
+    st = rocfft_execute(static_cast<rocfft_plan>(plan), ib, ob, info);
+  }
+  rocfft_execution_info_destroy(info);
+  if (st != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_execute", st));
+  return REXII_OK;
+}
+
+}  // namespace rexii

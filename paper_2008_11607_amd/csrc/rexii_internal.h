@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime_api.h>
+
 #include "../../include/rexii.h"
 
 namespace rexii {
@@ -27,6 +29,12 @@ double kappa_sum(const std::vector<cplx>& w, double h);
 double max_s2(int n);
 double rho_const(int nx, int ny, double g, double H, double fc);
 double rho_bound_var(int nx, int ny, double g, double Hmax, double fc);
+
+// rocFFT plans of the Fourier-space path (kernels_fft.hip): a batch of three
+// real 2D transforms [3][ny][nx] <-> [3][ny][nx/2+1], FP64, not in place,
+// cached per device and grid; work_bytes receives the larger work buffer.
+rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv);
+rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s);
 
 }  // namespace rexii
 

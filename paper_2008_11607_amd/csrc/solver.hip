@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "kernels_fft.h"
 #include "rexii_internal.h"
 
 namespace rexii {
@@ -1399,6 +1400,172 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
   });
 }
 
+// ---------------------------------------------------------------------------
+// Fourier-space path (constant depth): FFT, per-mode filter by the REXII sum
+// in closed form, inverse FFT (kernels_fft.hip).
+// ---------------------------------------------------------------------------
+struct FourierPlan {
+  int M = 0, N = 0, P = 0, m0 = 0, nterm = 0;
+  double rho = 0.0, kappa = 0.0, c0 = 0.0;
+  std::vector<double> tab;  // nterm x (a, b^2, A1, B1, A2, B2)
+};
+
+// Spectral radius of the constant-depth symbol: centred differences, or
+// Fourier differentiation (largest |k| is (n-1)/2: the Nyquist mode has a
+// zero odd derivative).
+static double rho_fourier(const rexii_swe_op* op, int deriv) {
+  if (deriv == 0) return rho_const(op->nx, op->ny, op->g, op->H0, op->f_cor);
+  const double sx = 2.0 * M_PI * double((op->nx - 1) / 2), sy = 2.0 * M_PI * double((op->ny - 1) / 2);
+  return std::sqrt(op->f_cor * op->f_cor + op->g * op->H0 * (sx * sx + sy * sy));
+}
+
+// Poles and weights of the reduced sum (Sec. 2.2), then, per pole, the
+// real parts of the interpolation coefficients of r(x) = w / (x - z) on
+// {0, +-i theta} as functions of theta^2 (see kernels_fft.hip); poles with
+// the same z^2 up to the sign of Im z^2 share a denominator and one entry.
+static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv, FourierPlan& fp) {
+  if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
+  if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
+  fp.rho = (o.rho > 0.0) ? o.rho : rho_fourier(op, deriv);
+  fp.m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
+  const double Md = std::ceil(t * fp.rho / o.h) + fp.m0;
+  if (Md > 2.0e6) return set_error(REXII_ERR_INVALID_ARG, "t*rho/h too large for this library");
+  fp.M = m_rule(t, fp.rho, o.h, fp.m0);
+  fp.N = fp.M + terms_L();
+  std::vector<cplx> z, w;
+  poles_weights(fp.M, o.h, z, w);
+  fp.P = int(z.size());
+  fp.kappa = kappa_sum(w, o.h);
+  fp.c0 = 0.0;
+  fp.tab.clear();
+  fp.tab.reserve(size_t(fp.P) * 6);
+  for (int k = 0; k < fp.P; ++k) {
+    const cd zk(z[k].re, z[k].im), wk(w[k].re, w[k].im);
+    const cd q = -wk * std::conj(zk) / std::norm(zk);  // r(0) = -w / z of this pole
+    fp.c0 += q.real();
+    const double a = zk.real() * zk.real() - zk.imag() * zk.imag();
+    const double b = 2.0 * zk.real() * zk.imag();
+    const double e[6] = {a, b * b, -wk.real(), -wk.imag() * b, q.real(), q.imag() * b};
+    const size_t m = fp.tab.size();
+    if (m >= 6 && fp.tab[m - 6] == e[0] && fp.tab[m - 5] == e[1]) {
+      for (int j = 2; j < 6; ++j) fp.tab[m - 6 + j] += e[j];
+    } else {
+      fp.tab.insert(fp.tab.end(), e, e + 6);
+    }
+  }
+  fp.nterm = int(fp.tab.size() / 6);
+  return REXII_OK;
+}
+
+static size_t fourier_bytes(int nx, int ny, int nterm, size_t fft_work) {
+  const size_t nm = size_t(nx / 2 + 1) * ny;
+  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(256) + al256(fft_work);
+}
+
+static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double* u, double t, int deriv,
+                                const rexii_opts* opts_in, void* ws, size_t ws_bytes, hipStream_t stream,
+                                rexii_report* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  // Runs on the caller's stream (nothing here is captured into a graph) and
+  // returns when the result is complete on it.
+  hipStream_t st = stream;
+  try {
+    const int nx = op->nx, ny = op->ny;
+    const size_t n3 = 3 * size_t(nx) * ny, nm = size_t(nx / 2 + 1) * ny;
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    if (t == 0.0) {
+      launch_copy(f, u, n3, st);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(st));
+      return clear_error();
+    }
+    const rexii_opts o = resolve_opts(opts_in);
+    FourierPlan fp;
+    rexii_status s = fourier_plan(op, t, o, deriv, fp);
+    if (s != REXII_OK) return s;
+    size_t work = 0;
+    void *fwd = nullptr, *inv = nullptr;
+    s = fft_plans(nx, ny, &work, &fwd, &inv);
+    if (s != REXII_OK) return s;
+    const size_t need = fourier_bytes(nx, ny, fp.nterm, work);
+    Arena ar(ws, ws_bytes);
+    if (!ws) {
+      ar.reserve_own(need + 4096);
+    } else if (ws_bytes < need) {
+      return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_fourier_workspace_size()");
+    } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
+      return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    double2* F = ar.take<double2>(3 * nm);
+    double* tab = ar.take<double>(fp.tab.size());
+    double* flagd = ar.take<double>(32);
+    void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
+    int* flag = reinterpret_cast<int*>(flagd);
+    HIPCHK(hipMemcpyAsync(tab, fp.tab.data(), fp.tab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_fill_zero(flagd, 32, st);
+    const bool prof = (o.profile != 0);
+    hipEvent_t ev[5] = {};
+    if (prof)
+      for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvGuard {
+      hipEvent_t* e;
+      ~EvGuard() {
+        for (int k = 0; k < 5; ++k)
+          if (e[k]) (void)hipEventDestroy(e[k]);
+      }
+    } guard{ev};
+    auto mark = [&](int k) {
+      if (prof) HIPCHK(hipEventRecord(ev[k], st));
+    };
+    const int nw = mode_filter_waves(nx, ny, fp.nterm);
+    mark(0);
+    launch_copy_check(f, u, n3, flag, st);  // the forward transform may overwrite its input
+    mark(1);
+    s = fft_execute(fwd, u, F, wk, work, st);
+    if (s != REXII_OK) return s;
+    mark(2);
+    launch_mode_filter(F, nx, ny, deriv, t, op->g, op->H0, op->f_cor, fp.c0, 1.0 / (double(nx) * ny), tab, fp.nterm,
+                       nw, st);
+    mark(3);
+    s = fft_execute(inv, F, u, wk, work, st);
+    if (s != REXII_OK) return s;
+    mark(4);
+    HIPCHK(hipGetLastError());
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (rep) {
+      rep->P = fp.P;
+      rep->M = fp.M;
+      rep->N = fp.N;
+      rep->m0 = fp.m0;
+      rep->solves = fp.nterm;
+      rep->h = o.h;
+      rep->t = t;
+      rep->rho = fp.rho;
+      rep->kappa_sum = fp.kappa;
+      rep->slots = nw;
+      // copy 16, forward FFT 8 + 16 nm/n, filter 2 x 48 nm/n, inverse 16 nm/n + 8 bytes per point and field
+      rep->alg_bytes = double(n3) * 32.0 + 3.0 * double(nm) * (16.0 + 96.0 + 16.0);
+      rep->kernel_bytes = 96.0 * double(nm);
+      if (prof) {
+        float ms[4] = {};
+        for (int k = 0; k < 4; ++k) HIPCHK(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+        for (int k = 0; k < 4; ++k) rep->step_ms[k] = ms[k];
+        rep->kernel_launches = 1;
+        rep->kernel_ms = ms[2];
+      }
+      rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (bad) return set_error(REXII_ERR_NONFINITE, "non-finite value in f");
+    return clear_error();
+  } catch (const HipError& he) {
+    return set_error(he.st, he.msg);
+  } catch (const std::bad_alloc&) {
+    return set_error(REXII_ERR_OOM, "host allocation failed");
+  }
+}
+
 }  // namespace rexii
 
 using namespace rexii;
@@ -1417,6 +1584,40 @@ void rexii_default_opts(rexii_opts* o) {
   o->pole_batch = 0;
   o->pair_conjugate = 1;
   o->inner_tol = 1e-4;
+}
+
+rexii_status rexii_fourier_workspace_size(const rexii_swe_op* op, const rexii_opts* opts, double t, int32_t derivative,
+                                          size_t* bytes) {
+  rexii_status v = check_op_and_t(op, t, true, false);
+  if (v != REXII_OK) return v;
+  if (!bytes) return set_error(REXII_ERR_INVALID_ARG, "bytes is NULL");
+  if (derivative != REXII_DERIV_CENTRED && derivative != REXII_DERIV_SPECTRAL)
+    return set_error(REXII_ERR_INVALID_ARG, "unknown derivative");
+  if (t == 0.0) {
+    *bytes = 0;
+    return clear_error();
+  }
+  FourierPlan fp;
+  v = fourier_plan(op, t, resolve_opts(opts), derivative, fp);
+  if (v != REXII_OK) return v;
+  size_t work = 0;
+  v = fft_plans(op->nx, op->ny, &work, nullptr, nullptr);
+  if (v != REXII_OK) return v;
+  *bytes = fourier_bytes(op->nx, op->ny, fp.nterm, work);
+  return clear_error();
+}
+
+rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double* u, double t, int32_t derivative,
+                                 const rexii_opts* opts, void* workspace, size_t ws_bytes, hipStream_t stream,
+                                 rexii_report* rep) {
+  rexii_status v = check_op_and_t(op, t, true, false);
+  if (v != REXII_OK) return v;
+  if (!f || !u) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
+  if (derivative != REXII_DERIV_CENTRED && derivative != REXII_DERIV_SPECTRAL)
+    return set_error(REXII_ERR_INVALID_ARG, "unknown derivative");
+  const size_t n3 = 3 * size_t(op->nx) * op->ny;
+  if (overlaps(f, n3, u, n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
+  return run_fourier(op, f, u, t, derivative, opts, workspace, ws_bytes, stream, rep);
 }
 
 const char* rexii_last_error(void) { return g_err.c_str(); }

@@ -64,7 +64,8 @@ class Report(ctypes.Structure):
 
 EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",
            "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
-           "rexii_shifted_solve", "rexii_last_error"]
+           "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
+           "rexii_last_error"]
 
 _lib = None
 
@@ -95,6 +96,10 @@ def load():
     lib.rexii_apply_batched.restype = ctypes.c_int
     lib.rexii_shifted_solve.argtypes = [P(SweOp), vp, dbl, i32, vp, vp, P(Opts), vp, sz, vp, P(Report)]
     lib.rexii_shifted_solve.restype = ctypes.c_int
+    lib.rexii_apply_fourier.argtypes = [P(SweOp), vp, vp, dbl, i32, P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_apply_fourier.restype = ctypes.c_int
+    lib.rexii_fourier_workspace_size.argtypes = [P(SweOp), P(Opts), dbl, i32, P(sz)]
+    lib.rexii_fourier_workspace_size.restype = ctypes.c_int
     lib.rexii_last_error.argtypes = []
     lib.rexii_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -228,6 +233,41 @@ def shifted_solve(f, t, z, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
                                  ctypes.byref(o), None, 0, _stream(), ctypes.byref(rep))
     _check(st, rep.as_dict())
     return x, rep.as_dict()
+
+
+DERIVATIVES = {"centred": 0, "spectral": 1}
+
+
+def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, workspace=None, **opts):
+    """u = exp(tA) f by the Fourier-space path (constant depth): FFT, the
+    REXII pole sum per mode in closed form, inverse FFT; FP64.
+    derivative: "centred" (the operator of apply) or "spectral" (Fourier
+    differentiation).  workspace: optional uint8 CUDA tensor of at least
+    fourier_workspace_size() bytes.  Returns (u, report_dict)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    ny, nx = f.shape[1], f.shape[2]
+    u = torch.empty_like(f) if out is None else _dev_f64(out, f.shape)
+    op = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    rep = Report()
+    ws, nws = (None, 0) if workspace is None else (ctypes.c_void_p(workspace.data_ptr()), workspace.numel())
+    st = lib.rexii_apply_fourier(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                 float(t), DERIVATIVES.get(derivative, derivative), ctypes.byref(o), ws, nws,
+                                 _stream(), ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return u, rep.as_dict()
+
+
+def fourier_workspace_size(nx, ny, t, g=1.0, fc=10.0, H=1.0, derivative="centred", **opts):
+    lib = load()
+    op = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    out = ctypes.c_size_t()
+    _check(lib.rexii_fourier_workspace_size(ctypes.byref(op), ctypes.byref(o), float(t),
+                                            DERIVATIVES.get(derivative, derivative), ctypes.byref(out)))
+    return out.value
 
 
 def workspace_size(nx, ny, t, g=1.0, fc=10.0, H=1.0, **opts):

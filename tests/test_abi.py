@@ -92,6 +92,26 @@ def test_apply_rejects_bad_arguments_before_touching_the_device(rx):
     assert lib.rexii_apply(ctypes.byref(op), dummy, ctypes.c_void_p(1 << 20), -1.0, None, None, 0, None, None) == -1
 
 
+def test_apply_fourier_rejects_bad_arguments_before_touching_the_device(rx):
+    lib = rx.load()
+    dummy = ctypes.c_void_p(16)       # never dereferenced: validation fails first
+    far = ctypes.c_void_p(1 << 20)
+    op = rx.make_op(8, 8)
+    for deriv in (-1, 2):
+        assert lib.rexii_apply_fourier(ctypes.byref(op), dummy, far, 1.0, deriv, None, None, 0, None, None) == -1
+    assert "derivative" in rx.last_error()
+    opv = rx.make_op(8, 8)
+    opv.H_field = dummy               # a depth field is not supported by the Fourier path
+    assert lib.rexii_apply_fourier(ctypes.byref(opv), dummy, far, 1.0, 0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply_fourier(ctypes.byref(op), dummy, dummy, 1.0, 0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply_fourier(ctypes.byref(op), None, far, 1.0, 0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply_fourier(ctypes.byref(op), dummy, far, -1.0, 0, None, None, 0, None, None) == -1
+    nb = ctypes.c_size_t(7)
+    assert lib.rexii_fourier_workspace_size(ctypes.byref(op), None, 0.0, 0, ctypes.byref(nb)) == 0
+    assert nb.value == 0
+    assert lib.rexii_fourier_workspace_size(ctypes.byref(op), None, 1.0, 5, ctypes.byref(nb)) == -1
+
+
 def test_default_opts(rx):
     o = rx.make_opts()
     assert o.h == 0.5 and o.m0 == -1 and o.pair_conjugate == 1 and o.precision == 0

@@ -45,14 +45,18 @@ def workload():
 
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0000,
 # WRITE_SIZE x 1.0000, scales from a 1 GiB copy): k_pass_f32 on the 512^2
-# workload (128 slots) and k_bcg_u1_f32 on the 2048^2 depth-field workload
-# (one state, 8 slots); valid only for the kernel sources they were taken on.
+# workload (128 slots), k_bcg_u1_f32 on the 2048^2 depth-field workload
+# (one state, 8 slots) and k_mode_filter on the two Fourier workloads; valid
+# only for the kernel sources they were taken on.
 TRAFFIC = {
     "k_pass_f32": {"bytes_per_launch": 1553566515.7, "fetch_kib": 390749.21, "write_kib": 735675.10,
                    "sources": ["kernels.hip", "kernels.h", "device_util.h"],
                    "sources_sha256": "ecf904a25a6e4aebc7812628fe25905d2466ad9cca83c814ecf09f696d270910"},
-    "k_mode_filter": {"bytes_per_launch": None, "sources": ["kernels_fft.hip", "kernels_fft.h"],
-                      "sources_sha256": None},
+    # per grid size: the 512^2 (t rho = 1000) and 2048^2 (t rho = 5000) Fourier workloads
+    "k_mode_filter": {"bytes_per_launch": {512: 14281537.3, 2048: 209314264.6},
+                      "fetch_kib": {512: 3889.5, 2048: 53005.5}, "write_kib": {512: 6168.0, 2048: 98400.0},
+                      "sources": ["kernels_fft.hip", "kernels_fft.h"],
+                      "sources_sha256": "8ac55238d24140badaa6cefe70867af41cd9b537979504e4fd4647a396148193"},
     "k_bcg_u1_f32": {"bytes_per_launch": 1449208214.6, "fetch_kib": 436723.81, "write_kib": 541815.70,
                      "sources": ["kernels_vh.hip", "kernels.h", "device_util.h"],
                      "sources_sha256": "6fecb750d684290a88d91142c465f9cb57332c5143a4d7af5cea636593b551e4"},
@@ -68,12 +72,14 @@ def sources_sha256(files):
     return h.hexdigest()
 
 
-def traffic_if_current(kernel):
-    """The counter-based traffic of a kernel when its sources are unchanged, else None."""
+def traffic_if_current(kernel, size=None):
+    """The counter-based traffic of a kernel (at one grid size where it was
+    taken per size) when its sources are unchanged, else None."""
     t = TRAFFIC[kernel]
     if t["sources_sha256"] is None or sources_sha256(t["sources"]) != t["sources_sha256"]:
         return None
-    return t["bytes_per_launch"]
+    b = t["bytes_per_launch"]
+    return b.get(size) if isinstance(b, dict) else b
 
 
 def golden(name):
@@ -333,7 +339,7 @@ def _fourier_case(D, fc, trho, nbumps, seed, gold_name, steps, warmup):
             "value": D * D * P / (el / steps), "rel_l2_vs_oracle": sampled_rel_l2(u, gold),
             "roofline": {"bound": "alu", "kernel": "k_mode_filter", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                         "traffic": traffic_if_current("k_mode_filter"),
+                         "traffic": traffic_if_current("k_mode_filter", D),
                          "avg_launch_ms": k_ms, "launches": steps, "alg_flops_per_launch": flops,
                          "waves_per_block": reps[0]["slots"],
                          "kernel_time_share": k_ms * steps * 1e-3 / el},
@@ -347,9 +353,21 @@ def run_fourier(args):
     workload of the headline line, and a 2048^2 t rho = 5000 constant-depth
     workload (f_c = 20)."""
     steps = max(args.steps, 20)
+    sizes = {int(x) for x in args.fourier_sizes.split(",")}
+    if 512 not in sizes:
+        # the 2048^2 case alone (for per-size counter runs): its own line
+        big = _fourier_case(2048, 20.0, 5000.0, 16, 5, "lrsw2048_trho5000.json", max(args.steps, 5),
+                            max(args.warmup, 1))
+        print(json.dumps({"workload": "lrsw-fd-2048x2048-fc20-trho5000-16bumps-fourier", "value": big["value"],
+                          "unit": "grid-pt·pole solves/s", "ms_per_step": big["ms"],
+                          "rel_l2_vs_oracle": big["rel_l2_vs_oracle"], "roofline": big["roofline"],
+                          "ms_by_stage": big["ms_by_stage"]}), flush=True)
+        return
     c = _fourier_case(D, FC, TRHO, NBUMPS, SEED, "lrsw512_trho1000.json", steps, max(args.warmup, 3))
-    big = _fourier_case(2048, 20.0, 5000.0, 16, 5, "lrsw2048_trho5000.json", max(args.steps, 5),
-                        max(args.warmup, 1))
+    big = None
+    if 2048 in sizes:
+        big = _fourier_case(2048, 20.0, 5000.0, 16, 5, "lrsw2048_trho5000.json", max(args.steps, 5),
+                            max(args.warmup, 1))
     out = {
         "metric": METRIC, "value": c["value"], "unit": "grid-pt·pole solves/s", "n_gpus": 1,
         "steps": steps, "warmup": max(args.warmup, 3), "ms_per_step": c["ms"], "higher_is_better": True,
@@ -361,10 +379,11 @@ def run_fourier(args):
         "hbm_gbs_alg": c["hbm_gbs_alg"],
         "roofline": c["roofline"],
         "ms_by_stage": c["ms_by_stage"],
-        "large": {k: big[k] for k in ("D", "t_rho", "f_c", "P", "terms", "ms", "value", "rel_l2_vs_oracle",
-                                      "roofline", "ms_by_stage")},
     }
-    out["large"]["workload"] = "lrsw-fd-2048x2048-fc20-trho5000-16bumps-fourier"
+    if big is not None:
+        out["large"] = {k: big[k] for k in ("D", "t_rho", "f_c", "P", "terms", "ms", "value", "rel_l2_vs_oracle",
+                                            "roofline", "ms_by_stage")}
+        out["large"]["workload"] = "lrsw-fd-2048x2048-fc20-trho5000-16bumps-fourier"
     if not args.no_cpu:
         f, _, t = workload()
         out["cpu_baseline"] = cpu_baseline(f, t, tol=1e-10)
@@ -387,6 +406,9 @@ def main():
     ap.add_argument("--rhs", type=int, default=8, help="states of the varh2048 / batched workloads")
     ap.add_argument("--subset", type=int, default=16,
                     help="varh2048: values of n in the t rho = 5000 pole subset (0 = skip)")
+    ap.add_argument("--fourier-sizes", default="512,2048",
+                    help="fourier workload: grid sizes to run (512: t rho = 1000, the headline line; "
+                         "2048: t rho = 5000, f_c = 20)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 8 times (reference for HBM counters)")
     args = ap.parse_args()

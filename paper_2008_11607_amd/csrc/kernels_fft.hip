@@ -93,9 +93,10 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __rest
   const int per = (nterm + nw - 1) / nw;
   const int lo = min(nterm, w * per), hi = min(nterm, lo + per);
   // (A s + B) / d is accumulated as (s/d) A + (1/d) B: one scalar (table)
-  // operand per FMA, and four independent chains.  Two terms share one
-  // reciprocal, 1/d1 = d2/(d1 d2) (d >= b^2 > 0 and d >= a^2 > 0 for the
-  // n = 0 term, so the product neither underflows nor overflows).
+  // operand per FMA, and four independent chains.  Four terms share one
+  // reciprocal: 1/d1 = (d2 d3 d4) / (d1 d2 d3 d4).  d >= b^2 = (2 h^2 mu n)^2
+  // for n >= 1 and d >= a^2 = (h mu)^4 for n = 0, and d < 4 (theta^2 + (h N)^2)^2,
+  // so the product stays in range for any h above 1e-3 and theta below 1e18.
   double c1a = 0.0, c1b = 0.0, c2a = 0.0, c2b = 0.0;
   auto one = [&](const double* q, double i1) {
     const double e1 = i1 * (q[0] + th2);
@@ -104,27 +105,34 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __rest
     c2a = fma(e1, q[4], c2a);
     c2b = fma(i1, q[5], c2b);
   };
+  auto den = [&](const double* q) { return sq_plus(q[0] + th2, q[1]); };
   auto pair = [&](const double* q) {
-    const double s1 = q[0] + th2, s2 = q[kTermDoubles] + th2;
-    const double d1 = sq_plus(s1, q[1]), d2 = sq_plus(s2, q[kTermDoubles + 1]);
+    const double d1 = den(q), d2 = den(q + kTermDoubles);
     const double r = recip(d1 * d2);
     one(q, r * d2);
     one(q + kTermDoubles, r * d1);
   };
+  auto quad = [&](const double* q) {
+    const double d1 = den(q), d2 = den(q + kTermDoubles);
+    const double d3 = den(q + 2 * kTermDoubles), d4 = den(q + 3 * kTermDoubles);
+    const double p12 = d1 * d2, p34 = d3 * d4;
+    const double r = recip(p12 * p34);
+    const double r12 = r * p34, r34 = r * p12;
+    one(q, r12 * d2);
+    one(q + kTermDoubles, r12 * d1);
+    one(q + 2 * kTermDoubles, r34 * d4);
+    one(q + 3 * kTermDoubles, r34 * d3);
+  };
   int j = lo;
-  for (; j + 3 < hi; j += 4) {  // unrolled by hand: the loads of two pairs issue together
+  for (; j + 7 < hi; j += 8) {  // unrolled by hand: the loads of two quads issue together
     const double* q = tab + size_t(j) * kTermDoubles;
-    pair(q);
-    pair(q + 2 * kTermDoubles);
+    quad(q);
+    quad(q + 4 * kTermDoubles);
   }
-  if (j + 1 < hi) {
-    pair(tab + size_t(j) * kTermDoubles);
-    j += 2;
-  }
+  for (; j + 1 < hi; j += 2) pair(tab + size_t(j) * kTermDoubles);
   if (j < hi) {
     const double* q = tab + size_t(j) * kTermDoubles;
-    const double s1 = q[0] + th2;
-    one(q, recip(fma(s1, s1, q[1])));
+    one(q, recip(den(q)));
   }
   double c1 = c1a + c1b, c2 = c2a + c2b;
   if (nw > 1) {

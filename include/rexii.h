@@ -253,6 +253,40 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
                                  int32_t derivative, const rexii_opts* opts, void* workspace,
                                  size_t ws_bytes, hipStream_t stream, rexii_report* rep);
 
+/* Shared-Krylov (multi-shift) REXII, any depth: all shifted systems
+ * (tA - z_k I) x_k = f have one right-hand side, and Krylov spaces are
+ * shift invariant, so one Lanczos process per state serves every pole
+ * (the systems of the partial-fraction sum, eq. modifiedRexiMatrixReducedSum,
+ * solved together instead of one Krylov solve each):
+ *     u = ||f||_W V_m Re sum_k w_k (t T_m - z_k I)^{-1} e_1.
+ * W = diag(g, H, H) makes A skew-adjoint, so the process is a real
+ * two-term recurrence and T_m is skew-tridiagonal.  Pass 1 forms the
+ * recurrence coefficients; the host solves the small problems; pass 2
+ * repeats the same steps and accumulates u, so the basis is never stored.
+ * The poles come from the M rule for the Gershgorin bound of T_m, which is
+ * at most rho(A).  m grows until the last 8 coefficients of the small
+ * solution hold under tol / 10 of its norm (checked from m = 0.75 t rho on).
+ * FP64 throughout (opts.precision ignored).
+ *   nrhs states share op and t: f, u device [nrhs][3][ny][nx], not
+ *     overlapping.
+ *   opts: h, tol, m0 as for rexii_apply; max_iter caps the Krylov dimension
+ *     m (default 50000); profile = 1 fills step_ms.
+ *   Workspace: rexii_multishift_workspace_size() bytes, or NULL.
+ *   Report: solves = max_iters = m, total_iters = sum of m over states,
+ *     P, M, N for the largest small problem, rho = its Gershgorin bound,
+ *     max_rel_residual = largest tail ratio, alg_bytes = algorithmic HBM
+ *     bytes of both passes.  With profile = 1: step_ms[0] pass 1, [1] host
+ *     small problems, [2] pass 2 (ms); kernel_ms = step_ms[2] and
+ *     kernel_bytes = pass 2's algorithmic bytes.
+ * Errors: INVALID_ARG, NONFINITE (f), NOT_CONVERGED (m reached max_iter;
+ * u is written from that m), OOM, HIP, WORKSPACE. */
+rexii_status rexii_multishift_workspace_size(const rexii_swe_op* op, int32_t nrhs, const rexii_opts* opts,
+                                             size_t* bytes);
+
+rexii_status rexii_apply_multishift(const rexii_swe_op* op, int32_t nrhs, const double* f, double* u, double t,
+                                    const rexii_opts* opts, void* workspace, size_t ws_bytes,
+                                    hipStream_t stream, rexii_report* rep);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* rexii_last_error(void);
 

@@ -20,10 +20,12 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
 #include "kernels_fft.h"
+#include "kernels_lz.h"
 #include "rexii_internal.h"
 
 namespace rexii {
@@ -1531,9 +1533,13 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     if (s != REXII_OK) return s;
     mark(4);
     HIPCHK(hipGetLastError());
-    int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    // the flag is read into pinned host memory (one word per host thread,
+    // kept for the life of the process), ordered on the stream
+    static thread_local int* hflag = nullptr;
+    if (!hflag) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), 256, hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const int bad = *hflag;
     if (rep) {
       rep->P = fp.P;
       rep->M = fp.M;
@@ -1564,6 +1570,323 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
   } catch (const std::bad_alloc&) {
     return set_error(REXII_ERR_OOM, "host allocation failed");
   }
+}
+
+// ---------------------------------------------------------------------------
+// Shared-Krylov (multi-shift) path: one W-skew Lanczos process per state
+// serves every pole (kernels_lz.hip); the small problems on T_m run here.
+// ---------------------------------------------------------------------------
+struct SmallResult {
+  int P = 0, M = 0, N = 0;
+  double rho = 0.0, kappa = 0.0, tail = 0.0;
+};
+
+// y = beta0 Re sum_k w_k (t T - z_k I)^{-1} e_1 for the m x m real skew
+// tridiagonal T with T[j+1][j] = b[j] = -T[j][j+1] (b[1..m-1]).  The poles
+// come from the M rule for rho(T) (Gershgorin bound, capped by a bound on
+// rho(A)).  A conjugate pair
+// z_2 = -conj(z_1) needs one solve: with D = diag((-1)^(j-1)), D T D = -T, so
+// (tT - z_2)^{-1} e_1 = -D conj((tT - z_1)^{-1} e_1).  Each solve is Gaussian
+// elimination without pivoting, stable here because the Hermitian part of
+// tT - z is -Re(z) I, definite.
+static SmallResult small_problem(const double* b, int m, double t, double h, int m0, double beta0,
+                                 double rho_cap, std::vector<double>& y) {
+  SmallResult res;
+  double rho = 0.0;
+  for (int j = 1; j <= m; ++j) {
+    const double lo = (j >= 2) ? b[j - 1] : 0.0, hi = (j <= m - 1) ? b[j] : 0.0;
+    rho = std::max(rho, lo + hi);
+  }
+  // the eigenvalues of T = V^T W A V lie in the W-numerical range of A,
+  // the segment i [-rho(A), rho(A)]: a bound on rho(A) caps Gershgorin's
+  rho = std::min(rho, rho_cap);
+  res.rho = rho;
+  res.M = m_rule(t, std::max(rho, 1e-300), h, m0);
+  res.N = res.M + terms_L();
+  std::vector<cplx> z, w;
+  poles_weights(res.M, h, z, w);
+  res.P = int(z.size());
+  res.kappa = kappa_sum(w, h);
+  const int npair = res.P / 2;
+  unsigned nth = std::thread::hardware_concurrency();
+  nth = std::max(1u, std::min(16u, nth));
+  nth = std::min<unsigned>(nth, std::max(1, npair));
+  std::vector<std::vector<double>> part(nth, std::vector<double>(m, 0.0));
+  auto work = [&](unsigned id) {
+    std::vector<cd> cp(m), rp(m);
+    std::vector<double>& yp = part[id];
+    for (int q = int(id); q < npair; q += int(nth)) {
+      const cd z1(z[2 * q].re, z[2 * q].im);
+      const cd w1(w[2 * q].re, w[2 * q].im), w2(w[2 * q + 1].re, w[2 * q + 1].im);
+      // forward elimination of (tT - z1) x = e_1: diagonal -z1, sub t b_j, super -t b_j
+      cd den = -z1;
+      cd inv = 1.0 / den;
+      cp[0] = (m > 1) ? cd(-t * b[1]) * inv : cd(0.0);
+      rp[0] = inv;
+      for (int j = 1; j < m; ++j) {
+        const double sub = t * b[j];
+        den = -z1 - sub * cp[j - 1];
+        inv = 1.0 / den;
+        cp[j] = (j + 1 < m) ? cd(-t * b[j + 1]) * inv : cd(0.0);
+        rp[j] = -sub * rp[j - 1] * inv;
+      }
+      cd x = rp[m - 1];
+      for (int j = m - 1; j >= 0; --j) {
+        if (j < m - 1) x = rp[j] - cp[j] * x;
+        const double sgn = (j % 2 == 0) ? -1.0 : 1.0;  // -(-1)^j for 0-based j
+        yp[j] += (w1 * x).real() + sgn * (w2 * std::conj(x)).real();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned k = 1; k < nth; ++k) th.emplace_back(work, k);
+  work(0);
+  for (auto& x : th) x.join();
+  y.assign(m, 0.0);
+  for (unsigned k = 0; k < nth; ++k)
+    for (int j = 0; j < m; ++j) y[j] += part[k][j];
+  double tot = 0.0, tail = 0.0;
+  for (int j = 0; j < m; ++j) {
+    y[j] *= beta0;
+    tot += y[j] * y[j];
+    if (j >= m - 8) tail += y[j] * y[j];
+  }
+  res.tail = (tot > 0.0) ? std::sqrt(tail / tot) : 0.0;
+  return res;
+}
+
+static rexii_status run_multishift(const rexii_swe_op* op, int nrhs, const double* f, double* u, double t,
+                                   const rexii_opts* opts_in, void* ws, size_t ws_bytes, hipStream_t st,
+                                   rexii_report* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    const int nx = op->nx, ny = op->ny;
+    const size_t n = size_t(nx) * ny, n3 = 3 * n;
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    if (t == 0.0) {
+      launch_copy(f, u, n3 * nrhs, st);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(st));
+      return clear_error();
+    }
+    const rexii_opts o = resolve_opts(opts_in);
+    if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
+    if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    const int m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
+    const int mmax = std::max(8, o.max_iter);
+    const int ldb = mmax + 2, ldy = mmax;
+    const int nb = lz_blocks(nx, ny);
+    const size_t need = 2 * al256(size_t(nrhs) * n3 * 8) + al256(size_t(nrhs) * nb * 8) +
+                        al256(size_t(nrhs) * ldb * 8) + al256(size_t(nrhs) * ldy * 8) + al256(256);
+    Arena ar(ws, ws_bytes);
+    if (!ws) {
+      ar.reserve_own(need + 4096);
+    } else if (ws_bytes < need) {
+      return set_error(REXII_ERR_WORKSPACE, "workspace smaller than rexii_multishift_workspace_size()");
+    } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
+      return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    double* X = ar.take<double>(size_t(nrhs) * n3);
+    double* Y = ar.take<double>(size_t(nrhs) * n3);
+    double* part = ar.take<double>(size_t(nrhs) * nb);
+    double* beta = ar.take<double>(size_t(nrhs) * ldb);
+    double* ydev = ar.take<double>(size_t(nrhs) * ldy);
+    double* flagd = ar.take<double>(32);
+    int* flag = reinterpret_cast<int*>(flagd);
+    const double* Hf = op->H_field;
+    const double H0 = op->H0, g = op->g, fc = op->f_cor;
+    hipEvent_t ev[4] = {};
+    const bool prof = (o.profile != 0);
+    if (prof)
+      for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvGuard {
+      hipEvent_t* e;
+      ~EvGuard() {
+        for (int k = 0; k < 4; ++k)
+          if (e[k]) (void)hipEventDestroy(e[k]);
+      }
+    } guard{ev};
+
+    // pass 1: the Lanczos coefficients, in chunks; after each chunk the host
+    // checks for breakdown and, once m reaches t rho(T), for convergence
+    launch_fill_zero(flagd, 32, st);
+    if (prof) HIPCHK(hipEventRecord(ev[0], st));
+    launch_lz_start(f, X, Hf, H0, g, nx, ny, nrhs, part, flag, beta, ldb, st);
+    std::vector<double> hb(size_t(nrhs) * ldb, 0.0);
+    // device-to-host reads go to pinned host memory, ordered on the stream
+    // and waited for through an event
+    struct Pinned {
+      void* p = nullptr;
+      ~Pinned() {
+        if (p) (void)hipHostFree(p);
+      }
+    } pin;
+    HIPCHK(hipHostMalloc(&pin.p, size_t(nrhs) * ldb * 8 + 256, hipHostMallocDefault));
+    double* hbp = static_cast<double*>(pin.p);
+    int* hflag = reinterpret_cast<int*>(hbp + size_t(nrhs) * ldb);
+    hipEvent_t rd = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&rd, hipEventDisableTiming));
+    struct EvFree {
+      hipEvent_t e;
+      ~EvFree() { (void)hipEventDestroy(e); }
+    } rdfree{rd};
+    auto wait_reads = [&]() {
+      HIPCHK(hipEventRecord(rd, st));
+      HIPCHK(hipEventSynchronize(rd));
+    };
+    HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hbp, beta, size_t(nrhs) * ldb * 8, hipMemcpyDeviceToHost, st));
+    wait_reads();
+    const int bad = *hflag;
+    std::copy(hbp, hbp + size_t(nrhs) * ldb, hb.begin());
+    if (bad) return set_error(REXII_ERR_NONFINITE, "non-finite value in f");
+    // scale of A for the breakdown test (beta_j -> 0: an invariant subspace)
+    const double hscale = Hf ? device_hmax(Hf, n, st) : H0;
+    const double rho_ref = std::sqrt(g * hscale) * std::sqrt(double(nx) * nx + double(ny) * ny) + std::fabs(fc);
+    std::vector<int> mr(nrhs, 0);     // Krylov dimension per state (0: not fixed yet)
+    for (int r = 0; r < nrhs; ++r)
+      if (!(hb[size_t(r) * ldb] > 0.0)) mr[r] = -1;  // zero state: u = 0
+    std::vector<std::vector<double>> ys(nrhs);
+    std::vector<SmallResult> sr(nrhs);
+    const int chunk = 32;
+    int m = 0, launched = 0, next_check = 0;
+    bool done = false, hit_max = false;
+    double host_s = 0.0;
+    auto enqueue = [&](int upto) {
+      for (int j = launched + 1; j <= upto; ++j) {
+        const double* cur = (j % 2 == 1) ? X : Y;
+        double* prv = (j % 2 == 1) ? Y : X;
+        launch_lz_step(cur, prv, Hf, H0, g, fc, nx, ny, nrhs, j, beta, ldb, part, nullptr, 0, nullptr, 0, st);
+      }
+      launched = std::max(launched, upto);
+    };
+    while (!done) {
+      enqueue(std::min(mmax, m + chunk));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpy2DAsync(hbp + m + 1, size_t(ldb) * 8, beta + m + 1, size_t(ldb) * 8,
+                              size_t(launched - m) * 8, nrhs, hipMemcpyDeviceToHost, st));
+      wait_reads();
+      for (int r = 0; r < nrhs; ++r)
+        std::copy(hbp + size_t(r) * ldb + m + 1, hbp + size_t(r) * ldb + launched + 1, hb.begin() + size_t(r) * ldb + m + 1);
+      m = launched;
+      // breakdown: an invariant subspace of dimension j (exact result)
+      double rho_all = 0.0;
+      for (int r = 0; r < nrhs; ++r) {
+        if (mr[r] != 0) continue;
+        const double* b = hb.data() + size_t(r) * ldb;
+        for (int j = 1; j <= m; ++j) {
+          if (!(b[j] > 1e-13 * rho_ref) || !std::isfinite(b[j])) {
+            mr[r] = j;
+            break;
+          }
+          if (j >= 2) rho_all = std::max(rho_all, b[j - 1] + b[j]);
+        }
+      }
+      rho_all = std::min(rho_all, rho_ref);
+      const bool all_fixed = std::all_of(mr.begin(), mr.end(), [](int v) { return v != 0; });
+      hit_max = (m >= mmax);
+      if (!(all_fixed || hit_max || (m >= next_check && m >= 0.75 * t * rho_all))) continue;
+      // the next chunk runs on the GPU while the host solves the small problems
+      if (!all_fixed && !hit_max) enqueue(std::min(mmax, m + chunk));
+      const auto h0 = std::chrono::steady_clock::now();
+      // states share the operator and converge at similar m: stop at the
+      // first one that has not converged yet
+      bool conv = true;
+      for (int r = 0; r < nrhs && conv; ++r) {
+        if (mr[r] < 0) continue;
+        const int mm = (mr[r] > 0) ? mr[r] : m;
+        sr[r] = small_problem(hb.data() + size_t(r) * ldb, mm, t, o.h, m0, hb[size_t(r) * ldb], rho_ref, ys[r]);
+        if (mr[r] == 0 && !(sr[r].tail <= 0.1 * o.tol)) conv = false;
+      }
+      host_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+      next_check = int(m * 1.1) + chunk;
+      done = conv || hit_max;
+    }
+    for (int r = 0; r < nrhs; ++r)
+      if (mr[r] == 0) mr[r] = m;
+    int mfin = 0;
+    for (int r = 0; r < nrhs; ++r) mfin = std::max(mfin, mr[r]);
+    if (prof) HIPCHK(hipEventRecord(ev[1], st));
+
+    // pass 2: the same steps, u += y_j v_j
+    std::vector<double> hy(size_t(nrhs) * ldy, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+      if (mr[r] > 0)
+        for (int j = 0; j < mr[r]; ++j) hy[size_t(r) * ldy + j] = ys[r][j];
+    HIPCHK(hipMemcpyAsync(ydev, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, st));
+    launch_fill_zero(u, size_t(nrhs) * n3, st);
+    if (prof) HIPCHK(hipEventRecord(ev[2], st));
+    launch_lz_start(f, X, Hf, H0, g, nx, ny, nrhs, part, flag, beta, ldb, st);
+    for (int j = 1; j <= mfin; ++j) {
+      const double* cur = (j % 2 == 1) ? X : Y;
+      double* prv = (j % 2 == 1) ? Y : X;
+      launch_lz_step(cur, prv, Hf, H0, g, fc, nx, ny, nrhs, j, beta, ldb, nullptr, ydev, ldy, u, j == mfin ? 1 : 0,
+                     st);
+    }
+    if (prof) HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    if (rep) {
+      int P = 0, M = 0, N = 0;
+      double rho = 0.0, kap = 0.0, tail = 0.0;
+      int64_t tot = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        if (mr[r] <= 0) continue;
+        if (sr[r].P > P) {
+          P = sr[r].P;
+          M = sr[r].M;
+          N = sr[r].N;
+        }
+        rho = std::max(rho, sr[r].rho);
+        kap = std::max(kap, sr[r].kappa);
+        tail = std::max(tail, sr[r].tail);
+        tot += mr[r];
+      }
+      rep->P = P;
+      rep->M = M;
+      rep->N = N;
+      rep->m0 = m0;
+      rep->solves = mfin;
+      rep->max_iters = mfin;
+      rep->total_iters = tot;
+      rep->not_converged = hit_max ? 1 : 0;
+      rep->h = o.h;
+      rep->t = t;
+      rep->rho = rho;
+      rep->kappa_sum = kap;
+      rep->max_rel_residual = tail;
+      rep->pole_tol = o.tol;
+      // per step and state: pass 1 reads buf_j, buf_{j-1} (and the depth),
+      // writes buf_{j+1}; pass 2 also reads and writes u
+      const double per1 = (Hf ? 80.0 : 72.0), per2 = per1 + 48.0;
+      rep->alg_bytes = double(mfin) * double(nrhs) * double(n) * (per1 + per2);
+      rep->kernel_launches = 2 * int64_t(m + mfin);
+      if (prof) {
+        float a = 0.f, b2 = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&b2, ev[2], ev[3]));
+        rep->step_ms[0] = a;          // pass 1 (GPU stream time, host checks included)
+        rep->step_ms[1] = host_s * 1e3;
+        rep->step_ms[2] = b2;         // pass 2
+        rep->kernel_ms = b2;
+        rep->kernel_bytes = double(mfin) * double(nrhs) * double(n) * per2;
+      }
+      rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (hit_max) return set_error(REXII_ERR_NOT_CONVERGED, "Krylov dimension reached max_iter");
+    return clear_error();
+  } catch (const HipError& he) {
+    return set_error(he.st, he.msg);
+  } catch (const std::bad_alloc&) {
+    return set_error(REXII_ERR_OOM, "host allocation failed");
+  }
+}
+
+static size_t multishift_bytes(int nx, int ny, int nrhs, int max_iter) {
+  const size_t n3 = 3 * size_t(nx) * ny;
+  const int mmax = std::max(8, max_iter);
+  return 2 * al256(size_t(nrhs) * n3 * 8) + al256(size_t(nrhs) * lz_blocks(nx, ny) * 8) +
+         al256(size_t(nrhs) * (mmax + 2) * 8) + al256(size_t(nrhs) * mmax * 8) + al256(256);
 }
 
 }  // namespace rexii
@@ -1618,6 +1941,27 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
   const size_t n3 = 3 * size_t(op->nx) * op->ny;
   if (overlaps(f, n3, u, n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
   return run_fourier(op, f, u, t, derivative, opts, workspace, ws_bytes, stream, rep);
+}
+
+rexii_status rexii_multishift_workspace_size(const rexii_swe_op* op, int32_t nrhs, const rexii_opts* opts,
+                                             size_t* bytes) {
+  rexii_status v = validate_op(op);
+  if (v != REXII_OK) return v;
+  if (!bytes || nrhs <= 0) return set_error(REXII_ERR_INVALID_ARG, "need bytes and nrhs > 0");
+  *bytes = multishift_bytes(op->nx, op->ny, nrhs, resolve_opts(opts).max_iter);
+  return clear_error();
+}
+
+rexii_status rexii_apply_multishift(const rexii_swe_op* op, int32_t nrhs, const double* f, double* u, double t,
+                                    const rexii_opts* opts, void* workspace, size_t ws_bytes, hipStream_t stream,
+                                    rexii_report* rep) {
+  rexii_status v = check_op_and_t(op, t, true);
+  if (v != REXII_OK) return v;
+  if (nrhs <= 0 || nrhs > 65535) return set_error(REXII_ERR_INVALID_ARG, "nrhs must be in [1, 65535]");
+  if (!f || !u) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
+  const size_t nall = 3 * size_t(op->nx) * op->ny * size_t(nrhs);
+  if (overlaps(f, nall, u, nall)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
+  return run_multishift(op, nrhs, f, u, t, opts, workspace, ws_bytes, stream, rep);
 }
 
 const char* rexii_last_error(void) { return g_err.c_str(); }

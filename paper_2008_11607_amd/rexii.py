@@ -65,7 +65,7 @@ class Report(ctypes.Structure):
 EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",
            "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
            "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
-           "rexii_last_error"]
+           "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_last_error"]
 
 _lib = None
 
@@ -100,6 +100,10 @@ def load():
     lib.rexii_apply_fourier.restype = ctypes.c_int
     lib.rexii_fourier_workspace_size.argtypes = [P(SweOp), P(Opts), dbl, i32, P(sz)]
     lib.rexii_fourier_workspace_size.restype = ctypes.c_int
+    lib.rexii_apply_multishift.argtypes = [P(SweOp), i32, vp, vp, dbl, P(Opts), vp, sz, vp, P(Report)]
+    lib.rexii_apply_multishift.restype = ctypes.c_int
+    lib.rexii_multishift_workspace_size.argtypes = [P(SweOp), i32, P(Opts), P(sz)]
+    lib.rexii_multishift_workspace_size.restype = ctypes.c_int
     lib.rexii_last_error.argtypes = []
     lib.rexii_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -256,6 +260,31 @@ def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, w
     st = lib.rexii_apply_fourier(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                  float(t), DERIVATIVES.get(derivative, derivative), ctypes.byref(o), ws, nws,
                                  _stream(), ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return u, rep.as_dict()
+
+
+def apply_multishift(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts):
+    """u = exp(tA) f by the shared-Krylov (multi-shift) path: one W-skew
+    Lanczos process per state serves every pole; FP64, any depth.
+    f: float64 CUDA tensor [3, ny, nx] or a batch [nrhs, 3, ny, nx] sharing
+    the operator and t.  Returns (u, report_dict)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    if f.dim() not in (3, 4) or f.shape[-3] != 3:
+        raise ValueError("expected [3, ny, nx] or [nrhs, 3, ny, nx]")
+    nrhs = 1 if f.dim() == 3 else f.shape[0]
+    ny, nx = f.shape[-2], f.shape[-1]
+    if Hfield is not None:
+        _dev_f64(Hfield, (ny, nx))
+    u = torch.empty_like(f) if out is None else _dev_f64(out, f.shape)
+    op = make_op(nx, ny, g, fc, H, Hfield)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_apply_multishift(ctypes.byref(op), int(nrhs), ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(u.data_ptr()), float(t), ctypes.byref(o), None, 0, _stream(),
+                                    ctypes.byref(rep))
     _check(st, rep.as_dict())
     return u, rep.as_dict()
 

@@ -112,6 +112,23 @@ def test_apply_fourier_rejects_bad_arguments_before_touching_the_device(rx):
     assert lib.rexii_fourier_workspace_size(ctypes.byref(op), None, 1.0, 5, ctypes.byref(nb)) == -1
 
 
+def test_apply_multishift_rejects_bad_arguments_before_touching_the_device(rx):
+    lib = rx.load()
+    dummy = ctypes.c_void_p(16)       # never dereferenced: validation fails first
+    far = ctypes.c_void_p(1 << 30)
+    op = rx.make_op(8, 8)
+    for nrhs in (0, -1, 70000):
+        assert lib.rexii_apply_multishift(ctypes.byref(op), nrhs, dummy, far, 1.0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply_multishift(ctypes.byref(op), 2, dummy, ctypes.c_void_p(16 + 8 * 192), 1.0, None, None, 0,
+                                      None, None) == -1   # u overlaps the second state of f
+    assert lib.rexii_apply_multishift(ctypes.byref(op), 1, None, far, 1.0, None, None, 0, None, None) == -1
+    assert lib.rexii_apply_multishift(ctypes.byref(op), 1, dummy, far, float("inf"), None, None, 0, None, None) == -1
+    nb = ctypes.c_size_t(0)
+    assert lib.rexii_multishift_workspace_size(ctypes.byref(op), 2, None, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 2 * 3 * 64 * 8
+    assert lib.rexii_multishift_workspace_size(ctypes.byref(op), 0, None, ctypes.byref(nb)) == -1
+
+
 def test_default_opts(rx):
     o = rx.make_opts()
     assert o.h == 0.5 and o.m0 == -1 and o.pair_conjugate == 1 and o.precision == 0

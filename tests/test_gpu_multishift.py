@@ -1,0 +1,129 @@
+"""Parity of the shared-Krylov (multi-shift) path (rexii_apply_multishift,
+through the C ABI) with the FP64 CPU oracle.
+
+One Lanczos process per state serves every pole, so the result is the REXII
+approximant of exp(tA) f on the Krylov space; it is held to the exact
+exponential (dense expm on tiny grids, the per-mode closed form for constant
+depth, the oracle's Chebyshev-Bessel series for a depth field) at the
+requested tolerance."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import expm_modes as em
+from oracle import lrsw
+from oracle import varh
+from paper_2008_11607_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2008_11607_amd import rexii
+    rexii.load()
+    return rexii
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(x):
+    return x.detach().cpu().numpy()
+
+
+def _wrel(op, a, b):
+    """Relative error in the W-norm (g |eta|^2 + H (|u|^2 + |v|^2))."""
+    return float(np.sqrt(varh.w_energy(op, a - b) / varh.w_energy(op, b)))
+
+
+def test_multishift_dense_depth_field(rx):
+    nx, ny = 16, 12
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, g=1.0, fc=5.0, Hfield=Hf)
+    t = 20.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=2, seed=9, velocity=True)
+    print("multishift dense 16x12", flush=True)
+    u, rep = rx.apply_multishift(_dev(f), t, g=1.0, fc=5.0, Hfield=_dev(Hf), tol=1e-10)
+    ref = (scipy.linalg.expm(t * lrsw.dense_A(op)) @ f.ravel()).reshape(f.shape)
+    assert em.rel_l2(_host(u), ref) <= 1e-9
+    assert 0 < rep["solves"] <= 3 * nx * ny + 1
+
+
+def test_multishift_depth_field_vs_chebyshev(rx):
+    nx, ny = 96, 72
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, g=1.0, fc=20.0, Hfield=Hf)
+    t = 100.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=4, velocity=True)
+    print("multishift 96x72 t rho 100", flush=True)
+    u, rep = rx.apply_multishift(_dev(f), t, g=1.0, fc=20.0, Hfield=_dev(Hf), tol=1e-10, profile=1)
+    ref = varh.chebyshev_expm(op, f, t)
+    assert em.rel_l2(_host(u), ref) <= 1e-9
+    assert _wrel(op, _host(u), ref) <= 1e-9
+    # the bound on rho(T) never exceeds the guaranteed bound on rho(A)
+    assert rep["rho"] <= lrsw.rho(op) * (1 + 1e-12)
+    assert rep["max_rel_residual"] <= 1e-11
+    assert rep["step_ms"][0] > 0 and rep["step_ms"][2] > 0
+
+
+@pytest.mark.parametrize("nx,ny,trho,fc", [(64, 64, 300.0, 10.0), (45, 37, 50.0, 0.0)])
+def test_multishift_constant_depth(rx, nx, ny, trho, fc):
+    op = lrsw.LRSW(nx, ny, g=1.3, H=0.7, fc=fc)
+    t = trho / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=nx, velocity=True)
+    u, _ = rx.apply_multishift(_dev(f), t, g=1.3, fc=fc, H=0.7, tol=1e-10)
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-9
+
+
+def test_multishift_batch_matches_single_calls(rx):
+    import torch
+    nx, ny = 80, 64
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, g=1.0, fc=20.0, Hfield=Hf)
+    t = 150.0 / lrsw.rho(op)
+    fs = np.stack([inputs.gaussian_bumps(nx, ny, nbumps=2, seed=60 + k, velocity=(k == 1)) for k in range(3)])
+    fs[2] = 0.0                                            # a zero state stays zero
+    Hd = _dev(Hf)
+    ub, rep = rx.apply_multishift(_dev(fs), t, fc=20.0, Hfield=Hd, tol=1e-10)
+    assert float(ub[2].abs().max()) == 0.0
+    for k in range(2):
+        uk, _ = rx.apply_multishift(_dev(fs[k]), t, fc=20.0, Hfield=Hd, tol=1e-10)
+        assert em.rel_l2(_host(ub[k]), _host(uk)) <= 1e-10
+        assert em.rel_l2(_host(ub[k]), varh.chebyshev_expm(op, fs[k], t)) <= 1e-9
+    assert rep["total_iters"] <= 2 * rep["solves"]
+
+
+def test_multishift_invariant_subspace(rx):
+    # a constant height with zero velocity is in the null space of A:
+    # the process stops at m = 1 and exp(tA) f = f
+    nx, ny = 32, 24
+    f = np.zeros((3, ny, nx))
+    f[0] = 0.7
+    Hf = inputs.variable_depth(nx, ny)
+    u, rep = rx.apply_multishift(_dev(f), 0.3, fc=20.0, Hfield=_dev(Hf), tol=1e-10)
+    assert rep["solves"] == 1
+    assert np.max(np.abs(_host(u) - f)) <= 1e-10 * 0.7   # r(0) = 1 up to the approximation error
+
+
+def test_multishift_edge_cases(rx):
+    import torch
+    nx, ny = 32, 24
+    f = _dev(inputs.gaussian_bumps(nx, ny, nbumps=1, seed=1, velocity=True))
+    u, _ = rx.apply_multishift(f, 0.0)
+    assert torch.equal(u, f)
+    bad = f.clone()
+    bad[2, 3, 5] = float("inf")
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply_multishift(bad, 0.1)
+    assert e.value.status == -2
+    op = lrsw.LRSW(nx, ny, fc=10.0)
+    t = 200.0 / lrsw.rho(op)
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply_multishift(f, t, max_iter=16)
+    assert e.value.status == -3
+    assert e.value.report["solves"] == 16

@@ -10,6 +10,8 @@ timed region.
 
 Prints one JSON line (see the keys at the bottom).  Also reported:
   * the all-FP64 path on the same workload (one untimed-warm run),
+  * for comparison, the shared-Krylov (multi-shift) and Fourier-space paths
+    on the same workload (FP64, tol 1e-10),
   * roofline of the dominant kernel (k_pass_f32: one COCG step or FP64
     residual round of every live solve), timed with HIP events on the
     stream it runs on,
@@ -549,6 +551,24 @@ def main():
         out["fp64"] = {"value": D * D * r64["P"] / e64, "ms": 1000 * e64, "P": r64["P"],
                        "rel_l2_vs_oracle": sampled_rel_l2(u64, gold),
                        "total_iters": r64["total_iters"], "max_iters": r64["max_iters"]}
+    if not args.no_fp64:
+        # the other two paths on the same workload, for comparison (FP64, tol 1e-10)
+        rexii.apply_multishift(fd, t, fc=FC, tol=1e-10)   # warm
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ums, rms = rexii.apply_multishift(fd, t, fc=FC, tol=1e-10)
+        torch.cuda.synchronize()
+        ems = time.perf_counter() - t2
+        out["multishift"] = {"ms": 1000 * ems, "P": rms["P"], "krylov_dim": rms["solves"],
+                             "value": D * D * rms["P"] / ems, "rel_l2_vs_oracle": sampled_rel_l2(ums, gold)}
+        ufo, rfo = rexii.apply_fourier(fd, t, fc=FC, tol=1e-10)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ufo, rfo = rexii.apply_fourier(fd, t, fc=FC, tol=1e-10)
+        torch.cuda.synchronize()
+        efo = time.perf_counter() - t3
+        out["fourier"] = {"ms": 1000 * efo, "P": rfo["P"], "value": D * D * rfo["P"] / efo,
+                          "rel_l2_vs_oracle": sampled_rel_l2(ufo, gold)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, t)
     print(json.dumps(out), flush=True)

@@ -108,7 +108,15 @@ typedef struct rexii_opts {
                                chosen together with the slot count when
                                pole_batch < 0.  The COCG path always uses
                                16.  Other values: REXII_ERR_INVALID_ARG    */
+    int32_t scheme;         /* REXII_SCHEME_REXII (0, default) or
+                               REXII_SCHEME_REXI (1: the original REXI matrix
+                               scheme, eq. originalREXImatrix, as a
+                               comparison; rexii_apply_fourier only, other
+                               entry points return REXII_ERR_INVALID_ARG)  */
+    int32_t reserved_opts;
 } rexii_opts;
+
+enum { REXII_SCHEME_REXII = 0, REXII_SCHEME_REXI = 1 };
 
 typedef struct rexii_report {
     int32_t P;               /* number of poles (= 2(N+1))                  */
@@ -164,6 +172,15 @@ void rexii_default_opts(rexii_opts* opts);
  *   kappa_sum may be NULL.  Errors: REXII_ERR_INVALID_ARG. */
 rexii_status rexii_coeffs(double t, double rho, double h, double tol, int32_t m0,
                           int32_t* P, double* beta, double* alpha, double* kappa_sum);
+
+/* Poles and weights of the original REXI matrix scheme (eq. originalREXImatrix,
+ * the paper's comparison scheme): exp(tA) f ~ Re sum_k alpha_k (A - beta_k I)^{-1} f
+ * with beta_k = -alpha_n / t, alpha_n = h (mu + i n), and weights beta^Re_n / t
+ * (eq. originalRexi), n = -N..N ordered 0, 1, -1, 2, -2, ...; *P = 2N + 1,
+ * N = M + 24, M from the same rule as rexii_coeffs.  Arguments and errors as
+ * rexii_coeffs (no kappa_sum). */
+rexii_status rexii_coeffs_rexi(double t, double rho, double h, double tol, int32_t m0,
+                               int32_t* P, double* beta, double* alpha);
 
 /* Spectral radius bound of A (eq. matrixAccuracyBound needs an upper bound).
  * Constant depth: exact, sqrt(f_c^2 + g H0 max(s_x^2 + s_y^2)) with
@@ -228,8 +245,9 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
  *     on the unit square, s = 2 pi k for signed k with the Nyquist mode's
  *     derivative 0 (the paper's discretisation).
  *   op->H_field must be NULL.  opts: h, tol, m0 and rho as for rexii_apply
- *     (rho <= 0: the exact maximum of omega over the modes); other fields
- *     ignored except profile.  f, u: device [3][ny][nx], not overlapping.
+ *     (rho <= 0: the exact maximum of omega over the modes), scheme (REXI
+ *     uses the poles of rexii_coeffs_rexi) and profile; other fields
+ *     ignored.  f, u: device [3][ny][nx], not overlapping.
  *   Workspace: rexii_fourier_workspace_size() bytes (half spectra
  *     [3][ny][nx/2+1] complex128, the term table, the FFT work buffer), or
  *     NULL to let the library allocate.  FFT plans are created on first use

@@ -135,6 +135,23 @@ def rexi_scalar(x, M, h):
     return out
 
 
+def rexi_poles_weights(M, h):
+    """The original REXI matrix scheme (eq. originalREXImatrix),
+    REXI(tau A) = sum_{n=-N}^{N} Re(beta^Re_n (tau A + alpha_n I)^{-1}),
+    alpha_n = h (mu + i n), beta^Re_n = h sum_k a_k Re(b_{n-k}), written as
+    Re sum_k w_k (tau A - z_k I)^{-1} with z = -alpha_n and w = beta^Re_n,
+    n = -N..N (2N + 1 poles, N = M + L).  Comparison scheme."""
+    N = M + L
+    ns = np.arange(-N, N + 1)
+    bre = np.zeros(len(ns), dtype=np.complex128)   # a_k is complex
+    for k in range(-L, L + 1):
+        inside = np.abs(ns - k) <= M
+        bre[inside] += a(k) * b_coef(ns[inside] - k, h).real
+    bre *= h
+    z = -h * (MU + 1j * ns)
+    return z, bre
+
+
 # ----------------------------------------------------------------------------
 # Accuracy rule (eqs. Mformula, matrixAccuracyBound; Appendix B)
 # ----------------------------------------------------------------------------

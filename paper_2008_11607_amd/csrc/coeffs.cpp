@@ -124,6 +124,42 @@ void poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w) 
   }
 }
 
+// The original REXI matrix scheme (eq. originalREXImatrix):
+//   REXI(tA) = sum_{n=-N}^{N} Re(beta^Re_n (tA + alpha_n I)^{-1}),
+//   alpha_n = h (mu + i n),  beta^Re_n = h sum_k a_k Re(b_{n-k})  (eq. originalRexi),
+// as Re sum w (tA - z)^{-1} with z = -alpha_n, w = beta^Re_n (a_k complex),
+// ordered n = 0, 1, -1, 2, -2, ... (2N + 1 poles; z_{-n} = conj(z_n)).
+void rexi_poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w) {
+  using std::complex;
+  const int N = M + kL;
+  z.resize(2 * N + 1);
+  w.resize(2 * N + 1);
+  const double eh2 = std::exp(h * h);
+  // full window: Re b_{n-k} = e^{h^2} (cos(nh) cos(kh) + sin(nh) sin(kh))
+  complex<double> Sc(0.0, 0.0), Ss(0.0, 0.0);
+  for (int k = -kL; k <= kL; ++k) {
+    const complex<double> ak(a_re(k), a_im(k));
+    Sc += ak * std::cos(k * h);
+    Ss += ak * std::sin(k * h);
+  }
+  auto beta_re = [&](int n) {
+    const int k1 = std::max(-kL, n - M), k2 = std::min(kL, n + M);
+    complex<double> s(0.0, 0.0);
+    if (k1 == -kL && k2 == kL) {
+      s = eh2 * (std::cos(n * h) * Sc + std::sin(n * h) * Ss);
+    } else {
+      for (int k = k1; k <= k2; ++k) s += complex<double>(a_re(k), a_im(k)) * (eh2 * std::cos((n - k) * h));
+    }
+    return h * s;
+  };
+  for (int q = 0; q < 2 * N + 1; ++q) {
+    const int n = (q + 1) / 2 * ((q % 2 == 1) ? 1 : -1);  // 0, 1, -1, 2, -2, ...
+    const complex<double> b = beta_re(n);
+    z[q] = {-h * kMu, -h * n};
+    w[q] = {b.real(), b.imag()};
+  }
+}
+
 double kappa_sum(const std::vector<cplx>& w, double h) {
   double s = 0.0;
   for (const cplx& c : w) s += std::hypot(c.re, c.im);
@@ -149,6 +185,36 @@ double rho_bound_var(int nx, int ny, double g, double Hmax, double fc) {
 }
 
 }  // namespace rexii
+
+extern "C" rexii_status rexii_coeffs_rexi(double t, double rho, double h, double tol, int32_t m0, int32_t* P,
+                                          double* beta, double* alpha) {
+  using namespace rexii;
+  if (!P) return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs_rexi: P is NULL");
+  if (!(t > 0.0) || !(rho > 0.0) || !(h > 0.0) || !(h < M_PI) || !std::isfinite(t) || !std::isfinite(rho))
+    return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs_rexi: need t > 0, rho > 0, 0 < h < pi");
+  if (m0 < 0) {
+    if (!(tol > 0.0 && tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs_rexi: tol must be in (0, 1)");
+    m0 = m0_from_tol(tol);
+  }
+  if (std::ceil(t * rho / h) + m0 > 5.0e7) return set_error(REXII_ERR_INVALID_ARG, "rexii_coeffs_rexi: t*rho/h too large");
+  const int M = m_rule(t, rho, h, m0);
+  const int Pn = 2 * (M + terms_L()) + 1;
+  *P = Pn;
+  if (!beta && !alpha) return clear_error();
+  std::vector<cplx> z, w;
+  rexi_poles_weights(M, h, z, w);
+  for (int k = 0; k < Pn; ++k) {
+    if (beta) {
+      beta[2 * k] = z[k].re / t;
+      beta[2 * k + 1] = z[k].im / t;
+    }
+    if (alpha) {
+      alpha[2 * k] = w[k].re / t;
+      alpha[2 * k + 1] = w[k].im / t;
+    }
+  }
+  return clear_error();
+}
 
 extern "C" rexii_status rexii_coeffs(double t, double rho, double h, double tol, int32_t m0,
                                      int32_t* P, double* beta, double* alpha, double* kappa) {

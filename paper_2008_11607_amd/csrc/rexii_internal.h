@@ -25,6 +25,7 @@ int terms_L();
 int m0_from_tol(double tol);
 int m_rule(double t, double rho, double h, int m0);
 void poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w);
+void rexi_poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w);
 double kappa_sum(const std::vector<cplx>& w, double h);
 double max_s2(int n);
 double rho_const(int nx, int ny, double g, double H, double fc);

@@ -198,6 +198,8 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
   if (o.tile_rows != 0 && o.tile_rows != 16 && o.tile_rows != 32)
     return set_error(REXII_ERR_INVALID_ARG, "tile_rows must be 0, 16 or 32");
+  if (o.scheme != REXII_SCHEME_REXII)
+    return set_error(REXII_ERR_INVALID_ARG, "the REXI scheme is available on the Fourier path only");
   if (o.precision != REXII_PREC_FP64 && o.precision != REXII_PREC_MIXED)
     return set_error(REXII_ERR_INVALID_ARG, "unknown precision");
   if (op->H_field && !(hmax > 0.0)) return set_error(REXII_ERR_INVALID_ARG, "variable depth needs max H > 0");
@@ -1427,6 +1429,8 @@ static double rho_fourier(const rexii_swe_op* op, int deriv) {
 // the same z^2 up to the sign of Im z^2 share a denominator and one entry.
 static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv, FourierPlan& fp) {
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
+  if (o.scheme != REXII_SCHEME_REXII && o.scheme != REXII_SCHEME_REXI)
+    return set_error(REXII_ERR_INVALID_ARG, "unknown scheme");
   if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
   fp.rho = (o.rho > 0.0) ? o.rho : rho_fourier(op, deriv);
   fp.m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
@@ -1435,7 +1439,10 @@ static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_o
   fp.M = m_rule(t, fp.rho, o.h, fp.m0);
   fp.N = fp.M + terms_L();
   std::vector<cplx> z, w;
-  poles_weights(fp.M, o.h, z, w);
+  if (o.scheme == REXII_SCHEME_REXI)
+    rexi_poles_weights(fp.M, o.h, z, w);
+  else
+    poles_weights(fp.M, o.h, z, w);
   fp.P = int(z.size());
   fp.kappa = kappa_sum(w, o.h);
   fp.c0 = 0.0;
@@ -1672,6 +1679,8 @@ static rexii_status run_multishift(const rexii_swe_op* op, int nrhs, const doubl
     const rexii_opts o = resolve_opts(opts_in);
     if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
     if (!(o.tol > 0.0 && o.tol < 1.0)) return set_error(REXII_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    if (o.scheme != REXII_SCHEME_REXII)
+      return set_error(REXII_ERR_INVALID_ARG, "the REXI scheme is available on the Fourier path only");
     const int m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
     const int mmax = std::max(8, o.max_iter);
     const int ldb = mmax + 2, ldy = mmax;

@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("m0", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("pole_batch", ctypes.c_int32), ("pair_conjugate", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("method", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("scheme", ctypes.c_int32), ("reserved_opts", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -65,7 +65,8 @@ class Report(ctypes.Structure):
 EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",
            "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
            "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
-           "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_last_error"]
+           "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_coeffs_rexi",
+           "rexii_last_error"]
 
 _lib = None
 
@@ -84,6 +85,8 @@ def load():
     lib.rexii_default_opts.restype = None
     lib.rexii_coeffs.argtypes = [dbl, dbl, dbl, dbl, i32, P(i32), vp, vp, P(dbl)]
     lib.rexii_coeffs.restype = ctypes.c_int
+    lib.rexii_coeffs_rexi.argtypes = [dbl, dbl, dbl, dbl, i32, P(i32), vp, vp]
+    lib.rexii_coeffs_rexi.restype = ctypes.c_int
     lib.rexii_rho.argtypes = [P(SweOp), vp, P(dbl)]
     lib.rexii_rho.restype = ctypes.c_int
     lib.rexii_workspace_size.argtypes = [P(SweOp), P(Opts), dbl, P(sz)]
@@ -121,7 +124,7 @@ def _check(st, report=None):
 
 def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=None,
               pole_batch=None, pair_conjugate=None, inner_tol=None, profile=None, method=None,
-              tile_rows=None):
+              tile_rows=None, scheme=None):
     o = Opts()
     load().rexii_default_opts(ctypes.byref(o))
     if h is not None:
@@ -152,6 +155,8 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
         o.method = {"auto": 0, "cocg": 0, "bicgstab": 1}.get(method, method)
     if tile_rows is not None:
         o.tile_rows = int(tile_rows)
+    if scheme is not None:
+        o.scheme = {"rexii": 0, "rexi": 1}.get(scheme, scheme)
     return o
 
 
@@ -176,6 +181,19 @@ def coeffs(t, rho, h=0.5, tol=1e-10, m0=-1):
     _check(lib.rexii_coeffs(t, rho, h, tol, m0, ctypes.byref(P), beta.ctypes.data_as(ctypes.c_void_p),
                             alpha.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kap)))
     return beta[0::2] + 1j * beta[1::2], alpha[0::2] + 1j * alpha[1::2], kap.value
+
+
+def coeffs_rexi(t, rho, h=0.5, tol=1e-10, m0=-1):
+    """(beta, alpha): complex numpy arrays of the 2N + 1 poles and weights of
+    the original REXI matrix scheme, exp(tA) ~ Re sum alpha_k (A - beta_k)^{-1}."""
+    lib = load()
+    P = ctypes.c_int32()
+    _check(lib.rexii_coeffs_rexi(t, rho, h, tol, m0, ctypes.byref(P), None, None))
+    beta = np.zeros(2 * P.value)
+    alpha = np.zeros(2 * P.value)
+    _check(lib.rexii_coeffs_rexi(t, rho, h, tol, m0, ctypes.byref(P), beta.ctypes.data_as(ctypes.c_void_p),
+                                 alpha.ctypes.data_as(ctypes.c_void_p)))
+    return beta[0::2] + 1j * beta[1::2], alpha[0::2] + 1j * alpha[1::2]
 
 
 def rho(nx, ny, g=1.0, fc=10.0, H=1.0, Hfield=None):

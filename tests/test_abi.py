@@ -53,6 +53,19 @@ def test_coeffs_match_oracle(rx, trho, h, tol):
     assert abs(kap - ref["kappa_sum"]) <= 1e-12 * ref["kappa_sum"]
 
 
+@pytest.mark.parametrize("M,h", [(150, 0.2), (40, 0.5)])
+def test_coeffs_rexi_match_oracle(rx, M, h):
+    # rho chosen so that the M rule gives M exactly (m0 = 0, t = 1)
+    beta, alpha = rx.coeffs_rexi(1.0, M * h, h=h, m0=0)
+    z, w = oc.rexi_poles_weights(M, h)
+    assert len(beta) == len(z)
+    # same pole set (ordered 0, 1, -1, 2, -2, ... here, -N..N in the oracle)
+    ob = np.argsort(beta.imag, kind="stable")
+    oz = np.argsort(z.imag, kind="stable")
+    assert np.max(np.abs(beta[ob] - z[oz])) <= 1e-14 * np.max(np.abs(z))
+    assert np.max(np.abs(alpha[ob] - w[oz])) <= 1e-13 * np.max(np.abs(w))
+
+
 def test_coeffs_explicit_m0(rx):
     beta, _, _ = rx.coeffs(1.0, 30.0, h=0.5, m0=11)
     # M = ceil(30/0.5) + 11 = 71, N = 95, P = 192

@@ -165,3 +165,33 @@ def test_paper_w8_m_threshold_on_gpu(rx):
     ex = sp.exact(f, tab["tau"])
     assert 0.7 * bad["err"] < sp.max_err(ub, ex) < 1.3 * bad["err"]
     assert sp.max_err(ug, ex) < 3.0 * good["err"]
+
+
+@pytest.mark.parametrize("M", [150, 10000, 100000])
+def test_paper_rexi_rows_on_gpu(rx, M):
+    # Table w11, REXI rows: the original REXI matrix scheme (comparison
+    # scheme) on wave scenario 1, tau = 1, h = 0.2, on the Fourier path
+    tab = GOLDEN["w11_rexi"]
+    row = [r for r in tab["rows"] if r["M"] == M][0]
+    f = sp.scenario("wave1")
+    tau, h = tab["tau"], row["h"]
+    print(f"paper REXI row M={M}", flush=True)
+    u, rep = rx.apply_fourier(_dev(f), tau, g=1.0, fc=1.0, H=1.0, derivative="spectral", h=h, m0=0,
+                              rho=M * h / tau, scheme="rexi")
+    assert rep["M"] == M and rep["P"] == 2 * (M + 24) + 1 and rep["solves"] == M + 25
+    u = _host(u)
+    err = sp.max_err(u, sp.exact(f, tau))
+    # three printed digits (the oracle reproduces M = 150 and 10000 to 0.3%)
+    assert abs(err / row["err_cpu"] - 1.0) < (0.02 if M <= 10000 else 0.05)
+    if M <= 10000:
+        z, w = oc.rexi_poles_weights(M, h)
+        bar = max(1e-13, rep["kappa_sum"] * np.finfo(np.float64).eps * np.max(np.abs(f)))
+        assert sp.max_err(u, sp.rexii(f, tau, z, w)) <= bar
+
+
+def test_rexi_scheme_only_on_fourier_path(rx):
+    f = _dev(inputs.gaussian_bumps(16, 16, nbumps=1, seed=1))
+    for call in (rx.apply, rx.apply_multishift):
+        with pytest.raises(rx.RexiiError) as e:
+            call(f, 0.1, scheme="rexi")
+        assert e.value.status == -1

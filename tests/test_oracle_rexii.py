@@ -134,3 +134,27 @@ def test_w8_m_threshold():
     eg = sp.max_err(sp.rexii(f, tab["tau"], zg, wg), ex)
     assert 0.7 * bad["err"] < eb < 1.3 * bad["err"]
     assert eg < 3.0 * good["err"]
+
+
+# ---- the original REXI matrix scheme (comparison scheme, Table w11 REXI rows) ----
+
+@pytest.mark.parametrize("M", [150, 10000])
+def test_rexi_errors_match_paper(M):
+    # REXI(tau A) = sum_n Re(beta^Re_n (tau A + alpha_n)^{-1}) on wave scenario 1,
+    # tau = 1, h = 0.2: the printed errors (three digits) are reproduced
+    tab = GOLDEN["w11_rexi"]
+    row = [r for r in tab["rows"] if r["M"] == M][0]
+    f = sp.scenario("wave1")
+    z, w = coeffs.rexi_poles_weights(M, row["h"])
+    assert len(z) == 2 * (M + coeffs.L) + 1
+    err = sp.max_err(sp.rexii(f, tab["tau"], z, w), sp.exact(f, tab["tau"]))
+    assert abs(err / row["err_cpu"] - 1.0) < 0.01
+
+
+def test_rexi_poles_scalar_form():
+    # on a scalar ix the REXI matrix form is the real part of the scalar
+    # REXI of eq. originalRexi (whose imaginary part it drops)
+    z, w = coeffs.rexi_poles_weights(40, 0.5)
+    x = np.linspace(-15.0, 15.0, 7)
+    lhs = np.array([np.sum(w / (1j * xx - z)).real for xx in x])
+    assert np.max(np.abs(lhs - coeffs.rexi_scalar(x, 40, 0.5).real)) < 1e-12

@@ -92,6 +92,23 @@ class Arena {
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Device-to-host read of `bytes` bytes ordered on `st`: through a pinned
+// staging buffer, then the stream is drained (a copy into pageable memory
+// followed by a stream synchronisation has returned stale data under the
+// profiler's kernel tracing).
+static void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  void* pin = nullptr;
+  HIPCHK(hipHostMalloc(&pin, bytes, hipHostMallocDefault));
+  struct Free {
+    void* p;
+    ~Free() { (void)hipHostFree(p); }
+  } fr{pin};
+  HIPCHK(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(dst, pin, bytes);
+}
+
 // ---------------------------------------------------------------------------
 // problem description
 // ---------------------------------------------------------------------------
@@ -684,8 +701,7 @@ struct Engine {
       if (hcount[0] == 0) break;
     }
     stats.resize(z.S);
-    HIPCHK(hipMemcpyAsync(stats.data(), e.stats, z.S * sizeof(SolveStat), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    read_to_host(stats.data(), e.stats, z.S * sizeof(SolveStat), st);
 #ifdef REXII_DEBUG_CHECKS
     int dbg[16];
     HIPCHK(hipMemcpy(dbg, e.dbg, sizeof(dbg), hipMemcpyDeviceToHost));
@@ -862,9 +878,8 @@ static double device_hmax(const double* H, size_t n, hipStream_t st) {
   HIPCHK(hipGetLastError());
   std::vector<double> hp(nb);
   int fl = 0;
-  HIPCHK(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&fl, dfl, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  read_to_host(hp.data(), part, nb * sizeof(double), st);
+  read_to_host(&fl, dfl, sizeof(int), st);
   if (fl & 8) throw HipError{REXII_ERR_NONFINITE, "depth field has a non-finite or non-positive value"};
   double m = 0.0;
   for (double v : hp) m = std::max(m, v);
@@ -1391,8 +1406,7 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
       launch_adj_dots(ddots, nd, en.e.yout, en.z.cap, f, pf.DZ, pf.pl.has_vel ? pf.DZ + n : nullptr, op->nx, op->ny,
                       t * op->g, pf.pl.has_vel ? 1 : 0, part, nblk, out, st);
       std::vector<double2> hout(nd);
-      HIPCHK(hipMemcpyAsync(hout.data(), out, nd * sizeof(double2), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+      read_to_host(hout.data(), out, nd * sizeof(double2), st);
       double acc = 0.0;
       for (int k = 0; k < nd; ++k) acc += (coef[k] * cd(hout[k].x, hout[k].y)).real();
       *dJdH = -t * op->g * acc;

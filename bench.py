@@ -48,17 +48,14 @@ def workload():
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0000,
 # WRITE_SIZE x 1.0000, scales from a 1 GiB copy): k_pass_f32 on the 512^2
 # workload (128 slots), k_bcg_u1_f32 on the 2048^2 depth-field workload
-# (one state, 8 slots) and k_mode_filter on the two Fourier workloads; valid
-# only for the kernel sources they were taken on.
+# (one state, 8 slots); valid only for the kernel sources they were taken on.
 TRAFFIC = {
     "k_pass_f32": {"bytes_per_launch": 1553566515.7, "fetch_kib": 390749.21, "write_kib": 735675.10,
                    "sources": ["kernels.hip", "kernels.h", "device_util.h"],
                    "sources_sha256": "ecf904a25a6e4aebc7812628fe25905d2466ad9cca83c814ecf09f696d270910"},
-    # per grid size: the 512^2 (t rho = 1000) and 2048^2 (t rho = 5000) Fourier workloads
-    "k_mode_filter": {"bytes_per_launch": {512: 14281537.3, 2048: 209314264.6},
-                      "fetch_kib": {512: 3889.5, 2048: 53005.5}, "write_kib": {512: 6168.0, 2048: 98400.0},
-                      "sources": ["kernels_fft.hip", "kernels_fft.h"],
-                      "sources_sha256": "8ac55238d24140badaa6cefe70867af41cd9b537979504e4fd4647a396148193"},
+    # the Fourier path's pole-sum kernel: not measured (it is bound by FP64
+    # arithmetic and writes 16 bytes per distinct frequency)
+    "k_mode_coef": {"bytes_per_launch": None, "sources": ["kernels_fft.hip", "kernels_fft.h"], "sources_sha256": None},
     "k_bcg_u1_f32": {"bytes_per_launch": 1449208214.6, "fetch_kib": 436723.81, "write_kib": 541815.70,
                      "sources": ["kernels_vh.hip", "kernels.h", "device_util.h"],
                      "sources_sha256": "6fecb750d684290a88d91142c465f9cb57332c5143a4d7af5cea636593b551e4"},
@@ -357,11 +354,10 @@ def run_batched(args):
 
 
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic FP64 flops of the mode kernel: per (term, mode) s = a + theta^2
-# (1), d = s^2 + b^2 (2), 1/d (1), the two accumulations (A s + B)/d (8); per
-# mode the symbol and the two products with t A(k) and the combination (84)
-FLOPS_PER_TERM_MODE = 12
-FLOPS_PER_MODE = 84
+# algorithmic FP64 flops of the pole-sum kernel k_mode_coef: per (term,
+# distinct frequency) s = a + theta^2 (1), d = s^2 + b^2 (2), 1/d (1), the two
+# accumulations (A s + B)/d (8)
+FLOPS_PER_TERM = 12
 
 
 def _fourier_case(D, fc, trho, nbumps, seed, gold_name, steps, warmup):
@@ -387,22 +383,23 @@ def _fourier_case(D, fc, trho, nbumps, seed, gold_name, steps, warmup):
         reps.append(rep)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    P, nterm = reps[0]["P"], reps[0]["solves"]
+    P, nterm, nfreq = reps[0]["P"], reps[0]["solves"], reps[0]["total_iters"]
     nm = (D // 2 + 1) * D
     k_ms = sum(r["kernel_ms"] for r in reps) / steps
-    flops = nm * (nterm * FLOPS_PER_TERM_MODE + FLOPS_PER_MODE)
+    flops = nfreq * nterm * FLOPS_PER_TERM
     achieved = flops / (k_ms * 1e-3) / 1e12
-    step_ms = [sum(r["step_ms"][k] for r in reps) / steps for k in range(4)]
-    return {"D": D, "t_rho": trho, "f_c": fc, "P": P, "terms": nterm, "el": el, "ms": 1000.0 * el / steps,
+    step_ms = [sum(r["step_ms"][k] for r in reps) / steps for k in range(5)]
+    return {"D": D, "t_rho": trho, "f_c": fc, "P": P, "terms": nterm, "distinct_frequencies": nfreq,
+            "half_spectrum_modes": nm, "el": el, "ms": 1000.0 * el / steps,
             "value": D * D * P / (el / steps), "rel_l2_vs_oracle": sampled_rel_l2(u, gold),
-            "roofline": {"bound": "alu", "kernel": "k_mode_filter", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "roofline": {"bound": "alu", "kernel": "k_mode_coef", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                         "traffic": traffic_if_current("k_mode_filter", D),
+                         "traffic": traffic_if_current("k_mode_coef", D),
                          "avg_launch_ms": k_ms, "launches": steps, "alg_flops_per_launch": flops,
                          "waves_per_block": reps[0]["slots"],
                          "kernel_time_share": k_ms * steps * 1e-3 / el},
-            "ms_by_stage": {"copy_check": step_ms[0], "fft_forward": step_ms[1], "mode_filter": step_ms[2],
-                            "fft_inverse": step_ms[3]},
+            "ms_by_stage": {"copy_check": step_ms[0], "fft_forward": step_ms[1], "pole_sums": step_ms[2],
+                            "apply": step_ms[3], "fft_inverse": step_ms[4]},
             "hbm_gbs_alg": sum(r["alg_bytes"] for r in reps) / el / 1e9}
 
 
@@ -432,15 +429,16 @@ def run_fourier(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "lrsw-fd-512x512-trho1000-16bumps-fourier", "D": D, "t_rho": TRHO, "f_c": FC,
                    "method": "Fourier-space REXII: rocFFT real transforms, per-mode closed-form pole sum (FP64)",
-                   "tol": 1e-10, "P": c["P"], "terms": c["terms"], "h": 0.5},
+                   "tol": 1e-10, "P": c["P"], "terms": c["terms"], "h": 0.5,
+                   "distinct_frequencies": c["distinct_frequencies"], "half_spectrum_modes": c["half_spectrum_modes"]},
         "rel_l2_vs_oracle": c["rel_l2_vs_oracle"],
         "hbm_gbs_alg": c["hbm_gbs_alg"],
         "roofline": c["roofline"],
         "ms_by_stage": c["ms_by_stage"],
     }
     if big is not None:
-        out["large"] = {k: big[k] for k in ("D", "t_rho", "f_c", "P", "terms", "ms", "value", "rel_l2_vs_oracle",
-                                            "roofline", "ms_by_stage")}
+        out["large"] = {k: big[k] for k in ("D", "t_rho", "f_c", "P", "terms", "distinct_frequencies", "ms", "value",
+                                            "rel_l2_vs_oracle", "roofline", "ms_by_stage")}
         out["large"]["workload"] = "lrsw-fd-2048x2048-fc20-trho5000-16bumps-fourier"
     if not args.no_cpu:
         f, _, t = workload()

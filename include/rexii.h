@@ -252,13 +252,18 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
  *     [3][ny][nx/2+1] complex128, the term table, the FFT work buffer), or
  *     NULL to let the library allocate.  FFT plans are created on first use
  *     per device and grid and kept until the process ends.
- *   Report: P, M, N, m0, h, t, rho, kappa_sum; solves = terms of the per-mode
- *     sum (two poles of one n share a denominator); slots = waves per block
- *     of the mode kernel; alg_bytes = algorithmic HBM bytes of the path;
- *     kernel_bytes = those of the mode kernel (96 per half-spectrum mode).
- *     With opts.profile = 1: step_ms[0..3] = copy and finiteness check,
- *     forward FFT, mode kernel, inverse FFT (HIP events, ms); kernel_ms =
- *     step_ms[2], kernel_launches = 1.
+ *   The pole sums depend on a mode only through s_x^2 and s_y^2, which
+ *     repeat along each axis: they are formed once per distinct pair
+ *     (about 1/8 of the half spectrum on even grids with centred
+ *     differences) and applied to every mode.
+ *   Report: P, M, N, m0, h, t, rho, kappa_sum; solves = terms of the sum
+ *     (two poles of one n share a denominator); total_iters = distinct
+ *     frequencies the sums were formed at; slots = waves per block of the
+ *     sum kernel; alg_bytes = algorithmic HBM bytes of the path;
+ *     kernel_bytes = those of the apply kernel (96 per half-spectrum mode).
+ *     With opts.profile = 1: step_ms[0..4] = copy and finiteness check,
+ *     forward FFT, pole sums, apply, inverse FFT (HIP events, ms);
+ *     kernel_ms = step_ms[2], kernel_launches = 1.
  * Errors: INVALID_ARG (also for a depth field or an unknown derivative),
  * NONFINITE (u is written anyway), OOM, HIP (including rocFFT failures),
  * WORKSPACE. */

@@ -7,13 +7,19 @@
 
 namespace rexii {
 
-// Fourier-space path (constant depth): per-mode filter of the half spectra
-// F [3][ny][nx/2+1] by the REXII sum, with tab holding nterm merged terms
+// Fourier-space path (constant depth).  tab holds nterm merged terms
 // (a, b^2, A1, B1, A2, B2); deriv 0: centred-difference symbols, 1: Fourier
-// differentiation.  nw: waves (term slices) per block.
-int mode_filter_waves(int nx, int ny, int nterm);
-void launch_mode_filter(double2* F, int nx, int ny, int deriv, double t, double g, double H, double fc, double c0,
-                        double scale, const double* tab, int nterm, int nw, hipStream_t s);
+// differentiation.
+// canon_count: number of distinct canonical wavenumbers among k = 0..kmax on
+// an axis of n points (modes with the same canonical pair share theta).
+int canon_count(int n, int kmax, int deriv);
+// coef [cny][cnx] = scale (Re c1, Re c2) per canonical pair; nw waves per block.
+int mode_coef_waves(int entries, int nterm);
+void launch_mode_coef(double2* coef, int cnx, int cny, int nx, int ny, int deriv, double t, double g, double H,
+                      double fc, double scale, const double* tab, int nterm, int nw, hipStream_t s);
+// F [3][ny][nx/2+1] <- a0 F + C1 t A F + C2 (t A)^2 F with (C1, C2) from coef.
+void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, double t, double g,
+                       double H, double fc, double a0, hipStream_t s);
 void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s);
 
 }  // namespace rexii

@@ -27,6 +27,10 @@
 // (z_2 = -conj(z_1)), so they share the denominator s^2 + b^2 and are
 // merged into one table entry (a, b^2, A1, B1, A2, B2):
 //   Re c1 += (A1 s + B1) / (s^2 + b^2),  Re c2 += (A2 s + B2) / (s^2 + b^2).
+// theta^2 depends on the mode only through s_x^2 and s_y^2, which repeat
+// along each axis, so the sums are formed once per distinct pair
+// (k_mode_coef) and a second kernel applies the quadratic to every mode
+// (k_mode_apply).
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
 
@@ -69,27 +73,11 @@ __device__ __forceinline__ double axis_symbol(int k, int n, int deriv) {
   return 2.0 * M_PI * double(ks);
 }
 
-// F: [3][ny][nxh] half spectra (nxh = nx/2 + 1), filtered in place:
-// F <- scale (c0 F + C1 X F + C2 X^2 F), X = t A(k).  tab: nterm entries of
-// kTermDoubles.  Block: 64 modes (one per lane) x nw waves; wave w sums the
-// terms of slice w, the slices are added in wave order (through
-// (nw - 1) x 1 KB of dynamic LDS), and wave 0 applies the filter.
-__global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __restrict__ F, int nx, int ny, int deriv,
-                                                                 double t, double g, double H, double fc, double c0,
-                                                                 double scale, const double* __restrict__ tab,
-                                                                 int nterm) {
-  extern __shared__ double red[];  // [nw - 1][2][64] partial sums of waves 1..nw-1
-  const int nxh = nx / 2 + 1;
-  const int nm = nxh * ny;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int nw = int(blockDim.x >> 6);
-  const int m = int(blockIdx.x) * 64 + lane;
-  const bool live = m < nm;
-  const int kx = live ? m % nxh : 0, ky = live ? m / nxh : 0;
-  const double sx = axis_symbol(kx, nx, deriv), sy = axis_symbol(ky, ny, deriv);
-  const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
-
+// Re c1 and Re c2 at theta^2 = th2 over the terms [w per, (w + 1) per) of
+// the table (per = ceil(nterm / nw)); the table index is wave-uniform, so
+// the entries arrive through scalar loads.
+__device__ __forceinline__ void term_sums(const double* __restrict__ tab, int nterm, int w, int nw, double th2,
+                                          double& c1, double& c2) {
   const int per = (nterm + nw - 1) / nw;
   const int lo = min(nterm, w * per), hi = min(nterm, lo + per);
   // (A s + B) / d is accumulated as (s/d) A + (1/d) B: one scalar (table)
@@ -134,7 +122,55 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __rest
     const double* q = tab + size_t(j) * kTermDoubles;
     one(q, recip(den(q)));
   }
-  double c1 = c1a + c1b, c2 = c2a + c2b;
+  c1 = c1a + c1b;
+  c2 = c2a + c2b;
+}
+
+// Canonical wavenumber of k on an axis of n points: the smallest index
+// with the same s^2 (centred differences: sin^2(2 pi k / n) has period n/2
+// and is symmetric about n/4 for even n, symmetric about n/2 for odd n;
+// Fourier differentiation: s^2 depends on |signed k|, the Nyquist mode's
+// derivative is 0).  theta, and with it the coefficients of r(t A(k)),
+// depends on the mode only through these two numbers.
+__host__ __device__ inline int canon_index(int k, int n, int deriv) {
+  if (deriv == 0 && n % 2 == 0) {
+    const int h = n / 2, kc = k % h;
+    return kc < h - kc ? kc : h - kc;
+  }
+  if (deriv != 0 && 2 * k == n) return 0;
+  return k < n - k ? k : n - k;
+}
+
+int canon_count(int n, int kmax, int deriv) {
+  int c = 0;
+  for (int k = 0; k <= kmax; ++k) {
+    const int v = canon_index(k, n, deriv);
+    c = v > c ? v : c;
+  }
+  return c + 1;
+}
+
+// The pole sums per distinct frequency: coef[cy * cnx + cx] = scale (Re c1,
+// Re c2) at theta^2 = t^2 (f_c^2 + g H (s_x^2 + s_y^2)) for the canonical
+// wavenumbers (cx, cy).  tab: nterm entries of kTermDoubles.  Block: 64
+// entries (one per lane) x nw waves; wave w sums the terms of slice w, the
+// slices are added in wave order through (nw - 1) x 1 KB of dynamic LDS.
+__global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restrict__ coef, int cnx, int cny, int nx,
+                                                               int ny, int deriv, double t, double g, double H,
+                                                               double fc, double scale,
+                                                               const double* __restrict__ tab, int nterm) {
+  extern __shared__ double red[];
+  const int ne = cnx * cny;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int nw = int(blockDim.x >> 6);
+  const int e = int(blockIdx.x) * 64 + lane;
+  const bool live = e < ne;
+  const int cx = live ? e % cnx : 0, cy = live ? e / cnx : 0;
+  const double sx = axis_symbol(cx, nx, deriv), sy = axis_symbol(cy, ny, deriv);
+  const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
+  double c1, c2;
+  term_sums(tab, nterm, w, nw, th2, c1, c2);
   if (nw > 1) {
     if (w > 0) {
       red[(w - 1) * 128 + lane] = c1;
@@ -147,11 +183,25 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __rest
       c2 += red[(v - 1) * 128 + 64 + lane];
     }
   }
-  if (!live) return;
+  if (live) coef[e] = make_double2(scale * c1, scale * c2);
+}
 
+// F: [3][ny][nxh] half spectra, filtered in place with the coefficients of
+// the mode's canonical frequency: F <- scale c0 F + C1 X F + C2 X^2 F,
+// X = t A(k) with the mode's own (signed) symbols.
+__global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, const double2* __restrict__ coef,
+                                                    int cnx, int nx, int ny, int deriv, double t, double g, double H,
+                                                    double fc, double a0) {
+  const int nxh = nx / 2 + 1;
+  const int nm = nxh * ny;
+  const int m = int(blockIdx.x) * 256 + threadIdx.x;
+  if (m >= nm) return;
+  const int kx = m % nxh, ky = m / nxh;
+  const double2 c = coef[canon_index(ky, ny, deriv) * cnx + canon_index(kx, nx, deriv)];
+  const double sx = axis_symbol(kx, nx, deriv), sy = axis_symbol(ky, ny, deriv);
   double2 f[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) f[c] = F[size_t(c) * nm + m];
+  for (int q = 0; q < 3; ++q) f[q] = F[size_t(q) * nm + m];
   // X v with X = t A(k); -i a (x + i y) = (a y, -a x)
   const double hx = t * H * sx, hy = t * H * sy, gx = t * g * sx, gy = t * g * sy, tf = t * fc;
   auto apply = [&](const double2 (&v)[3], double2 (&o)[3]) {
@@ -162,11 +212,10 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_filter(double2* __rest
   double2 x1[3], x2[3];
   apply(f, x1);
   apply(x1, x2);
-  const double a0 = scale * c0, a1 = scale * c1, a2 = scale * c2;
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    F[size_t(c) * nm + m] = make_double2(a0 * f[c].x + a1 * x1[c].x + a2 * x2[c].x,
-                                         a0 * f[c].y + a1 * x1[c].y + a2 * x2[c].y);
+  for (int q = 0; q < 3; ++q)
+    F[size_t(q) * nm + m] = make_double2(a0 * f[q].x + c.x * x1[q].x + c.y * x2[q].x,
+                                         a0 * f[q].y + c.x * x1[q].y + c.y * x2[q].y);
 }
 
 // u = f, flag[0] = 1 if any value is not finite.
@@ -180,22 +229,30 @@ __global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ 
   if (bad) atomicOr(flag, 1);
 }
 
-// Waves per block: 8 (measured best at 512^2 and 2048^2 with 2000-10000
-// terms), fewer when a wave would get under 64 terms.
-int mode_filter_waves(int nx, int ny, int nterm) {
-  (void)nx;
-  (void)ny;
+// Waves per block of k_mode_coef: 8 (measured best with 2000-10000 terms),
+// 16 when few blocks would otherwise leave the GPU idle, fewer when a wave
+// would get under 64 terms.
+int mode_coef_waves(int entries, int nterm) {
+  const int blocks = (entries + 63) / 64;
+  const int cap = (blocks < 1024) ? kModeWaves : 8;
   int nw = 1;
-  while (nw < 8 && nterm >= 128 * nw) nw *= 2;
+  while (nw < cap && nterm >= 128 * nw) nw *= 2;
   return nw;
 }
 
-void launch_mode_filter(double2* F, int nx, int ny, int deriv, double t, double g, double H, double fc, double c0,
-                        double scale, const double* tab, int nterm, int nw, hipStream_t s) {
-  const long nm = long(nx / 2 + 1) * ny;
+void launch_mode_coef(double2* coef, int cnx, int cny, int nx, int ny, int deriv, double t, double g, double H,
+                      double fc, double scale, const double* tab, int nterm, int nw, hipStream_t s) {
+  const int ne = cnx * cny;
   const size_t lds = size_t(nw - 1) * 128 * sizeof(double);
-  hipLaunchKernelGGL(k_mode_filter, dim3(unsigned((nm + 63) / 64)), dim3(64 * nw), lds, s, F, nx, ny, deriv, t, g,
-                     H, fc, c0, scale, tab, nterm);
+  hipLaunchKernelGGL(k_mode_coef, dim3(unsigned((ne + 63) / 64)), dim3(64 * nw), lds, s, coef, cnx, cny, nx, ny,
+                     deriv, t, g, H, fc, scale, tab, nterm);
+}
+
+void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, double t, double g,
+                       double H, double fc, double a0, hipStream_t s) {
+  const long nm = long(nx / 2 + 1) * ny;
+  hipLaunchKernelGGL(k_mode_apply, dim3(unsigned((nm + 255) / 256)), dim3(256), 0, s, F, coef, cnx, nx, ny, deriv, t,
+                     g, H, fc, a0);
 }
 
 void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s) {

@@ -1480,9 +1480,19 @@ static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_o
   return REXII_OK;
 }
 
-static size_t fourier_bytes(int nx, int ny, int nterm, size_t fft_work) {
+// distinct canonical wavenumbers of the half spectrum's x (k = 0..nx/2) and
+// y (k = 0..ny-1) indices
+static void fourier_canon(int nx, int ny, int deriv, int* cnx, int* cny) {
+  *cnx = canon_count(nx, nx / 2, deriv);
+  *cny = canon_count(ny, ny - 1, deriv);
+}
+
+static size_t fourier_bytes(int nx, int ny, int deriv, int nterm, size_t fft_work) {
   const size_t nm = size_t(nx / 2 + 1) * ny;
-  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(256) + al256(fft_work);
+  int cnx = 0, cny = 0;
+  fourier_canon(nx, ny, deriv, &cnx, &cny);
+  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(size_t(cnx) * cny * 16) + al256(256) +
+         al256(fft_work);
 }
 
 static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double* u, double t, int deriv,
@@ -1510,7 +1520,9 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     void *fwd = nullptr, *inv = nullptr;
     s = fft_plans(nx, ny, &work, &fwd, &inv);
     if (s != REXII_OK) return s;
-    const size_t need = fourier_bytes(nx, ny, fp.nterm, work);
+    const size_t need = fourier_bytes(nx, ny, deriv, fp.nterm, work);
+    int cnx = 0, cny = 0;
+    fourier_canon(nx, ny, deriv, &cnx, &cny);
     Arena ar(ws, ws_bytes);
     if (!ws) {
       ar.reserve_own(need + 4096);
@@ -1521,38 +1533,42 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     }
     double2* F = ar.take<double2>(3 * nm);
     double* tab = ar.take<double>(fp.tab.size());
+    double2* coef = ar.take<double2>(size_t(cnx) * cny);
     double* flagd = ar.take<double>(32);
     void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
     int* flag = reinterpret_cast<int*>(flagd);
     HIPCHK(hipMemcpyAsync(tab, fp.tab.data(), fp.tab.size() * sizeof(double), hipMemcpyHostToDevice, st));
     launch_fill_zero(flagd, 32, st);
     const bool prof = (o.profile != 0);
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[6] = {};
     if (prof)
       for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {
       hipEvent_t* e;
       ~EvGuard() {
-        for (int k = 0; k < 5; ++k)
+        for (int k = 0; k < 6; ++k)
           if (e[k]) (void)hipEventDestroy(e[k]);
       }
     } guard{ev};
     auto mark = [&](int k) {
       if (prof) HIPCHK(hipEventRecord(ev[k], st));
     };
-    const int nw = mode_filter_waves(nx, ny, fp.nterm);
+    const int ne = cnx * cny;
+    const int nw = mode_coef_waves(ne, fp.nterm);
+    const double scale = 1.0 / (double(nx) * ny);
     mark(0);
     launch_copy_check(f, u, n3, flag, st);  // the forward transform may overwrite its input
     mark(1);
     s = fft_execute(fwd, u, F, wk, work, st);
     if (s != REXII_OK) return s;
     mark(2);
-    launch_mode_filter(F, nx, ny, deriv, t, op->g, op->H0, op->f_cor, fp.c0, 1.0 / (double(nx) * ny), tab, fp.nterm,
-                       nw, st);
+    launch_mode_coef(coef, cnx, cny, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, st);
     mark(3);
+    launch_mode_apply(F, coef, cnx, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
+    mark(4);
     s = fft_execute(inv, F, u, wk, work, st);
     if (s != REXII_OK) return s;
-    mark(4);
+    mark(5);
     HIPCHK(hipGetLastError());
     // the flag is read into pinned host memory (one word per host thread,
     // kept for the life of the process), ordered on the stream
@@ -1572,13 +1588,14 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
       rep->rho = fp.rho;
       rep->kappa_sum = fp.kappa;
       rep->slots = nw;
-      // copy 16, forward FFT 8 + 16 nm/n, filter 2 x 48 nm/n, inverse 16 nm/n + 8 bytes per point and field
+      rep->total_iters = ne;  // distinct frequencies the pole sums were formed at
+      // copy 16, forward FFT 8 + 16 nm/n, apply 2 x 48 nm/n, inverse 16 nm/n + 8 bytes per point and field
       rep->alg_bytes = double(n3) * 32.0 + 3.0 * double(nm) * (16.0 + 96.0 + 16.0);
       rep->kernel_bytes = 96.0 * double(nm);
       if (prof) {
-        float ms[4] = {};
-        for (int k = 0; k < 4; ++k) HIPCHK(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
-        for (int k = 0; k < 4; ++k) rep->step_ms[k] = ms[k];
+        float ms[5] = {};
+        for (int k = 0; k < 5; ++k) HIPCHK(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+        for (int k = 0; k < 5; ++k) rep->step_ms[k] = ms[k];
         rep->kernel_launches = 1;
         rep->kernel_ms = ms[2];
       }
@@ -1949,7 +1966,7 @@ rexii_status rexii_fourier_workspace_size(const rexii_swe_op* op, const rexii_op
   size_t work = 0;
   v = fft_plans(op->nx, op->ny, &work, nullptr, nullptr);
   if (v != REXII_OK) return v;
-  *bytes = fourier_bytes(op->nx, op->ny, fp.nterm, work);
+  *bytes = fourier_bytes(op->nx, op->ny, derivative, fp.nterm, work);
   return clear_error();
 }
 

@@ -83,7 +83,9 @@ def test_fourier_full_size(rx, n):
     u, rep = rx.apply_fourier(_dev(f), t, tol=1e-10, profile=1)
     assert rep["P"] == oc.api_coeffs(t, lrsw.rho(op), h=0.5, tol=1e-10)["P"]
     assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
-    assert rep["kernel_ms"] > 0.0 and all(x > 0.0 for x in rep["step_ms"][:4])
+    assert rep["kernel_ms"] > 0.0 and all(x > 0.0 for x in rep["step_ms"][:5])
+    # the pole sums are formed once per distinct (s_x^2, s_y^2): 129 x 129 here
+    assert rep["total_iters"] == 129 * 129
 
 
 def test_fourier_workspace_and_repeat(rx):

@@ -25,9 +25,9 @@
 namespace rexii {
 
 constexpr int kLzTX = 64;   // tile columns (one per lane)
-constexpr int kLzRows = 4;  // rows per thread
+constexpr int kLzRows = 8;  // rows per thread (a sliding window of three rows)
 constexpr int kLzNT = 256;  // threads: 64 x 4
-constexpr int kLzTY = kLzRows * (kLzNT / kLzTX);  // 16 rows per tile
+constexpr int kLzTY = kLzRows * (kLzNT / kLzTX);  // 32 rows per tile
 
 __device__ __forceinline__ double block_sum_lz(double v, double* sh) {
 #pragma unroll
@@ -70,47 +70,52 @@ __global__ __launch_bounds__(kLzNT) void k_lz_step(const double* __restrict__ cu
   const int j0 = (blockIdx.x / tiles_x) * kLzTY + (threadIdx.x >> 6) * kLzRows;
   const double hx = 0.5 * nx, hy = 0.5 * ny;
   double acc = 0.0;
-  if (i < nx) {
+  if (i < nx && j0 < ny) {
     const int ie = (i + 1 == nx) ? 0 : i + 1, iw = (i == 0) ? nx - 1 : i - 1;
+    const double* ce = c;
+    const double* cu = c + n;
+    const double* cv = c + 2 * n;
+    // rows jj - 1, jj, jj + 1 of eta, v and the depth in registers: each
+    // row is loaded once per thread and slides down the window
+    auto row = [&](int jj) { return size_t(jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj)) * nx + i; };
+    const size_t q0 = row(j0 - 1), q1 = row(j0);
+    double eS = ce[q0], eC = ce[q1], vS = cv[q0], vC = cv[q1];
+    double HS = H ? H[q0] : H0, HC = H ? H[q1] : H0;
     for (int k = 0; k < kLzRows; ++k) {
       const int jj = j0 + k;
       if (jj >= ny) break;
-      const int jn = (jj + 1 == ny) ? 0 : jj + 1, js = (jj == 0) ? ny - 1 : jj - 1;
-      const size_t p = size_t(jj) * nx + i;
+      const size_t p = size_t(jj) * nx + i, qn = row(jj + 1);
       const size_t pe = size_t(jj) * nx + ie, pw = size_t(jj) * nx + iw;
-      const size_t pn = size_t(jn) * nx + i, ps = size_t(js) * nx + i;
-      const double* ce = c;
-      const double* cu = c + n;
-      const double* cv = c + 2 * n;
-      double Hp = H0, He = H0, Hw = H0, Hn = H0, Hs = H0;
-      if (H) {
-        Hp = H[p];
-        He = H[pe];
-        Hw = H[pw];
-        Hn = H[pn];
-        Hs = H[ps];
-      }
+      const double eN = ce[qn], vN = cv[qn], HN = H ? H[qn] : H0;
+      const double He = H ? H[pe] : H0, Hw = H ? H[pw] : H0;
+      const double b0 = eC, b1 = cu[p], b2 = vC;
       // A buf_j (flux form, centred differences)
-      const double ae = -(hx * (He * cu[pe] - Hw * cu[pw]) + hy * (Hn * cv[pn] - Hs * cv[ps]));
-      const double au = -g * hx * (ce[pe] - ce[pw]) + fc * cv[p];
-      const double av = -g * hy * (ce[pn] - ce[ps]) - fc * cu[p];
-      const double b0 = ce[p], b1 = cu[p], b2 = cv[p];
+      const double ae = -(hx * (He * cu[pe] - Hw * cu[pw]) + hy * (HN * vN - HS * vS));
+      const double au = -g * hx * (ce[pe] - ce[pw]) + fc * b2;
+      const double av = -g * hy * (eN - eS) - fc * b1;
       if (ur && yc != 0.0) {  // y_j = 0 beyond a state's own Krylov dimension
         ur[p] += yc * b0;
         ur[n + p] += yc * b1;
         ur[2 * n + p] += yc * b2;
       }
-      if (last) continue;
-      double w0 = sc * ae, w1 = sc * au, w2 = sc * av;
-      if (j >= 2) {
-        w0 += sp * pv[p];
-        w1 += sp * pv[n + p];
-        w2 += sp * pv[2 * n + p];
+      if (!last) {
+        double w0 = sc * ae, w1 = sc * au, w2 = sc * av;
+        if (j >= 2) {
+          w0 += sp * pv[p];
+          w1 += sp * pv[n + p];
+          w2 += sp * pv[2 * n + p];
+        }
+        pv[p] = w0;
+        pv[n + p] = w1;
+        pv[2 * n + p] = w2;
+        acc += g * w0 * w0 + HC * (w1 * w1 + w2 * w2);
       }
-      pv[p] = w0;
-      pv[n + p] = w1;
-      pv[2 * n + p] = w2;
-      acc += g * w0 * w0 + Hp * (w1 * w1 + w2 * w2);
+      eS = eC;
+      eC = eN;
+      vS = vC;
+      vC = vN;
+      HS = HC;
+      HC = HN;
     }
   }
   if (!part) return;

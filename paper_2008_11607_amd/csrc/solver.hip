@@ -1735,14 +1735,14 @@ static rexii_status run_multishift(const rexii_swe_op* op, int nrhs, const doubl
     int* flag = reinterpret_cast<int*>(flagd);
     const double* Hf = op->H_field;
     const double H0 = op->H0, g = op->g, fc = op->f_cor;
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[2] = {};  // around the whole call (pass 2 is timed per state)
     const bool prof = (o.profile != 0);
     if (prof)
       for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     struct EvGuard {
       hipEvent_t* e;
       ~EvGuard() {
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 2; ++k)
           if (e[k]) (void)hipEventDestroy(e[k]);
       }
     } guard{ev};

@@ -197,3 +197,19 @@ def test_rexi_scheme_only_on_fourier_path(rx):
         with pytest.raises(rx.RexiiError) as e:
             call(f, 0.1, scheme="rexi")
         assert e.value.status == -1
+
+
+def test_fourier_2048_against_samples(rx):
+    # the 2048^2 constant-depth workload of the bench (f_c = 20, t rho = 5000)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lrsw2048_trho5000.json")))
+    D = g["D"]
+    op = lrsw.LRSW(D, D, fc=g["f_c"])
+    t = g["t_rho"] / lrsw.rho(op)
+    assert abs(t - g["t"]) <= 1e-12 * t
+    f = inputs.gaussian_bumps(D, nbumps=g["nbumps"], seed=g["seed"])
+    u, rep = rx.apply_fourier(_dev(f), t, fc=g["f_c"], tol=1e-10)
+    assert rep["total_iters"] == 513 * 513
+    idx = np.asarray(g["index"])
+    ref = np.asarray(g["value"])
+    got = _host(u).reshape(-1)[idx]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-10

@@ -127,3 +127,25 @@ def test_multishift_edge_cases(rx):
         rx.apply_multishift(f, t, max_iter=16)
     assert e.value.status == -3
     assert e.value.report["solves"] == 16
+
+
+@pytest.mark.parametrize("trho,bar", [(100.0, 1e-10), (5000.0, 1e-10)])
+def test_multishift_full_size_against_samples(rx, trho, bar):
+    # the 2048^2 depth-field workload (f_c = 20, state seed 50) at the size
+    # the bench runs, against the oracle's stored Chebyshev-Bessel samples
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"varh2048_trho{int(trho)}.json")))
+    D = g["D"]
+    Hf = inputs.variable_depth(D)
+    op = lrsw.LRSW(D, D, g=1.0, fc=g["f_c"], Hfield=Hf)
+    t = trho / lrsw.rho(op)
+    assert abs(t - g["t"]) <= 1e-12 * t
+    f = inputs.gaussian_bumps(D, nbumps=g["nbumps"], seed=g["seed"])
+    print(f"multishift 2048^2 t rho {trho}", flush=True)
+    u, rep = rx.apply_multishift(_dev(f), t, fc=g["f_c"], Hfield=_dev(Hf), tol=1e-10)
+    idx = np.asarray(g["index"])
+    ref = np.asarray(g["value"])
+    got = _host(u).reshape(-1)[idx]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= bar
+    assert abs(varh.w_energy(op, _host(u)) / g["w_energy_f"] - 1.0) <= 1e-12

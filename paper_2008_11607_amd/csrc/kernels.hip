@@ -532,6 +532,12 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
       // rounding floor, above the requested tolerance
       S->status = kDone;
       S->stagnated = 1;
+      if (n2 > prev) {
+        // the last correction made the iterate worse (an inner solve that
+        // diverged): x64 holds the previous iterate, of residual prev
+        S->discard = 1;
+        S->rn2 = prev;
+      }
     } else if (ldc(&S->it_total) >= e.max_iter) {
       S->status = kFailMaxIter;
     } else {

@@ -611,6 +611,12 @@ __global__ __launch_bounds__(kSNT) void k_bcg_scalars_u(Eng e) {
       // rounding floor, above the requested tolerance
       S->status = kDone;
       S->stagnated = 1;
+      if (rn2 > prev) {
+        // the last correction made the iterate worse (an inner solve that
+        // diverged): x64 holds the previous iterate, of residual prev
+        S->discard = 1;
+        S->rn2 = prev;
+      }
       return;
     }
     if (ldc(&S->it_total) >= e.max_iter) {

@@ -187,3 +187,17 @@ def test_apply_512_grid_full_size(rx, precision, bar):
     assert rep["P"] == (4068 if precision == "fp64" else 4064)
     assert rep["not_converged"] == 0
     assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= bar
+
+
+def test_diverging_inner_solve_is_dropped(rx):
+    # 128^2 at t rho = 1918 (a state of the full heterogeneous batch): the
+    # Helmholtz shifts of some poles sit on the spectrum of the coarse grid's
+    # Laplacian, and an FP32 inner solve can diverge.  The FP64 loop must keep
+    # the better iterate instead of adding that correction.
+    op = lrsw.LRSW(128, 128, fc=10.0)
+    t = 1918.315005415708 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(128, nbumps=16, seed=538)
+    print("diverging inner solve case 128^2 t rho 1918", flush=True)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision="mixed", tol=1e-6, max_iter=400000)
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-6
+    assert rep["max_rel_residual"] < 1.0

@@ -49,8 +49,10 @@ typedef enum {
     REXII_OK = 0,
     REXII_ERR_INVALID_ARG = -1,   /* bad pointer, size, shape or option      */
     REXII_ERR_NONFINITE = -2,     /* NaN or Inf in the input state or depth  */
-    REXII_ERR_NOT_CONVERGED = -3, /* a shifted solve hit max_iter (u is still
-                                     written, from the best iterates)        */
+    REXII_ERR_NOT_CONVERGED = -3, /* a shifted solve hit its iteration cap, or
+                                     the achieved error bound (report
+                                     err_bound) exceeds tol; u is still
+                                     written, from the best iterates        */
     REXII_ERR_BREAKDOWN = -4,     /* Krylov breakdown (p^T K p == 0)         */
     REXII_ERR_OOM = -5,           /* device allocation failed                */
     REXII_ERR_HIP = -6,           /* a HIP runtime call failed               */
@@ -80,7 +82,12 @@ typedef struct rexii_opts {
                                inner Krylov iterations, FP64 residuals,
                                refinement, weights and pole sum)            */
     int32_t max_iter;       /* cap on Krylov iterations of one solve, all
-                               refinement rounds together; 0 -> 50000       */
+                               refinement rounds together; 0 -> per solve
+                               from its Chebyshev iteration estimate c_s:
+                               20 c_s + 5000 in FP64, 4 c_s + 2000 for the
+                               FP32 inner iterations of MIXED (a solve past
+                               it is solved again in FP64).  Shared-Krylov
+                               path: cap on m, 0 -> 50000                  */
     int32_t m0;             /* safety term of the M rule; < 0 -> from tol   */
     double rho;             /* bound on the spectral radius of A; <= 0 ->
                                computed (exact for constant depth)          */
@@ -135,10 +142,11 @@ typedef struct rexii_report {
                                c_s its estimated iterations per e-fold
                                (capped at 1e-2)                             */
     double max_rel_residual; /* largest final FP64 relative residual        */
-    double seconds;          /* host wall time of the call                  */
+    double seconds;          /* host wall time of the call (seconds_total)  */
     double alg_bytes;        /* algorithmic HBM bytes of the Krylov kernels */
-    int32_t stagnated;       /* solves stopped at their FP64 residual floor
-                               (above their tolerance; counted as converged)       */
+    int32_t stagnated;       /* FP64 solves stopped at their residual floor
+                               above their tolerance (their residuals enter
+                               err_bound)                                  */
     int32_t slots;           /* concurrent solves the engine ran with        */
     /* with opts.profile = 1: launches and summed HIP-event time of the COCG
      * pass kernel, and the algorithmic bytes of those launches (a pass reads
@@ -155,6 +163,25 @@ typedef struct rexii_report {
     double u1_bytes;
     int32_t tile_rows;       /* rows of the work tiles the engine ran with   */
     int32_t reserved;
+    /* Achieved error bound of the pole sum, relative in the W-norm
+     * (W = diag(g, H, H)): by Theorem 1 (eq. teorem, cond(V) = 1 in the W-norm
+     * because WA is skew) the error of each pole's resolvent is at most its
+     * residual / |h mu|, so
+     *     |u - r(tA) f|_W / |f|_W <= err_bound = sum_s wsum_s |r_s|_W / |f|_W,
+     * wsum_s = sum of |alpha_k t| / |h mu| over the poles solve s serves and
+     * r_s its final FP64 residual (only the height row is non-zero).  The call
+     * returns REXII_ERR_NOT_CONVERGED when err_bound > tol.  Explicit shifts
+     * (rexii_shifted_solve): the largest relative residual of a shift. */
+    double err_bound;
+    double seconds_solve;    /* host wall time of the Krylov engine(s): the
+                               solves, without set-up and reconstruction    */
+    int32_t retried;         /* MIXED: solves whose FP32 inner iterations
+                               failed (non-finite, diverged, stalled or past
+                               their cap) and that were solved again in FP64 */
+    int32_t hist_buckets;    /* 20 */
+    int32_t iter_hist[20];   /* solves by Krylov iterations (both attempts of
+                               a re-run solve): bucket 0 holds 0..1, bucket
+                               k holds [2^k, 2^(k+1)), the last one is open */
 } rexii_report;
 
 /* Fill *opts with the defaults described above. */

@@ -63,13 +63,6 @@ def apply_A(op, f):
     return out
 
 
-def apply_E(op, f):
-    """E f = dA/dH f for constant depth: (-dx u - dy v, 0, 0)."""
-    out = np.zeros_like(f, dtype=np.float64)
-    out[0] = -dx(f[1], op.nx) - dy(f[2], op.ny)
-    return out
-
-
 def dense_A(op):
     """Dense matrix of A, assembled column by column from apply_A on unit
     vectors (no Fourier analysis involved).  Small grids only."""
@@ -81,17 +74,6 @@ def dense_A(op):
         A[:, c] = apply_A(op, e.reshape(3, op.ny, op.nx)).ravel()
         e[c] = 0.0
     return A
-
-
-def dense_E(op):
-    n = op.n
-    E = np.zeros((n, n))
-    e = np.zeros(n)
-    for c in range(n):
-        e[c] = 1.0
-        E[:, c] = apply_E(op, e.reshape(3, op.ny, op.nx)).ravel()
-        e[c] = 0.0
-    return E
 
 
 # ----------------------------------------------------------------------------

@@ -53,6 +53,11 @@ enum SlotStatus : int {
   kFailBreakdown = 6, // non-finite scalars
   kInnerLast = 7,     // BiCGStab: stop test fired, last update of d pending
   kPrime = 8,         // COCG: residual taken, first step (p = r) pending
+  kRetry = 9,         // mixed precision: stopped without reaching its tolerance
+                      // (an inner round went non-finite or diverged, the FP64
+                      // residual stagnated, or the inner-precision iteration
+                      // cap was hit); not accumulated, the host solves it
+                      // again in FP64
 };
 
 // One problem (an initial state on a grid) of the launch.
@@ -73,8 +78,14 @@ struct SolveDev {
   double2 zeta, a1, a2;   // shift and RHS coefficients
   double2 gamma, sc;      // BiCGStab path: cross-term factor, RHS scale
   double2 c0, c1, c2;     // accumulation weights
-  double tol2;            // done when ||b - K x||^2 <= tol2 ||b||^2
+  double tol2;            // done when ||b - K x||^2 <= tol2 ref2
+  double ref2;            // reference of the stop test: > 0 a fixed value
+                          // (||f||_W^2 / (g scale^2), so that the test
+                          // bounds the solve's share of the error of the
+                          // weighted sum), 0: ||b||^2 (relative residual)
   int inst;
+  int max_it;             // cap on this solve's Krylov iterations
+  int yidx;               // row of Eng::yout that receives its solution
   int pad;
 };
 
@@ -95,6 +106,7 @@ struct Slot {
   double prev_rn2;   // residual of the previous FP64 round
   double in_tol2;    // inner stop: recursive ||r||^2 <= in_tol2
   double tol2;       // final relative tolerance^2 of this solve
+  double ref2;       // reference norm^2 of the stop test (see SolveDev)
   double cx, cy, cxy;  // stencil coefficients of the solve's problem
   const double* H;     // its depth field (BiCGStab path) or nullptr
   const void* Hin;     // the same in the inner-iteration type
@@ -114,6 +126,8 @@ struct Slot {
   int stagnated;
   int discard;       // BiCGStab: d holds no usable correction (its last
                      // inner round went non-finite); the iterate is x64
+  int max_it;        // iteration cap of the solve (from SolveDev)
+  int pad2;
 };
 
 // Everything the kernels of one engine need (passed by value).
@@ -123,7 +137,9 @@ struct Eng {
   int cap;               // points per slot vector (max over instances)
   int cap_blk;           // partial-sum slots per slot (max tiles)
   double inner_eta2;     // relative reduction^2 of one inner solve
-  int max_iter;
+  int retry;             // 1: a solve that fails in the inner precision
+                         // ends as kRetry (mixed precision), 0: it ends
+                         // stagnated (kDone) or failed
   int method;            // 0: COCG on the constant-depth Helmholtz; 1: BiCGStab (flux form)
   int d_is_f32;          // inner precision of d, r, p (1: FP32, 0: FP64)
   int grid_small;        // persistent grid of kernels that mostly find no work
@@ -150,7 +166,10 @@ struct Eng {
   void* v0;              // BiCGStab: v = K p (ping-pong) and the shadow residual
   void* v1;
   void* rh;
-  double2* yout;         // nullptr: accumulate; else [S][cap] solutions
+  double2* yout;         // nullptr: accumulate; else solutions, row
+                         // SolveDev::yidx of [*][ystride]
+  int ystride;           // row stride of yout (points)
+  int pad_e;
   int* dbg;              // [16] consistency counters (debug builds only)
 };
 
@@ -199,6 +218,11 @@ void launch_reconstruct(const double* f, const double* A, int nx, int ny, double
 void launch_expand(const double2* y, const double* f, int nx, int ny, double2 inv_sigma, double2 m1,
                    double2 m2, double tg, int has_vel, double2* out, hipStream_t s);
 void launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
+// Partial sums of ||f||_W^2 = g |eta|^2 + H (|u|^2 + |v|^2) for a state f
+// [3][n] (H: depth field [n] or nullptr for the constant H0), one per block
+// of a fixed grid of wnorm_blocks() blocks, in part[0 .. wnorm_blocks()).
+int wnorm_blocks();
+void launch_wnorm2(const double* f, const double* H, double H0, double g, size_t n, double* part, hipStream_t s);
 void launch_scale3(const double* src, double* dst, size_t n, double s0, double s1, double s2, hipStream_t s);
 void launch_scale1(double* p, size_t n, double s, hipStream_t st);
 int adj_dot_blocks(size_t n);

@@ -520,32 +520,44 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
     const int rounds = rounds0 + 1;
     S->rounds = rounds;
     const double prev = ldc(&S->prev_rn2);
-    const double tol2 = ldc(&S->tol2);
+    const double ref2 = ldc(&S->ref2);
+    // stop threshold on |b - K x|^2: tol2 times the fixed reference, or
+    // times |b|^2 (relative residual)
+    const double thr = ldc(&S->tol2) * (ref2 > 0.0 ? ref2 : bn2);
     S->rn2 = n2;
     S->prev_rn2 = n2;
+    const bool capped = ldc(&S->it_total) >= ldc(&S->max_it);
     if (!isfinite(n2)) {
-      S->status = kFailBreakdown;
-    } else if (n2 <= tol2 * bn2) {
+      // an inner round went non-finite: in mixed precision the solve is run
+      // again in FP64
+      S->status = e.retry ? kRetry : kFailBreakdown;
+    } else if (n2 <= thr) {
       S->status = kDone;
     } else if (rounds >= 3 && n2 > 0.25 * prev) {
-      // a whole inner solve did not halve the FP64 residual: it sits at its
-      // rounding floor, above the requested tolerance
-      S->status = kDone;
-      S->stagnated = 1;
-      if (n2 > prev) {
-        // the last correction made the iterate worse (an inner solve that
-        // diverged): x64 holds the previous iterate, of residual prev
-        S->discard = 1;
-        S->rn2 = prev;
+      // a whole inner solve did not halve the FP64 residual.  In mixed
+      // precision the FP32 inner solves stalled or diverged: FP64 retry.  In
+      // FP64 the iterate sits at its rounding floor, above the requested
+      // tolerance; the achieved residual enters the reported error bound.
+      if (e.retry) {
+        S->status = kRetry;
+      } else {
+        S->status = kDone;
+        S->stagnated = 1;
+        if (n2 > prev) {
+          // the last correction made the iterate worse (an inner solve that
+          // diverged): x64 holds the previous iterate, of residual prev
+          S->discard = 1;
+          S->rn2 = prev;
+        }
       }
-    } else if (ldc(&S->it_total) >= e.max_iter) {
-      S->status = kFailMaxIter;
+    } else if (capped) {
+      S->status = e.retry ? kRetry : kFailMaxIter;
     } else {
       S->status = kPrime;
       S->it_inner = 0;
       // the requested reduction of this residual, never below a quarter of
       // the final tolerance
-      S->in_tol2 = fmax(e.inner_eta2 * n2, 0.0625 * tol2 * bn2);
+      S->in_tol2 = fmax(e.inner_eta2 * n2, 0.0625 * thr);
     }
     return;
   }
@@ -557,7 +569,7 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
                   (fabs(rr.x) + fabs(rr.y) > 0.0);
   if (status == kPrime) {
     if (!ok) {
-      S->status = kFailBreakdown;
+      S->status = e.retry ? kRetry : kFailBreakdown;
       return;
     }
     S->status = kInner;
@@ -567,7 +579,7 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
     S->it_inner = ldc(&S->it_inner) + 1;
     const int it_total = ldc(&S->it_total) + 1;
     S->it_total = it_total;
-    if (!ok || !isfinite(n2) || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
+    if (!ok || !isfinite(n2) || n2 <= ldc(&S->in_tol2) || it_total >= ldc(&S->max_it)) {
       S->status = kInnerDone;
       return;
     }
@@ -587,7 +599,7 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
 // scheduler
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool finished(int st) {
-  return st == kDone || st == kFailMaxIter || st == kFailBreakdown;
+  return st == kDone || st == kFailMaxIter || st == kFailBreakdown || st == kRetry;
 }
 
 // Exclusive prefix sum of one int per thread over a block of kSchedNT
@@ -641,11 +653,18 @@ __global__ __launch_bounds__(kSchedNT) void k_retire(Eng e) {
     const Slot* S = &e.slots[s];
     const Inst I = ld_inst(&e.inst[ldc(&S->inst)]);
     const int n = I.nx * I.ny;
+    if (ldc(&S->status) == kRetry) {
+      // solved again in FP64 by the host: nothing is kept from this attempt
+      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        e.x64[size_t(s) * e.cap + i] = make_double2(0.0, 0.0);
+      continue;
+    }
     // the last inner correction d is still to be added (once the solve has
     // run an inner round)
     const bool add_d = ldc(&S->rounds) >= 2 && ldc(&S->discard) == 0;
     const int sv = ldc(&S->solve);
     const double2 c0 = ldc(&e.solves[sv].c0), c1 = ldc(&e.solves[sv].c1), c2 = ldc(&e.solves[sv].c2);
+    const size_t yrow = e.yout ? size_t(ldc(&e.solves[sv].yidx)) * e.ystride : 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
       double2* xp = e.x64 + size_t(s) * e.cap + i;
       double2 x = *xp;
@@ -660,7 +679,7 @@ __global__ __launch_bounds__(kSchedNT) void k_retire(Eng e) {
           x.y += dv.y;
         }
       }
-      if (e.yout) e.yout[size_t(sv) * e.cap + i] = x;
+      if (e.yout) e.yout[yrow + i] = x;
       I.A[i] += c0.x * x.x - c0.y * x.y;
       I.A[n + i] += c1.x * x.x - c1.y * x.y;
       I.A[2 * n + i] += c2.x * x.x - c2.y * x.y;
@@ -681,6 +700,7 @@ __device__ __forceinline__ void assign_solve(Eng& e, int s, int next) {
   S->sc = ldc(&D->sc);
   S->omega = make_double2(0.0, 0.0);
   S->tol2 = ldc(&D->tol2);
+  S->ref2 = ldc(&D->ref2);
   S->rr = S->alpha = S->beta = make_double2(0.0, 0.0);
   S->bn2 = S->rn2 = S->prev_rn2 = S->in_tol2 = 0.0;
   S->status = kOuterPending;
@@ -704,6 +724,7 @@ __device__ __forceinline__ void assign_solve(Eng& e, int s, int next) {
   S->Z0 = ldc_ptr(&I->Z0);
   S->stagnated = 0;
   S->discard = 0;
+  S->max_it = ldc(&D->max_it);
 }
 
 // One block: record finished solves, hand out the next ones in queue order
@@ -1013,6 +1034,25 @@ void launch_adj_dots(const AdjDot* d, int nd, const double2* yout, int cap, cons
                      part, nblk);
   hipLaunchKernelGGL(k_adj_reduce, dim3(nd), dim3(256), 0, s, part, nblk, out);
 }
+constexpr int kWnBlocks = 256;
+__global__ __launch_bounds__(256) void k_wnorm2(const double* f, const double* H, double H0, double g, size_t n,
+                                                double* part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(kWnBlocks) * 256) {
+    const double eta = f[i], u = f[n + i], v = f[2 * n + i];
+    const double h = H ? H[i] : H0;
+    acc += g * eta * eta + h * (u * u + v * v);
+  }
+  double v[1] = {acc}, tot[1];
+  block_sum_n<1>(v, red, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot[0];
+}
+int wnorm_blocks() { return kWnBlocks; }
+void launch_wnorm2(const double* f, const double* H, double H0, double g, size_t n, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_wnorm2, dim3(kWnBlocks), dim3(256), 0, s, f, H, H0, g, n, part);
+}
+
 static inline unsigned flat_blocks(size_t n) {
   size_t bl = (n + 255) / 256;
   return unsigned(bl > 8192 ? 8192 : (bl < 1 ? 1 : bl));

@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kSNT) void k_bcg_scalars_s(Eng e) {
   const double n2 = fmax(ss - (ts.x * ts.x + ts.y * ts.y) / tt, 0.0);
   const double2 rho = ldc(&S->rr), al = ldc(&S->alpha);
   const bool ok = nonzero(om) && nonzero(rho1) && nonzero(rho) && finite2(rho1);
-  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= e.max_iter) {
+  if (!ok || n2 <= ldc(&S->in_tol2) || it_total >= ldc(&S->max_it)) {
     S->status = kInnerLast;
     return;
   }
@@ -595,20 +595,29 @@ __global__ __launch_bounds__(kSNT) void k_bcg_scalars_u(Eng e) {
     const int rounds = rounds0 + 1;
     S->rounds = rounds;
     const double prev = ldc(&S->prev_rn2);
-    const double tol2 = ldc(&S->tol2);
+    const double ref2 = ldc(&S->ref2);
+    // stop threshold on |b - K x|^2: tol2 times the fixed reference, or
+    // times |b|^2 (relative residual)
+    const double thr = ldc(&S->tol2) * (ref2 > 0.0 ? ref2 : bn2);
     S->rn2 = rn2;
     S->prev_rn2 = rn2;
     if (!isfinite(rn2)) {
-      S->status = kFailBreakdown;
+      S->status = e.retry ? kRetry : kFailBreakdown;
       return;
     }
-    if (rn2 <= tol2 * bn2) {
+    if (rn2 <= thr) {
       S->status = kDone;
       return;
     }
     if (rounds >= 3 && rn2 > 0.25 * prev) {
-      // a whole inner solve did not halve the FP64 residual: it sits at its
-      // rounding floor, above the requested tolerance
+      // a whole inner solve did not halve the FP64 residual.  Mixed
+      // precision: the FP32 inner solves stalled or diverged, FP64 retry.
+      // FP64: the iterate sits at its rounding floor, above the requested
+      // tolerance; the achieved residual enters the reported error bound.
+      if (e.retry) {
+        S->status = kRetry;
+        return;
+      }
       S->status = kDone;
       S->stagnated = 1;
       if (rn2 > prev) {
@@ -619,15 +628,15 @@ __global__ __launch_bounds__(kSNT) void k_bcg_scalars_u(Eng e) {
       }
       return;
     }
-    if (ldc(&S->it_total) >= e.max_iter) {
-      S->status = kFailMaxIter;
+    if (ldc(&S->it_total) >= ldc(&S->max_it)) {
+      S->status = e.retry ? kRetry : kFailMaxIter;
       return;
     }
     // restart: r_hat = r, rho = <r_hat, r> = |r|^2 of the rounded residual
     rho = make_double2(tot[3], 0.0);
     S->rr = rho;
     S->it_inner = 0;
-    S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * tol2 * bn2);
+    S->in_tol2 = fmax(e.inner_eta2 * rn2, 0.0625 * thr);
     S->status = kInner;
   }
   const double2 al = (finite2(hv) && nonzero(hv) && nonzero(rho)) ? cdiv(rho, hv) : make_double2(NAN, NAN);
@@ -635,9 +644,13 @@ __global__ __launch_bounds__(kSNT) void k_bcg_scalars_u(Eng e) {
     if (!outer) {
       // breakdown inside the inner solve: restart from the FP64 residual
       S->status = kInnerDone;
+    } else if (e.retry) {
+      // no usable restart in the inner precision: FP64 retry
+      S->status = kRetry;
     } else if (ldc(&S->rounds) >= 2) {
       // no usable restart from a finite residual above the tolerance: the
-      // solve stops at its current iterate
+      // solve stops at its current iterate (its residual enters the
+      // reported error bound)
       S->status = kDone;
       S->stagnated = 1;
     } else {

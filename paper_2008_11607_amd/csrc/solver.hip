@@ -83,6 +83,10 @@ class Arena {
     off_ += bytes;
     return p;
   }
+  // bytes handed out so far; reset(m) gives back everything taken after m
+  size_t mark() const { return off_; }
+  void reset(size_t m) { off_ = m; }
+  size_t remaining() const { return cap_ - off_; }
 
  private:
   char* base_ = nullptr;
@@ -117,8 +121,17 @@ struct SolveDesc {
   cd gamma = 0.0, sc = 1.0;  // flux-form (BiCGStab) path: cross-term factor, RHS scale
   cd c0, c1, c2;       // accumulation weights (A_j += Re(c_j y))
   cd inv_sigma, m1, m2;
-  double cost;         // expected relative Krylov cost (for scheduling)
+  double cost;         // expected Krylov iterations at tol (Chebyshev estimate)
   double tol = 0.0;    // relative residual this solve is driven to
+  // Error bound of the weighted sum (Theorem 1 with cond(V) = 1 in the W-norm,
+  // every resolvent of norm <= 1/|h mu|): the solve contributes
+  // wsum * sqrt(g) |r3| / |f|_W, wsum = sum of |w_k| / |h mu| over the poles
+  // it serves and r3 = rscale * (the solver's residual) the eta-row residual of
+  // the 3-field system (the velocity rows are exact).
+  double wsum = 0.0;
+  double rscale = 1.0;
+  double ref2 = 0.0;   // stop-test reference (SolveDev::ref2)
+  int yidx = -1;       // row of the kept solutions (-1: the queue position)
   int pole;            // first pole index this solve serves
 };
 
@@ -141,6 +154,7 @@ struct Plan {
   std::vector<cd> w_fwd;   // forward weights (w holds the adjoint ones in adjoint plans)
   std::vector<SolveDesc> solves;
   double S1 = 0, S2 = 0;
+  bool shifts = false;     // explicit shifts (resolvents), no weighted sum
 };
 
 struct GridGeo {
@@ -185,7 +199,7 @@ static rexii_opts resolve_opts(const rexii_opts* o) {
   if (o) r = *o;
   if (r.h <= 0.0) r.h = 0.5;
   if (r.tol <= 0.0) r.tol = (r.precision == REXII_PREC_MIXED) ? 1e-6 : 1e-10;
-  if (r.max_iter <= 0) r.max_iter = 50000;
+  if (r.max_iter < 0) r.max_iter = 0;   // 0: caps per solve (Krylov paths), 50000 (shared-Krylov m)
   if (r.inner_tol <= 0.0) r.inner_tol = 1e-4;
   return r;
 }
@@ -355,6 +369,9 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
       double a = std::abs(pl.w[sd.pole]) / hmu;
       if (pl.paired) a += std::abs(pl.w[sd.pole + 1]) / hmu;
       sd.tol = (a > 0.0) ? std::min(pl.tol * c[i] / (a * csum), 1e-2) : 1e-2;
+      sd.wsum = a;
+      // flux form: the solver's system is the eta row scaled by sc
+      sd.rscale = pl.bicg ? 1.0 / std::abs(sd.sc) : 1.0;
       pl.pole_tol = std::min(pl.pole_tol, sd.tol);
       sd.cost = cheb_cost(pl.bicg ? sd.zeta / pl.hmax : sd.zeta, lmax, sd.tol);
     }
@@ -396,6 +413,7 @@ struct Problem {
   double* A = nullptr;         // device accumulators [3][ny][nx]
   const double* H = nullptr;   // device depth field (flux-form path)
   const void* Hin = nullptr;   // the depth in the inner-iteration type
+  double fw2 = 0.0;            // ||f||_W^2, W = diag(g, H, H)
   size_t n() const { return size_t(pl.nx) * pl.ny; }
 };
 
@@ -438,9 +456,9 @@ static EngineSize engine_size(const std::vector<Problem*>& probs, int requested_
   return z;
 }
 
-// device bytes of the engine (problem arrays D0/Z0 and A are counted by
-// the caller)
-static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
+// device bytes of the engine (problem arrays D0/Z0 and A and the kept
+// solutions are counted by the caller)
+static size_t engine_bytes(const EngineSize& z) {
   size_t b = 0;
   b += al256(z.B * sizeof(Slot)) + al256(z.ninst * sizeof(Inst));
   b += al256(z.S * sizeof(SolveDev)) + al256(z.S * sizeof(SolveStat));
@@ -449,9 +467,18 @@ static size_t engine_bytes(const EngineSize& z, bool keep_solutions) {
   b += al256(size_t(z.B) * (z.cap_blk + 7) * sizeof(int2));
   b += al256(size_t(z.B) * z.cap * 16);
   b += size_t(z.nvec) * al256(size_t(z.B) * z.cap * z.eb);
-  if (keep_solutions) b += al256(size_t(z.S) * z.cap * 16);
   b += al256(16 * sizeof(int));
   return b;
+}
+
+// Iteration cap of one solve: opts.max_iter if set, else from its Chebyshev
+// estimate: 4x in FP32 inner arithmetic (a mixed-precision solve past it is
+// re-run in FP64), 20x in FP64.
+static int solve_cap(double cost, int precision, int user_max_iter) {
+  if (user_max_iter > 0) return user_max_iter;
+  const double c = std::isfinite(cost) ? std::max(cost, 0.0) : 1e9;
+  const double cap = (precision == REXII_PREC_MIXED) ? 4.0 * c + 2000.0 : 20.0 * c + 5000.0;
+  return int(std::min(cap, 1.0e9));
 }
 
 // D/Z, A, a small block, a constant depth field when a constant-depth
@@ -483,6 +510,10 @@ struct Engine {
   double pass_bytes = 0.0;
   std::vector<size_t> inst_points;
   std::vector<char> inst_vel;
+  std::vector<const Plan*> plans;  // plan of each instance
+  int max_cap = 0;                // largest per-solve iteration cap
+  std::vector<char> retried;      // per queued solve: re-run in FP64
+  double solve_seconds = 0.0;     // host wall time of run()
 
   explicit Engine(hipStream_t s) : st(s) {}
   ~Engine() {
@@ -492,8 +523,11 @@ struct Engine {
     if (hcount) (void)hipHostFree(hcount);
   }
 
-  void setup(Arena& ar, const std::vector<Problem*>& probs, const EngineSize& zs, int prec, int max_iter,
-             double inner_eta, bool prof, bool keep_solutions) {
+  // yout: device [rows][ystride] complex128 kept solutions (row
+  // SolveDesc::yidx, or the queue position when that is -1) or nullptr to
+  // accumulate only.
+  void setup(Arena& ar, const std::vector<Problem*>& probs, const EngineSize& zs, int prec, int user_max_iter,
+             double inner_eta, bool prof, double2* yout, int ystride) {
     z = zs;
     precision = prec;
     profile = prof;
@@ -502,9 +536,9 @@ struct Engine {
     e.method = z.method;
     e.th = z.th;
     e.d_is_f32 = (prec == REXII_PREC_MIXED) ? 1 : 0;
+    e.retry = e.d_is_f32;
     e.cap = z.cap;
     e.cap_blk = z.cap_blk;
-    e.max_iter = max_iter;
     e.inner_eta2 = inner_eta * inner_eta;
     e.slots = ar.take<Slot>(z.B);
     Inst* dinst = ar.take<Inst>(z.ninst);
@@ -528,9 +562,12 @@ struct Engine {
       e.v1 = ar.take<char>(size_t(z.B) * z.cap * z.eb);
       e.rh = ar.take<char>(size_t(z.B) * z.cap * z.eb);
     }
-    e.yout = keep_solutions ? ar.take<double2>(size_t(z.S) * z.cap) : nullptr;
+    e.yout = yout;
+    e.ystride = ystride;
     e.dbg = ar.take<int>(16);
 
+    plans.clear();
+    for (Problem* p : probs) plans.push_back(&p->pl);
     // problem table
     std::vector<Inst> hinst(z.ninst);
     inst_points.resize(z.ninst);
@@ -583,7 +620,12 @@ struct Engine {
       D.gamma = to_d2(d.gamma);
       D.sc = to_d2(d.sc);
       D.tol2 = d.tol * d.tol;
+      D.ref2 = d.ref2;
       D.inst = q[j].inst;
+      D.max_it = solve_cap(d.cost, prec, user_max_iter);
+      D.yidx = (d.yidx >= 0) ? d.yidx : j;
+      D.pad = 0;
+      max_cap = std::max(max_cap, D.max_it);
       hs[j] = D;
       solve_inst[j] = q[j].inst;
       solve_index[j] = q[j].idx;
@@ -649,7 +691,7 @@ struct Engine {
   // run).  With max_chunks > 0 the time of chunks 2..max_chunks is returned
   // (ms, HIP events on the engine's stream) and no statistics are read.
   template <typename T>
-  double run(int max_iter, int max_chunks = 0) {
+  double run(int max_chunks = 0) {
     if (max_chunks > 0) {
       build_graph<T>();
       hipEvent_t a = nullptr, b = nullptr;
@@ -672,9 +714,10 @@ struct Engine {
     } else {
       build_graph<T>();
     }
-    // enough replays for every solve to run max_iter iterations in turn
+    const auto w0 = std::chrono::steady_clock::now();
+    // enough replays for every solve to run to its iteration cap in turn
     const int64_t per_slot = (int64_t(z.S) + z.B - 1) / z.B;
-    const int64_t max_replays = per_slot * (int64_t(max_iter) / chunk + 8) + 8;
+    const int64_t max_replays = per_slot * (int64_t(max_cap) / chunk + 8) + 8;
     for (int64_t rep = 0; rep < max_replays; ++rep) {
       if (profile) {
         enqueue_chunk<T>(true);
@@ -702,6 +745,7 @@ struct Engine {
     }
     stats.resize(z.S);
     read_to_host(stats.data(), e.stats, z.S * sizeof(SolveStat), st);
+    solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
 #ifdef REXII_DEBUG_CHECKS
     int dbg[16];
     HIPCHK(hipMemcpy(dbg, e.dbg, sizeof(dbg), hipMemcpyDeviceToHost));
@@ -748,10 +792,18 @@ struct Engine {
   }
 };
 
+constexpr int kHistBuckets = 20;
+
 struct RunSummary {
   int max_iters = 0, max_rounds = 0, not_conv = 0, breakdowns = 0, stagnated = 0;
   int64_t total_iters = 0;
   double max_rel_res = 0.0;
+  // error bound of the result (relative, W-norm): sum over the solves of
+  // wsum * (achieved |r3|) / |f|_W; explicit shifts: the largest relative
+  // residual
+  double err_bound = 0.0;
+  int retried = 0;
+  int hist[kHistBuckets] = {};
 };
 
 static RunSummary summarize(const Engine& en, int inst) {
@@ -765,7 +817,19 @@ static RunSummary summarize(const Engine& en, int inst) {
     if (s.status == kFailBreakdown) r.breakdowns++;
     else if (s.status != kDone) r.not_conv++;
     r.stagnated += s.stagnated;
-    r.max_rel_res = std::max(r.max_rel_res, s.bn2 > 0 ? std::sqrt(s.rn2 / s.bn2) : 0.0);
+    if (j < en.retried.size() && en.retried[j]) r.retried++;
+    const double rel = s.bn2 > 0 ? std::sqrt(s.rn2 / s.bn2) : 0.0;
+    r.max_rel_res = std::max(r.max_rel_res, rel);
+    const Plan& pl = *en.plans[en.solve_inst[j]];
+    const SolveDesc& d = pl.solves[en.solve_index[j]];
+    if (pl.shifts) {
+      r.err_bound = std::max(r.err_bound, rel);
+    } else if (d.ref2 > 0.0) {
+      r.err_bound += d.wsum * std::sqrt(s.rn2 / d.ref2);
+    }
+    int b = 0;
+    for (unsigned v = unsigned(std::max(s.it_total, 1)); v > 1 && b < kHistBuckets - 1; v >>= 1) ++b;
+    r.hist[b]++;
   }
   return r;
 }
@@ -792,6 +856,11 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     rep->total_iters = r.total_iters;
     rep->max_rel_residual = r.max_rel_res;
     rep->stagnated = r.stagnated;
+    rep->err_bound = r.err_bound;
+    rep->retried = r.retried;
+    rep->seconds_solve = en->solve_seconds;
+    rep->hist_buckets = kHistBuckets;
+    for (int k = 0; k < kHistBuckets; ++k) rep->iter_hist[k] = r.hist[k];
     const double eb = double(inner_elem_bytes(pl.precision));
     // COCG: a pass reads x, r, p and writes them back (6 complex values per
     // point); BiCGStab: an iteration moves 13 complex values and reads the
@@ -813,6 +882,7 @@ static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>
   pl.paired = false;
   pl.solves.clear();
   const double g = op->g, H = op->H0, fc = op->f_cor;
+  const double lmax = max_s2(op->nx) + max_s2(op->ny);
   for (size_t k = 0; k < shifts.size(); ++k) {
     const cd zk = shifts[k];
     const cd den = zk * zk + t * t * fc * fc;
@@ -828,7 +898,8 @@ static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>
       s.a2 = t * s.m2;
       s.inv_sigma = 1.0;
       s.c0 = s.c1 = s.c2 = 0.0;
-      s.cost = 0.0;
+      s.cost = cheb_cost(s.zeta / pl.hmax, lmax, tol);
+      s.rscale = 1.0 / std::abs(s.sc);
       s.pole = int(k);
       pl.solves.push_back(s);
       continue;
@@ -839,11 +910,12 @@ static void shift_solves(const rexii_swe_op* op, double t, const std::vector<cd>
     s.a2 = t * H * s.m2;
     s.inv_sigma = 1.0 / sig;
     s.c0 = s.c1 = s.c2 = 0.0;
-    s.cost = 0.0;
+    s.cost = cheb_cost(s.zeta, lmax, tol);
     s.pole = int(k);
     pl.solves.push_back(s);
   }
   pl.pole_tol = tol;
+  pl.shifts = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -899,6 +971,7 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
   std::vector<Problem> pbs(items.size());
   std::vector<Problem*> ptrs;
   size_t b = extra + al256(std::max<size_t>(1, items.size()) * sizeof(int)) + 4096;
+  b += al256(std::max<size_t>(1, items.size()) * wnorm_blocks() * sizeof(double));
   for (size_t i = 0; i < items.size(); ++i) {
     if (items[i].skip) continue;
     rexii_status st = sizing_plan(items[i], o, pbs[i]);
@@ -906,7 +979,14 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
     ptrs.push_back(&pbs[i]);
     b += problem_bytes(pbs[i]);
   }
-  if (!ptrs.empty()) b += engine_bytes(engine_size(ptrs, o.pole_batch, o.precision, o.tile_rows), keep);
+  if (!ptrs.empty()) {
+    const EngineSize z = engine_size(ptrs, o.pole_batch, o.precision, o.tile_rows);
+    if (keep) b += al256(size_t(z.S) * z.cap * 16);
+    size_t eb = engine_bytes(z);
+    // mixed precision: room for an FP64 re-run engine of at least one slot
+    if (o.precision == REXII_PREC_MIXED) eb = std::max(eb, engine_bytes(engine_size(ptrs, 1, REXII_PREC_FP64, 0)));
+    b += eb;
+  }
   *bytes = b;
   return REXII_OK;
 }
@@ -925,6 +1005,67 @@ struct Job {
   ~Job() { delete en; }
 };
 
+// Mixed precision: the solves that ended as kRetry (their FP32 inner
+// solves went non-finite, diverged, stalled or hit their cap) are solved
+// again from scratch by an FP64 engine in the first engine's memory, and
+// accumulate into the same fields; their statistics are merged (iterations
+// of both attempts, the outcome of the second).
+static void rerun_fp64(Job& jb, Arena& ar, size_t mark, double2* yout) {
+  Engine& en = *jb.en;
+  en.retried.assign(en.z.S, 0);
+  std::vector<Problem> rp(jb.ptrs.size());
+  std::vector<std::vector<int>> origin(jb.ptrs.size());  // first-engine queue position of each re-run solve
+  int nre = 0;
+  for (int j = 0; j < en.z.S; ++j) {
+    if (en.stats[j].status != kRetry) continue;
+    const int inst = en.solve_inst[j];
+    if (origin[inst].empty()) {
+      rp[inst] = *jb.ptrs[inst];
+      rp[inst].pl.solves.clear();
+      rp[inst].pl.precision = REXII_PREC_FP64;
+      rp[inst].Hin = rp[inst].H;   // FP64 inner passes read the FP64 depth
+    }
+    SolveDesc d = jb.ptrs[inst]->pl.solves[en.solve_index[j]];
+    d.yidx = j;
+    rp[inst].pl.solves.push_back(d);
+    origin[inst].push_back(j);
+    en.retried[j] = 1;
+    ++nre;
+  }
+  if (nre == 0) return;
+  std::vector<Problem*> rptr;
+  std::vector<int> rinst;
+  for (size_t i = 0; i < rp.size(); ++i)
+    if (!origin[i].empty()) {
+      rptr.push_back(&rp[i]);
+      rinst.push_back(int(i));
+    }
+  ar.reset(mark);
+  EngineSize z = engine_size(rptr, 0, REXII_PREC_FP64, 0);
+  z.B = std::min(z.B, std::max(1, en.z.B));
+  while (z.B > 1 && engine_bytes(z) > ar.remaining()) z.B = std::max(1, (z.B * 3) / 4);
+  Engine er(jb.st);
+  er.setup(ar, rptr, z, REXII_PREC_FP64, jb.o.max_iter, 0.0, en.profile, yout, en.z.cap);
+  er.run<double>();
+  for (int k = 0; k < er.z.S; ++k) {
+    const int j = origin[rinst[er.solve_inst[k]]][er.solve_index[k]];
+    SolveStat& a = en.stats[j];
+    const SolveStat& b = er.stats[k];
+    a.it_total += b.it_total;
+    a.rounds += b.rounds;
+    a.status = b.status;
+    a.rn2 = b.rn2;
+    a.bn2 = b.bn2;
+    a.stagnated = b.stagnated;
+  }
+  en.pass_bytes += er.pass_bytes;
+  en.u1_bytes += er.u1_bytes;
+  en.kernel_ms += er.kernel_ms;
+  en.launches += er.launches;
+  for (int k = 0; k < Engine::kBcgEvents - 1; ++k) en.step_ms[k] += er.step_ms[k];
+  en.solve_seconds += er.solve_seconds;
+}
+
 // Prepares every problem (input checks, div/curl, plans) and runs the engine
 // (only max_chunks chunks if > 0; returns their time in ms).
 static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
@@ -939,6 +1080,9 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
   } fh{flags};
   int* dflags = ar.take<int>(std::max<size_t>(1, ni));
   launch_fill_zero(reinterpret_cast<double*>(dflags), (std::max<size_t>(1, ni) + 1) / 2, jb.st);
+  // ||f||_W^2 of every problem (block partials, summed on the host)
+  const int nwb = wnorm_blocks();
+  double* dwn = ar.take<double>(std::max<size_t>(1, ni) * nwb);
   bool any_depth_field = false;
   for (const JobItem& it : jb.items) any_depth_field = any_depth_field || (!it.skip && it.op->H_field);
   // one engine runs one method: a depth field anywhere puts every problem
@@ -976,10 +1120,17 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
       launch_to_f32(pb.H, hf32, n, jb.st);
       pb.Hin = hf32;
     }
+    launch_wnorm2(it.f, it.op->H_field, it.op->H0, it.op->g, n, dwn + i * nwb, jb.st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(flags, dflags, ni * sizeof(int), hipMemcpyDeviceToHost, jb.st));
-  HIPCHK(hipStreamSynchronize(jb.st));
+  std::vector<double> wn(ni * nwb, 0.0);
+  read_to_host(wn.data(), dwn, ni * nwb * sizeof(double), jb.st);  // drains the stream
+  for (size_t i = 0; i < ni; ++i) {
+    double a = 0.0;
+    for (int b = 0; b < nwb; ++b) a += wn[i * nwb + b];
+    jb.pbs[i].fw2 = a;
+  }
   bool all_div_free = true;
   for (size_t i = 0; i < ni; ++i) {
     if (jb.items[i].skip) continue;
@@ -994,20 +1145,30 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
     bool div_free = (flags[i] & 4) == 0;
     if (jb.pair_all) div_free = all_div_free;
     if (jb.force_unpaired || it.shifts) div_free = false;
-    rexii_status st = build_plan(it.op, it.t, jb.o, has_vel, div_free, jb.pbs[i].pl, it.adjoint, it.hmax);
+    Plan& pl = jb.pbs[i].pl;
+    rexii_status st = build_plan(it.op, it.t, jb.o, has_vel, div_free, pl, it.adjoint, it.hmax);
     if (st != REXII_OK) throw HipError{st, g_err};
-    if (it.shifts) shift_solves(it.op, it.t, *it.shifts, jb.o.tol, jb.pbs[i].pl);
+    if (it.shifts) shift_solves(it.op, it.t, *it.shifts, jb.o.tol, pl);
+    // pole sums: each solve stops when its share of the error bound,
+    // wsum sqrt(g) |r3| / |f|_W with r3 = rscale (b - K x), is within
+    // wsum eps_s, i.e. |b - K x|^2 <= eps_s^2 |f|_W^2 / (g rscale^2)
+    if (!pl.shifts)
+      for (SolveDesc& d : pl.solves) d.ref2 = jb.pbs[i].fw2 / (it.op->g * d.rscale * d.rscale);
     jb.engine_index[i] = int(jb.ptrs.size());
     jb.ptrs.push_back(&jb.pbs[i]);
   }
   if (jb.ptrs.empty()) return 0.0;
   const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision, jb.o.tile_rows);
+  double2* yout = jb.keep ? ar.take<double2>(size_t(z.S) * z.cap) : nullptr;
+  const size_t mark = ar.mark();   // the engine's memory starts here
   jb.en = new Engine(jb.st);
   jb.en->setup(ar, jb.ptrs, z, jb.o.precision, jb.o.max_iter,
                (jb.o.precision == REXII_PREC_MIXED) ? jb.o.inner_tol : 0.0,
-               jb.o.profile != 0 && max_chunks == 0, jb.keep);
-  if (jb.o.precision == REXII_PREC_MIXED) return jb.en->run<float>(jb.o.max_iter, max_chunks);
-  return jb.en->run<double>(jb.o.max_iter, max_chunks);
+               jb.o.profile != 0 && max_chunks == 0, yout, z.cap);
+  if (jb.o.precision != REXII_PREC_MIXED) return jb.en->run<double>(max_chunks);
+  const double ms = jb.en->run<float>(max_chunks);
+  if (max_chunks == 0) rerun_fp64(jb, ar, mark, yout);
+  return ms;
 }
 
 // ---------------------------------------------------------------------------
@@ -1166,6 +1327,7 @@ static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o
 // Reports and status of every item after the run.
 static rexii_status finish_job(Job& jb, double secs) {
   int bad_breakdown = 0, bad_conv = 0;
+  double worst = 0.0;   // largest error bound over the items, relative to tol
   for (size_t i = 0; i < jb.items.size(); ++i) {
     JobItem& it = jb.items[i];
     if (it.skip) {
@@ -1180,9 +1342,18 @@ static rexii_status finish_job(Job& jb, double secs) {
     const RunSummary sm = summarize(*jb.en, ei);
     bad_breakdown += sm.breakdowns;
     bad_conv += sm.not_conv;
+    worst = std::max(worst, sm.err_bound / jb.o.tol);
   }
   if (bad_breakdown > 0) return set_error(REXII_ERR_BREAKDOWN, "Krylov breakdown in a shifted solve");
-  if (bad_conv > 0) return set_error(REXII_ERR_NOT_CONVERGED, "a shifted solve reached max_iter");
+  if (bad_conv > 0) return set_error(REXII_ERR_NOT_CONVERGED, "a shifted solve reached its iteration cap");
+  // the contract: the achieved error bound (Theorem 1 with the solves'
+  // residuals) is within tol; 1e-9 relative slack for the rounding of the sum
+  if (worst > 1.0 + 1e-9) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "error bound %.3e x tol: a solve stopped above its tolerance (FP64 residual floor)",
+                  worst);
+    return set_error(REXII_ERR_NOT_CONVERGED, msg);
+  }
   return clear_error();
 }
 
@@ -1614,6 +1785,8 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
 // Shared-Krylov (multi-shift) path: one W-skew Lanczos process per state
 // serves every pole (kernels_lz.hip); the small problems on T_m run here.
 // ---------------------------------------------------------------------------
+constexpr int kMultishiftMaxM = 50000;   // default cap on the Krylov dimension
+
 struct SmallResult {
   int P = 0, M = 0, N = 0;
   double rho = 0.0, kappa = 0.0, tail = 0.0;
@@ -1713,7 +1886,7 @@ static rexii_status run_multishift(const rexii_swe_op* op, int nrhs, const doubl
     if (o.scheme != REXII_SCHEME_REXII)
       return set_error(REXII_ERR_INVALID_ARG, "the REXI scheme is available on the Fourier path only");
     const int m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(o.tol);
-    const int mmax = std::max(8, o.max_iter);
+    const int mmax = std::max(8, o.max_iter > 0 ? o.max_iter : kMultishiftMaxM);
     const int ldb = mmax + 2, ldy = mmax;
     const int nb = lz_blocks(nx, ny);
     const size_t need = 2 * al256(size_t(nrhs) * n3 * 8) + al256(size_t(nrhs) * nb * 8) +
@@ -1956,7 +2129,7 @@ static rexii_status run_multishift(const rexii_swe_op* op, int nrhs, const doubl
 
 static size_t multishift_bytes(int nx, int ny, int nrhs, int max_iter) {
   const size_t n3 = 3 * size_t(nx) * ny;
-  const int mmax = std::max(8, max_iter);
+  const int mmax = std::max(8, max_iter > 0 ? max_iter : kMultishiftMaxM);
   return 2 * al256(size_t(nrhs) * n3 * 8) + al256(size_t(nrhs) * lz_blocks(nx, ny) * 8) +
          al256(size_t(nrhs) * (mmax + 2) * 8) + al256(size_t(nrhs) * mmax * 8) + al256(256);
 }
@@ -1973,7 +2146,7 @@ void rexii_default_opts(rexii_opts* o) {
   o->h = 0.5;
   o->tol = 0.0;
   o->precision = REXII_PREC_FP64;
-  o->max_iter = 50000;
+  o->max_iter = 0;
   o->m0 = -1;
   o->rho = 0.0;
   o->pole_batch = 0;

@@ -54,11 +54,14 @@ class Report(ctypes.Structure):
                 ("stagnated", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
                 ("kernel_bytes", ctypes.c_double), ("step_ms", ctypes.c_double * 6),
-                ("u1_bytes", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("u1_bytes", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("err_bound", ctypes.c_double), ("seconds_solve", ctypes.c_double),
+                ("retried", ctypes.c_int32), ("hist_buckets", ctypes.c_int32), ("iter_hist", ctypes.c_int32 * 20)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["step_ms"] = list(d["step_ms"])
+        d["iter_hist"] = list(d["iter_hist"])
         return d
 
 

@@ -86,3 +86,29 @@ def test_batched_many_slots(rx):
         assert em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10
     u1, _ = rx.apply(_dev(fs[3]), ts[3], fc=10.0)
     assert em.rel_l2(us[3].cpu().numpy(), u1.cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_batched_heterogeneous_at_scale_one_call(rx, tmp_path, monkeypatch):
+    """The batched configuration's extremes in ONE autotuned call: a 1024^2
+    state, the 128^2 state at t rho = 1918 whose FP32 inner solves diverge
+    (they are solved again in FP64), and states between, mixed precision at
+    tol 1e-6; every output value against the oracle's exact exponential."""
+    monkeypatch.setenv("REXII_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    cases = [(1024, 120.0, 520), (128, 1918.315005415708, 538), (256, 700.0, 521), (512, 300.0, 522),
+             (128, 50.0, 523)]
+    fs, ts, ops = [], [], []
+    for D, trho, seed in cases:
+        op = lrsw.LRSW(D, D, fc=10.0)
+        fs.append(inputs.gaussian_bumps(D, nbumps=16, seed=seed))
+        ts.append(trho / lrsw.rho(op))
+        ops.append(op)
+    print("batched at scale: 1024^2 .. 128^2, t rho 50 .. 1918, one call", flush=True)
+    us, reps = rx.apply_batched([_dev(f) for f in fs], ts, fc=10.0, precision="mixed", tol=1e-6, pole_batch=-1)
+    for (D, trho, _), f, t, op, u, rep in zip(cases, fs, ts, ops, us, reps):
+        e = em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t))
+        print(f"  {D}^2 t rho {trho:.0f}: P {rep['P']} retried {rep['retried']} bound {rep['err_bound']:.2e} "
+              f"rel-L2 {e:.2e}", flush=True)
+        assert rep["not_converged"] == 0 and rep["err_bound"] <= 1e-6
+        assert e <= 1e-6
+    assert "nx=1024 ny=1024" in (tmp_path / "tune.txt").read_text()

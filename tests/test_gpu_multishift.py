@@ -50,7 +50,7 @@ def test_multishift_dense_depth_field(rx):
     print("multishift dense 16x12", flush=True)
     u, rep = rx.apply_multishift(_dev(f), t, g=1.0, fc=5.0, Hfield=_dev(Hf), tol=1e-10)
     ref = (scipy.linalg.expm(t * lrsw.dense_A(op)) @ f.ravel()).reshape(f.shape)
-    assert em.rel_l2(_host(u), ref) <= 1e-9
+    assert em.rel_l2(_host(u), ref) <= 1e-10
     assert 0 < rep["solves"] <= 3 * nx * ny + 1
 
 
@@ -63,8 +63,8 @@ def test_multishift_depth_field_vs_chebyshev(rx):
     print("multishift 96x72 t rho 100", flush=True)
     u, rep = rx.apply_multishift(_dev(f), t, g=1.0, fc=20.0, Hfield=_dev(Hf), tol=1e-10, profile=1)
     ref = varh.chebyshev_expm(op, f, t)
-    assert em.rel_l2(_host(u), ref) <= 1e-9
-    assert _wrel(op, _host(u), ref) <= 1e-9
+    assert em.rel_l2(_host(u), ref) <= 1e-10
+    assert _wrel(op, _host(u), ref) <= 1e-10
     # the bound on rho(T) never exceeds the guaranteed bound on rho(A)
     assert rep["rho"] <= lrsw.rho(op) * (1 + 1e-12)
     assert rep["max_rel_residual"] <= 1e-11
@@ -77,7 +77,7 @@ def test_multishift_constant_depth(rx, nx, ny, trho, fc):
     t = trho / lrsw.rho(op)
     f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=nx, velocity=True)
     u, _ = rx.apply_multishift(_dev(f), t, g=1.3, fc=fc, H=0.7, tol=1e-10)
-    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-9
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
 
 
 def test_multishift_batch_matches_single_calls(rx):
@@ -94,7 +94,7 @@ def test_multishift_batch_matches_single_calls(rx):
     for k in range(2):
         uk, _ = rx.apply_multishift(_dev(fs[k]), t, fc=20.0, Hfield=Hd, tol=1e-10)
         assert em.rel_l2(_host(ub[k]), _host(uk)) <= 1e-10
-        assert em.rel_l2(_host(ub[k]), varh.chebyshev_expm(op, fs[k], t)) <= 1e-9
+        assert em.rel_l2(_host(ub[k]), varh.chebyshev_expm(op, fs[k], t)) <= 1e-10
     assert rep["total_iters"] <= 2 * rep["solves"]
 
 
@@ -129,10 +129,13 @@ def test_multishift_edge_cases(rx):
     assert e.value.report["solves"] == 16
 
 
-@pytest.mark.parametrize("trho,bar", [(100.0, 1e-10), (5000.0, 1e-10)])
+@pytest.mark.parametrize("trho,bar", [(5000.0, 1e-10)])
 def test_multishift_full_size_against_samples(rx, trho, bar):
     # the 2048^2 depth-field workload (f_c = 20, state seed 50) at the size
     # the bench runs, against the oracle's stored Chebyshev-Bessel samples
+    # (t rho = 100 is compared over the whole field in test_gpu_varh; the
+    # series at t rho = 5000 takes ~20 minutes of CPU time, so its values are
+    # stored at 4096 points and the W-energy covers the whole field)
     import json
     import os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"varh2048_trho{int(trho)}.json")))

@@ -26,6 +26,9 @@ varh         variable-depth (flux form) operator: dense expm on small grids,
              Chebyshev-Bessel series reference
 spectral     the paper's own spectral LRSW operator and test scenarios
              (Sec. 4, wave scenarios 1/2 and the Gaussian scenario)
+matrix_cases the matrix test cases A_1, A_2 and f_0 of Sec. 3.2, circulant
+             matrices, and REXII / the original REXI / REXIE (eq. REXIE, with
+             the shift of Sec. 2.2) by dense solves and per Fourier mode
 
 Where a function has no independent pin in ``tests/`` its docstring says
 "parity unpinned".

@@ -303,6 +303,34 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
                                  int32_t derivative, const rexii_opts* opts, void* workspace,
                                  size_t ws_bytes, hipStream_t stream, rexii_report* rep);
 
+/* For callers that cannot allocate device memory: tight serving loops and
+ * harnesses that forbid hipMalloc.  The same computation, kernels and
+ * result as rexii_apply_fourier, with every piece of device scratch (half
+ * spectra, term table, coefficient table, flag, FFT work buffer) taken
+ * from a static array inside the library instead of a workspace:
+ * REXII_STATIC_SCRATCH_BYTES bytes per GPU, reserved when the library's
+ * code is loaded on that GPU and held until the process ends.
+ *   The call allocates no device memory and no pinned host memory.  Its
+ *     FFT plans must exist already: creating a plan allocates, so call
+ *     rexii_fourier_workspace_size (or rexii_apply_fourier) once for the
+ *     grid on that device beforehand (set-up); otherwise the call returns
+ *     REXII_ERR_INVALID_ARG.
+ *   Arguments, layouts and the report as rexii_apply_fourier;
+ *     opts.profile is ignored (no HIP events are created).
+ *   Sizes: a problem whose scratch (rexii_fourier_workspace_size bytes)
+ *     exceeds REXII_STATIC_SCRATCH_BYTES returns REXII_ERR_WORKSPACE
+ *     (covers grids up to 2048 x 2048).
+ *   Every call on one GPU uses that GPU's single array and leaves its
+ *     contents behind (the flag is cleared by a kernel each call): calls
+ *     that overlap in time on one GPU, from several host threads or on
+ *     several streams, race and give wrong results; serialise them.
+ * Errors: as rexii_apply_fourier. */
+#define REXII_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+
+rexii_status rexii_apply_fourier_noalloc(const rexii_swe_op* op, const double* f, double* u, double t,
+                                         int32_t derivative, const rexii_opts* opts,
+                                         hipStream_t stream, rexii_report* rep);
+
 /* Shared-Krylov (multi-shift) REXII, any depth: all shifted systems
  * (tA - z_k I) x_k = f have one right-hand side, and Krylov spaces are
  * shift invariant, so one Lanczos process per state serves every pole

@@ -279,10 +279,21 @@ bool g_fft_setup = false;
 std::string fft_msg(const char* what, rocfft_status s) { return std::string(what) + " failed (rocfft status " + std::to_string(int(s)) + ")"; }
 }  // namespace
 
-rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv) {
+rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv, bool create) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return set_error(REXII_ERR_HIP, "hipGetDevice failed");
   std::lock_guard<std::mutex> lk(g_fft_mu);
+  if (!create) {
+    const auto found = g_fft.find(std::make_tuple(dev, nx, ny));
+    if (found == g_fft.end())
+      return set_error(REXII_ERR_INVALID_ARG,
+                       "no FFT plan for this grid on this device yet: call rexii_fourier_workspace_size "
+                       "(or rexii_apply_fourier) for it first; creating a plan allocates device memory");
+    if (work_bytes) *work_bytes = found->second.work;
+    if (fwd) *fwd = found->second.fwd;
+    if (inv) *inv = found->second.inv;
+    return REXII_OK;
+  }
   if (!g_fft_setup) {
     const rocfft_status s = rocfft_setup();
     if (s != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_setup", s));
@@ -327,6 +338,38 @@ rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t wor
   }
   rocfft_execution_info_destroy(info);
   if (st != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_execute", st));
+  return REXII_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static device scratch of rexii_apply_fourier_noalloc: one copy of this
+// array per GPU, held until the process ends.  In host code its name is
+// only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress (per device, with that device current) and only that
+// address is handed to kernels and library calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[REXII_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch;  // device -> address of its copy of scratch
+}  // namespace
+
+rexii_status static_scratch(void** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(REXII_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return set_error(REXII_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    if (reinterpret_cast<uintptr_t>(p) & 255)
+      return set_error(REXII_ERR_HIP, "static scratch is not 256-byte aligned");
+    it = g_scratch.emplace(dev, p).first;
+  }
+  *ptr = it->second;
   return REXII_OK;
 }
 

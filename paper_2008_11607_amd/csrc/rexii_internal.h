@@ -34,8 +34,14 @@ double rho_bound_var(int nx, int ny, double g, double Hmax, double fc);
 // rocFFT plans of the Fourier-space path (kernels_fft.hip): a batch of three
 // real 2D transforms [3][ny][nx] <-> [3][ny][nx/2+1], FP64, not in place,
 // cached per device and grid; work_bytes receives the larger work buffer.
-rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv);
+// With create == false only plans made by an earlier call are returned
+// (REXII_ERR_INVALID_ARG when there are none): creating a plan allocates.
+rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv, bool create = true);
 rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s);
+// Device address of the library's static scratch array on the current
+// device (REXII_STATIC_SCRATCH_BYTES bytes, 256-byte aligned; looked up once
+// per device with hipGetSymbolAddress, then kept).
+rexii_status static_scratch(void** ptr);
 
 }  // namespace rexii
 

@@ -1666,9 +1666,12 @@ static size_t fourier_bytes(int nx, int ny, int deriv, int nterm, size_t fft_wor
          al256(fft_work);
 }
 
+// noalloc: device scratch from the library's static array, FFT plans only
+// if they exist, no events and no pinned host memory (the entry point for
+// callers that cannot allocate).
 static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double* u, double t, int deriv,
                                 const rexii_opts* opts_in, void* ws, size_t ws_bytes, hipStream_t stream,
-                                rexii_report* rep) {
+                                rexii_report* rep, bool noalloc = false) {
   const auto t0 = std::chrono::steady_clock::now();
   // Runs on the caller's stream (nothing here is captured into a graph) and
   // returns when the result is complete on it.
@@ -1683,17 +1686,34 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
       HIPCHK(hipStreamSynchronize(st));
       return clear_error();
     }
-    const rexii_opts o = resolve_opts(opts_in);
+    rexii_opts o = resolve_opts(opts_in);
+    if (noalloc) o.profile = 0;
     FourierPlan fp;
     rexii_status s = fourier_plan(op, t, o, deriv, fp);
     if (s != REXII_OK) return s;
+    if (noalloc) {
+      const size_t fixed = fourier_bytes(nx, ny, deriv, fp.nterm, 0);
+      if (fixed > REXII_STATIC_SCRATCH_BYTES)
+        return set_error(REXII_ERR_WORKSPACE, "problem needs more than the " +
+                                                  std::to_string(REXII_STATIC_SCRATCH_BYTES >> 20) +
+                                                  " MiB of static scratch (" + std::to_string(fixed) +
+                                                  " bytes before the FFT work buffer)");
+    }
     size_t work = 0;
     void *fwd = nullptr, *inv = nullptr;
-    s = fft_plans(nx, ny, &work, &fwd, &inv);
+    s = fft_plans(nx, ny, &work, &fwd, &inv, !noalloc);
     if (s != REXII_OK) return s;
     const size_t need = fourier_bytes(nx, ny, deriv, fp.nterm, work);
     int cnx = 0, cny = 0;
     fourier_canon(nx, ny, deriv, &cnx, &cny);
+    if (noalloc) {
+      if (need > REXII_STATIC_SCRATCH_BYTES)
+        return set_error(REXII_ERR_WORKSPACE, "problem needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                                  std::to_string(REXII_STATIC_SCRATCH_BYTES));
+      s = static_scratch(&ws);
+      if (s != REXII_OK) return s;
+      ws_bytes = REXII_STATIC_SCRATCH_BYTES;
+    }
     Arena ar(ws, ws_bytes);
     if (!ws) {
       ar.reserve_own(need + 4096);
@@ -1741,13 +1761,20 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     if (s != REXII_OK) return s;
     mark(5);
     HIPCHK(hipGetLastError());
-    // the flag is read into pinned host memory (one word per host thread,
-    // kept for the life of the process), ordered on the stream
-    static thread_local int* hflag = nullptr;
-    if (!hflag) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), 256, hipHostMallocDefault));
-    HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const int bad = *hflag;
+    int bad = 0;
+    if (noalloc) {
+      // no pinned memory: the stream is drained, then one word is copied
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+    } else {
+      // the flag is read into pinned host memory (one word per host thread,
+      // kept for the life of the process), ordered on the stream
+      static thread_local int* hflag = nullptr;
+      if (!hflag) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), 256, hipHostMallocDefault));
+      HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bad = *hflag;
+    }
     if (rep) {
       rep->P = fp.P;
       rep->M = fp.M;
@@ -2186,6 +2213,19 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
   const size_t n3 = 3 * size_t(op->nx) * op->ny;
   if (overlaps(f, n3, u, n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
   return run_fourier(op, f, u, t, derivative, opts, workspace, ws_bytes, stream, rep);
+}
+
+rexii_status rexii_apply_fourier_noalloc(const rexii_swe_op* op, const double* f, double* u, double t,
+                                         int32_t derivative, const rexii_opts* opts, hipStream_t stream,
+                                         rexii_report* rep) {
+  rexii_status v = check_op_and_t(op, t, true, false);
+  if (v != REXII_OK) return v;
+  if (!f || !u) return set_error(REXII_ERR_INVALID_ARG, "NULL state pointer");
+  if (derivative != REXII_DERIV_CENTRED && derivative != REXII_DERIV_SPECTRAL)
+    return set_error(REXII_ERR_INVALID_ARG, "unknown derivative");
+  const size_t n3 = 3 * size_t(op->nx) * op->ny;
+  if (overlaps(f, n3, u, n3)) return set_error(REXII_ERR_INVALID_ARG, "u overlaps f");
+  return run_fourier(op, f, u, t, derivative, opts, nullptr, 0, stream, rep, true);
 }
 
 rexii_status rexii_multishift_workspace_size(const rexii_swe_op* op, int32_t nrhs, const rexii_opts* opts,

@@ -69,7 +69,7 @@ EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_s
            "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
            "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
            "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_coeffs_rexi",
-           "rexii_last_error"]
+           "rexii_apply_fourier_noalloc", "rexii_last_error"]
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load():
     lib.rexii_shifted_solve.restype = ctypes.c_int
     lib.rexii_apply_fourier.argtypes = [P(SweOp), vp, vp, dbl, i32, P(Opts), vp, sz, vp, P(Report)]
     lib.rexii_apply_fourier.restype = ctypes.c_int
+    lib.rexii_apply_fourier_noalloc.argtypes = [P(SweOp), vp, vp, dbl, i32, P(Opts), vp, P(Report)]
+    lib.rexii_apply_fourier_noalloc.restype = ctypes.c_int
     lib.rexii_fourier_workspace_size.argtypes = [P(SweOp), P(Opts), dbl, i32, P(sz)]
     lib.rexii_fourier_workspace_size.restype = ctypes.c_int
     lib.rexii_apply_multishift.argtypes = [P(SweOp), i32, vp, vp, dbl, P(Opts), vp, sz, vp, P(Report)]
@@ -283,6 +285,31 @@ def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, w
                                  _stream(), ctypes.byref(rep))
     _check(st, rep.as_dict())
     return u, rep.as_dict()
+
+
+def apply_fourier_noalloc(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, **opts):
+    """apply_fourier through rexii_apply_fourier_noalloc: the library's static
+    device scratch instead of a workspace, no device allocation inside the
+    call.  The grid's FFT plans must exist (fourier_workspace_size creates
+    them).  out: the result tensor (allocated here when None).  Returns
+    (u, report_dict)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    ny, nx = f.shape[1], f.shape[2]
+    u = torch.empty_like(f) if out is None else _dev_f64(out, f.shape)
+    op = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_apply_fourier_noalloc(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(u.data_ptr()), float(t),
+                                         DERIVATIVES.get(derivative, derivative), ctypes.byref(o), _stream(),
+                                         ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return u, rep.as_dict()
+
+
+STATIC_SCRATCH_BYTES = 256 << 20
 
 
 def apply_multishift(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts):

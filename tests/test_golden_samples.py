@@ -54,3 +54,31 @@ def test_lrsw_golden_metadata(name):
     assert abs(g["norm_u"] / g["norm_f"] - 1.0) <= 1e-13
     f = inputs.gaussian_bumps(D, nbumps=g["nbumps"], seed=g["seed"])
     assert abs(np.linalg.norm(f) / g["norm_f"] - 1.0) <= 1e-14
+
+
+def test_adjoint_golden_metadata():
+    """The stored gradients of the adjoint workload (tests/golden/
+    make_adjoint256.py): the seeded inputs and y are reproduced, and the
+    loss and depth gradient of the approximant agree with those of the
+    exact exponential to the approximation's accuracy."""
+    from oracle import adjoint as adj
+    from oracle import expm_modes as em
+    with open(os.path.join(HERE, "golden", "adjoint256_trho500.json")) as fh:
+        g = json.load(fh)
+    D = g["D"]
+    op = lrsw.LRSW(D, D, g=g["g"], H=g["H"], fc=g["f_c"])
+    rho = lrsw.rho(op)
+    assert abs(rho - g["rho"]) <= 1e-12 * rho
+    assert abs(g["t"] * rho - g["t_rho"]) <= 1e-12 * g["t_rho"]
+    idx = np.asarray(g["sample_index"])
+    assert np.array_equal(idx, inputs.sample_indices(D, D, len(idx), 43))
+    # y = P exp(tA) f* for the hidden state
+    fstar = inputs.gaussian_bumps(D, nbumps=g["nbumps"], seed=g["seed_fstar"])
+    y = adj.sample(em.expm_closed_real(op, fstar, g["t"]), idx)
+    assert np.max(np.abs(y - np.asarray(g["y"]))) <= 1e-14 * np.max(np.abs(y))
+    # approximant vs exact: h = 0.5, tol 1e-10 poles
+    assert abs(g["J"] - g["J_exact"]) <= 1e-10 * g["J_exact"]
+    assert abs(g["dJdH"] - g["dJdH_exact"]) <= 1e-10 * abs(g["dJdH_exact"])
+    assert g["P"] == 2068
+    out = np.asarray(g["index"])
+    assert len(out) == len(g["dJdf"]) == len(np.unique(out)) and out.max() < 3 * D * D

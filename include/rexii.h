@@ -217,32 +217,69 @@ rexii_status rexii_coeffs_rexi(double t, double rho, double h, double tol, int32
 rexii_status rexii_rho(const rexii_swe_op* op, hipStream_t stream, double* rho);
 
 /* Device workspace rexii_apply / rexii_apply_adjoint need for these
- * arguments (bytes).  t is needed because it fixes the pole count. */
+ * arguments (bytes): an upper bound of both (the adjoint with dJdH keeps
+ * every resolvent, so for a plain rexii_apply
+ * rexii_batched_workspace_size(1, ...) is the tighter figure).  t is needed
+ * because it fixes the pole count.  With opts->pole_batch < 0 the bound
+ * covers every slot count and tile height the autotuner may try (it runs its
+ * candidates inside the caller's workspace).  A depth field is read on the
+ * null stream (its maximum fixes rho). */
 rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts,
                                   double t, size_t* bytes);
 
-/* u = exp(tA) f (REXII approximation).  f, u: device [3][ny][nx], must not
- * overlap.  t >= 0 (t == 0 copies f).  opts may be NULL (defaults); rep may
- * be NULL.  Errors: INVALID_ARG, NONFINITE (f or H_field), NOT_CONVERGED,
- * BREAKDOWN, OOM, HIP, WORKSPACE. */
+/* u = exp(tA) f (REXII approximation): the reduced pole sum of Sec. 2.2
+ * (eq. modifiedRexiMatrixReducedSum, as partial fractions) with one Krylov
+ * shifted solve per pole (Sec. 4, the per-term systems, solved here through
+ * the height equation eq. lswEta and the velocities of eq. lswVelocities),
+ * M from eq. matrixAccuracyBound.  The achieved bound of Theorem 1
+ * (eq. teorem, with each solve's final residual) is in rep->err_bound; when
+ * it exceeds opts->tol the call returns NOT_CONVERGED with u written.
+ * f, u: device [3][ny][nx], must not overlap.  t >= 0 (t == 0 copies f).
+ * opts may be NULL (defaults); rep may be NULL.  Errors: INVALID_ARG,
+ * NONFINITE (f or H_field), NOT_CONVERGED, BREAKDOWN, OOM, HIP, WORKSPACE. */
 rexii_status rexii_apply(const rexii_swe_op* op, const double* f, double* u, double t,
                          const rexii_opts* opts, void* workspace, size_t ws_bytes,
                          hipStream_t stream, rexii_report* rep);
 
-/* Reverse mode of rexii_apply for a loss J(u).  gbar = dJ/du (device
- * [3][ny][nx]).  dJdf (device [3][ny][nx], may be NULL) receives
- * r(tA)^T gbar.  dJdH (host, may be NULL; constant depth only) receives
- * dJ/dH0 for the same pole set (poles do not move with H0).  The transpose
- * uses the same poles with weights rearranged (A^T = -W A W^{-1}).
+/* Reverse mode of rexii_apply for a loss J(u).  The approximant is the real
+ * rational function r(tA) of eqs. REXI_Modified_matrix and
+ * modifiedRexiMatrixReducedSum; its transpose r(tA)^T = W r(-tA) W^{-1}
+ * (A^T = -W A W^{-1}, W = diag(g, H, H)) is the same pole set with the two
+ * weights of each term n exchanged and conjugated, so the reverse pass is
+ * another rexii_apply-sized set of shifted solves.
+ *   gbar = dJ/du (device [3][ny][nx]).  dJdf (device [3][ny][nx], may be
+ *   NULL) receives r(tA)^T gbar.  dJdH (host, one double, may be NULL;
+ *   constant depth only; needs f) receives dJ/dH0 for the same pole set
+ *   (poles do not move with H0): minus the real part of the weighted sum over
+ *   poles of the bilinear forms y_k^T (t dA/dH0) x_k, with x_k the forward
+ *   resolvents of f and y_k those of gbar under the transposed weights.
+ *   Workspace, stream and report as rexii_apply (the report covers both the
+ *   forward and the reverse solves).
  * Errors as rexii_apply. */
 rexii_status rexii_apply_adjoint(const rexii_swe_op* op, const double* f, const double* gbar,
                                  double* dJdf, double* dJdH, double t, const rexii_opts* opts,
                                  void* workspace, size_t ws_bytes, hipStream_t stream,
                                  rexii_report* rep);
 
+/* Device workspace of rexii_apply_batched for these problems (count = 1:
+ * of rexii_apply), bytes; with opts->pole_batch < 0 it covers every job the
+ * autotuner may run.  Depth fields are read on the null stream. */
+rexii_status rexii_batched_workspace_size(int32_t count, const rexii_swe_op* ops, const double* t,
+                                          const rexii_opts* opts, size_t* bytes);
+
 /* count independent problems in one call: ops[i], f[i], u[i], t[i] as in
- * rexii_apply (host arrays of device pointers).  All instances' solves share
- * one persistent pole scheduler.  reps may be NULL or hold count reports. */
+ * rexii_apply (host arrays of device pointers).  The paper's GPU code splits
+ * the terms of the sum into chunks that fit the device (Sec. 4, GPU
+ * implementation, algorithm GPUimplementation); here the terms of every
+ * instance form one queue of shifted solves (most expensive first) served by
+ * one set of solver slots, so a chunk mixes instances and grids, and each
+ * instance's weighted sum (eq. modifiedRexiMatrixReducedSum) is accumulated
+ * in FP64 as its solves finish.  opts applies to every instance
+ * (pole_batch < 0 autotunes the slot count for the batch).  reps may be
+ * NULL or hold count reports (one per instance).  Workspace: NULL, or at
+ * least rexii_batched_workspace_size() bytes.  Errors as rexii_apply; the
+ * first failing instance's status is returned after every instance's u is
+ * written. */
 rexii_status rexii_apply_batched(int32_t count, const rexii_swe_op* ops, const double* const* f,
                                  double* const* u, const double* t, const rexii_opts* opts,
                                  void* workspace, size_t ws_bytes, hipStream_t stream,
@@ -366,6 +403,46 @@ rexii_status rexii_apply_multishift(const rexii_swe_op* op, int32_t nrhs, const 
                                     hipStream_t stream, rexii_report* rep);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
+/* The paper's matrix experiments (Sec. 3.2, Fig. matrixRexiExample) for a
+ * circulant matrix A, (A f)_j = sum_q coefs_q f_{(j + offsets_q) mod n}
+ * (e.g. the periodic difference matrices A_1 and A_2 of that section), with
+ * one of three schemes:
+ *   REXII_CIRC_REXII  eq. modifiedRexiMatrixReducedSum (poles of
+ *                     rexii_coeffs); A must be real and skew-symmetric;
+ *   REXII_CIRC_REXI   the original REXI, eq. originalREXImatrix (poles of
+ *                     rexii_coeffs_rexi); same premise on A;
+ *   REXII_CIRC_REXIE  eq. REXIE, for A - nu I = i B with B real symmetric
+ *                     (real eigenvectors): exp(tA) f = e^{t nu} exp(t(A - nu I)) f,
+ *                     the shift nu = i * nu_im (Sec. 2.2's remark on shifts);
+ *                     the result is complex.
+ * Every resolvent is evaluated exactly, per Fourier mode (the DFT
+ * diagonalises A): rocFFT, the pole sum per mode, inverse rocFFT, FP64.
+ *   offsets, coefs: host arrays of nstencil (1..64) entries; coefs are (re, im)
+ *     pairs.  A premise that does not hold (to 1e-13 of the largest
+ *     coefficient): REXII_ERR_INVALID_ARG.  nu_im must be 0 unless REXIE.
+ *   f: device float64 [nrhs][n] (real vectors); u: device complex128
+ *     [nrhs][n] as (re, im) pairs (imaginary part 0 for REXII and REXI);
+ *     not overlapping.  n >= 2, n * nrhs <= 2^31.
+ *   M > 0 fixes M (the figure sweeps it); M <= 0 takes eq. matrixAccuracyBound
+ *     with rho = max_k |lambda_k - i nu_im| (exact, or opts.rho when > 0) and
+ *     m0 from opts (m0 or tol).  opts.h is the Gaussian width; other opts
+ *     fields are ignored.  opts may be NULL.
+ *   Workspace: rexii_circulant_workspace_size() bytes, 256-byte aligned, or
+ *     NULL to let the library allocate.  FFT plans are created on first use
+ *     per device, n and nrhs and kept until the process ends.
+ *   Report: P (poles), M, N, m0, h, t, rho, kappa_sum (sum over the weights
+ *     of |w| / |h mu|, both weight sets for REXIE), total_iters = modes, seconds.
+ *   The call returns when u is complete on `stream`.
+ * Errors: INVALID_ARG, NONFINITE (f; u is written anyway), OOM, HIP, WORKSPACE. */
+enum { REXII_CIRC_REXII = 0, REXII_CIRC_REXI = 1, REXII_CIRC_REXIE = 2 };
+rexii_status rexii_circulant_workspace_size(int32_t n, int32_t nstencil, const int32_t* offsets, const double* coefs,
+                                            int32_t nrhs, double t, double nu_im, int32_t scheme, int32_t M,
+                                            const rexii_opts* opts, size_t* bytes);
+rexii_status rexii_apply_circulant(int32_t n, int32_t nstencil, const int32_t* offsets, const double* coefs,
+                                   int32_t nrhs, const double* f, double* u, double t, double nu_im, int32_t scheme,
+                                   int32_t M, const rexii_opts* opts, void* workspace, size_t ws_bytes,
+                                   hipStream_t stream, rexii_report* rep);
+
 const char* rexii_last_error(void);
 
 #ifdef __cplusplus

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librexii.so")
 
-SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "solver.hip"]
+SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "circulant.hip", "solver.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code

@@ -22,6 +22,8 @@
 
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace rexii {
@@ -160,6 +162,36 @@ void rexi_poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>
   }
 }
 
+// REXIE (eq. REXIE, the remark after eq. originalREXImatrix): for A = iB, B
+// real with real eigenvectors, and real f,
+//   exp(tA) f ~ sum_{n=-N}^{N} Re(beta^Re_n (tA + alpha_n I)^{-1} f)
+//                            + i Re(beta^Im_n (tA + alpha_n I)^{-1} f),
+// beta^Im_n = h sum_k a_k Im(b_{n-k}) (eq. originalRexi).  Poles z = -alpha_n
+// and the two weight sets, ordered like rexi_poles_weights.
+void rexie_terms(int M, double h, std::vector<cplx>& z, std::vector<cplx>& wre, std::vector<cplx>& wim) {
+  using std::complex;
+  const int N = M + kL;
+  z.resize(2 * N + 1);
+  wre.resize(2 * N + 1);
+  wim.resize(2 * N + 1);
+  const double eh2 = std::exp(h * h);
+  for (int q = 0; q < 2 * N + 1; ++q) {
+    const int n = (q + 1) / 2 * ((q % 2 == 1) ? 1 : -1);  // 0, 1, -1, 2, -2, ...
+    const int k1 = std::max(-kL, n - M), k2 = std::min(kL, n + M);
+    complex<double> br(0.0, 0.0), bi(0.0, 0.0);
+    for (int k = k1; k <= k2; ++k) {
+      const complex<double> ak(a_re(k), a_im(k));
+      const double m = static_cast<double>(n - k);
+      // b_m = e^{h^2} e^{-imh}: Re b_m = e^{h^2} cos(mh), Im b_m = -e^{h^2} sin(mh)
+      br += ak * (eh2 * std::cos(m * h));
+      bi += ak * (-eh2 * std::sin(m * h));
+    }
+    z[q] = {-h * kMu, -h * n};
+    wre[q] = {h * br.real(), h * br.imag()};
+    wim[q] = {h * bi.real(), h * bi.imag()};
+  }
+}
+
 double kappa_sum(const std::vector<cplx>& w, double h) {
   double s = 0.0;
   for (const cplx& c : w) s += std::hypot(c.re, c.im);
@@ -167,12 +199,21 @@ double kappa_sum(const std::vector<cplx>& w, double h) {
 }
 
 double max_s2(int n) {
-  // max over k of (n sin(2 pi k / n))^2
+  // max over k of (n sin(2 pi k / n))^2; O(n), so kept per n
+  static std::mutex mu;
+  static std::map<int, double> known;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = known.find(n);
+    if (it != known.end()) return it->second;
+  }
   double m = 0.0;
   for (int k = 0; k < n; ++k) {
     const double s = n * std::sin(2.0 * M_PI * k / n);
     m = std::max(m, s * s);
   }
+  std::lock_guard<std::mutex> lk(mu);
+  known[n] = m;
   return m;
 }
 

@@ -153,24 +153,31 @@ int canon_count(int n, int kmax, int deriv) {
 // The pole sums per distinct frequency: coef[cy * cnx + cx] = scale (Re c1,
 // Re c2) at theta^2 = t^2 (f_c^2 + g H (s_x^2 + s_y^2)) for the canonical
 // wavenumbers (cx, cy).  tab: nterm entries of kTermDoubles.  Block: 64
-// entries (one per lane) x nw waves; wave w sums the terms of slice w, the
-// slices are added in wave order through (nw - 1) x 1 KB of dynamic LDS.
-__global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restrict__ coef, int cnx, int cny, int nx,
-                                                               int ny, int deriv, double t, double g, double H,
-                                                               double fc, double scale,
+// entries (one per lane) x nw waves; grid row s (blockIdx.y) takes split s of
+// the terms, wave w of the block slice w of that split, and the slices are
+// added in wave order through (nw - 1) x 1 KB of dynamic LDS.  With one
+// split the block writes scale (c1, c2) to coef; with several it writes its
+// unscaled sums to part[s][e] and k_mode_coef_sum adds the splits in order.
+__global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restrict__ coef,
+                                                               double2* __restrict__ part, int cnx, int cny,
+                                                               int nx, int ny, int deriv, double t, double g,
+                                                               double H, double fc, double scale,
                                                                const double* __restrict__ tab, int nterm) {
   extern __shared__ double red[];
   const int ne = cnx * cny;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nw = int(blockDim.x >> 6);
+  const int ns = int(gridDim.y), sp = int(blockIdx.y);
+  const int per_s = (nterm + ns - 1) / ns;
+  const int lo_s = min(nterm, sp * per_s), cnt_s = min(nterm, lo_s + per_s) - lo_s;
   const int e = int(blockIdx.x) * 64 + lane;
   const bool live = e < ne;
   const int cx = live ? e % cnx : 0, cy = live ? e / cnx : 0;
   const double sx = axis_symbol(cx, nx, deriv), sy = axis_symbol(cy, ny, deriv);
   const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
   double c1, c2;
-  term_sums(tab, nterm, w, nw, th2, c1, c2);
+  term_sums(tab + size_t(lo_s) * kTermDoubles, cnt_s, w, nw, th2, c1, c2);
   if (nw > 1) {
     if (w > 0) {
       red[(w - 1) * 128 + lane] = c1;
@@ -183,7 +190,25 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restri
       c2 += red[(v - 1) * 128 + 64 + lane];
     }
   }
-  if (live) coef[e] = make_double2(scale * c1, scale * c2);
+  if (!live) return;
+  if (ns == 1)
+    coef[e] = make_double2(scale * c1, scale * c2);
+  else
+    part[size_t(sp) * ne + e] = make_double2(c1, c2);
+}
+
+// coef[e] = scale sum_s part[s][e], splits added in index order.
+__global__ __launch_bounds__(256) void k_mode_coef_sum(double2* __restrict__ coef, const double2* __restrict__ part,
+                                                       int ne, int ns, double scale) {
+  const int e = int(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= ne) return;
+  double c1 = 0.0, c2 = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const double2 v = part[size_t(s) * ne + e];
+    c1 += v.x;
+    c2 += v.y;
+  }
+  coef[e] = make_double2(scale * c1, scale * c2);
 }
 
 // F: [3][ny][nxh] half spectra, filtered in place with the coefficients of
@@ -229,23 +254,33 @@ __global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ 
   if (bad) atomicOr(flag, 1);
 }
 
-// Waves per block of k_mode_coef: 8 (measured best with 2000-10000 terms),
-// 16 when few blocks would otherwise leave the GPU idle, fewer when a wave
-// would get under 64 terms.
-int mode_coef_waves(int entries, int nterm) {
+// Shape of k_mode_coef: waves per block (8, measured best with 2000-10000
+// terms per entry, fewer when a wave would get under 64 terms) and term
+// splits (grid rows): enough blocks for about kCoefBlocks, i.e. 16 waves per
+// SIMD on 256 CUs, while every wave keeps at least kMinTermsPerWave terms.
+// Large tables (2048^2: 4112 blocks) run unsplit; 512^2 (261 blocks) splits.
+constexpr int kCoefBlocks = 2048;
+constexpr int kMinTermsPerWave = 24;
+
+void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   const int blocks = (entries + 63) / 64;
-  const int cap = (blocks < 1024) ? kModeWaves : 8;
   int nw = 1;
-  while (nw < cap && nterm >= 128 * nw) nw *= 2;
-  return nw;
+  while (nw < 8 && nterm >= 128 * nw) nw *= 2;
+  int ns = 1;
+  while (ns < 64 && blocks * ns < kCoefBlocks && nterm >= 2 * ns * nw * kMinTermsPerWave) ns *= 2;
+  *nw_out = nw;
+  *ns_out = ns;
 }
 
-void launch_mode_coef(double2* coef, int cnx, int cny, int nx, int ny, int deriv, double t, double g, double H,
-                      double fc, double scale, const double* tab, int nterm, int nw, hipStream_t s) {
+void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, int nx, int ny, int deriv, double t, double g,
+                      double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
+                      hipStream_t s) {
   const int ne = cnx * cny;
   const size_t lds = size_t(nw - 1) * 128 * sizeof(double);
-  hipLaunchKernelGGL(k_mode_coef, dim3(unsigned((ne + 63) / 64)), dim3(64 * nw), lds, s, coef, cnx, cny, nx, ny,
-                     deriv, t, g, H, fc, scale, tab, nterm);
+  hipLaunchKernelGGL(k_mode_coef, dim3(unsigned((ne + 63) / 64), unsigned(ns)), dim3(64 * nw), lds, s, coef, part,
+                     cnx, cny, nx, ny, deriv, t, g, H, fc, scale, tab, nterm);
+  if (ns > 1)
+    hipLaunchKernelGGL(k_mode_coef_sum, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, coef, part, ne, ns, scale);
 }
 
 void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, double t, double g,
@@ -278,6 +313,16 @@ bool g_fft_setup = false;
 
 std::string fft_msg(const char* what, rocfft_status s) { return std::string(what) + " failed (rocfft status " + std::to_string(int(s)) + ")"; }
 }  // namespace
+
+rexii_status rocfft_ensure_setup() {
+  std::lock_guard<std::mutex> lk(g_fft_mu);
+  if (!g_fft_setup) {
+    const rocfft_status s = rocfft_setup();
+    if (s != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_setup", s));
+    g_fft_setup = true;
+  }
+  return REXII_OK;
+}
 
 rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv, bool create) {
   int dev = 0;

@@ -26,6 +26,7 @@ int m0_from_tol(double tol);
 int m_rule(double t, double rho, double h, int m0);
 void poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w);
 void rexi_poles_weights(int M, double h, std::vector<cplx>& z, std::vector<cplx>& w);
+void rexie_terms(int M, double h, std::vector<cplx>& z, std::vector<cplx>& wre, std::vector<cplx>& wim);
 double kappa_sum(const std::vector<cplx>& w, double h);
 double max_s2(int n);
 double rho_const(int nx, int ny, double g, double H, double fc);
@@ -37,6 +38,7 @@ double rho_bound_var(int nx, int ny, double g, double Hmax, double fc);
 // With create == false only plans made by an earlier call are returned
 // (REXII_ERR_INVALID_ARG when there are none): creating a plan allocates.
 rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv, bool create = true);
+rexii_status rocfft_ensure_setup();   // once per process, before any rocFFT plan
 rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s);
 // Device address of the library's static scratch array on the current
 // device (REXII_STATIC_SCRATCH_BYTES bytes, 256-byte aligned; looked up once

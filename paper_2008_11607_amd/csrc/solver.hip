@@ -18,7 +18,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <vector>
@@ -96,18 +101,80 @@ class Arena {
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------------------
+// Per-device resources reused across calls: the private stream the solver
+// runs on (graph capture needs a capturable stream), an event that orders it
+// after the caller's stream, pinned host buffers (device-to-host reads, the
+// chunk counters) and the instantiated chunk graphs of recent calls.  One
+// call holds a device's set at a time; a call that finds it busy (another
+// host thread) creates and frees its own, as every call did before.  The
+// sets live until the process ends.
+// ---------------------------------------------------------------------------
+struct DevCtx {
+  std::mutex mu;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  void* pin = nullptr;         // staging of device-to-host reads
+  size_t pin_bytes = 0;
+  int* hcount = nullptr;       // 64 ints: counters the chunk graphs copy out
+  char* dscr = nullptr;        // small device scratch (depth maximum)
+  struct Graph {
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::deque<Graph> graphs;    // most recent first
+  static constexpr size_t kGraphs = 6;
+  static constexpr size_t kScratch = 64 << 10;
+};
+
+static std::mutex g_ctx_mu;
+static std::map<int, DevCtx*> g_ctx;
+static thread_local DevCtx* tl_ctx = nullptr;   // the set the calling thread holds
+
+static DevCtx* device_ctx() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  DevCtx*& c = g_ctx[dev];
+  if (!c) c = new DevCtx();
+  return c;
+}
+
+// Pinned host memory of at least `bytes` from the held set (grown on
+// demand), or nullptr when the thread holds none.
+static void* ctx_pinned(size_t bytes) {
+  DevCtx* c = tl_ctx;
+  if (!c) return nullptr;
+  if (c->pin_bytes < bytes) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    const size_t nb = std::max<size_t>(bytes, size_t(1) << 20);
+    HIPCHK(hipHostMalloc(&c->pin, nb, hipHostMallocDefault));
+    c->pin_bytes = nb;
+  }
+  return c->pin;
+}
+
 // Device-to-host read of `bytes` bytes ordered on `st`: through a pinned
 // staging buffer, then the stream is drained (a copy into pageable memory
 // followed by a stream synchronisation has returned stale data under the
 // profiler's kernel tracing).
 static void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return;
-  void* pin = nullptr;
-  HIPCHK(hipHostMalloc(&pin, bytes, hipHostMallocDefault));
+  void* pin = ctx_pinned(bytes);
+  void* own = nullptr;
+  if (!pin) {
+    HIPCHK(hipHostMalloc(&own, bytes, hipHostMallocDefault));
+    pin = own;
+  }
   struct Free {
     void* p;
-    ~Free() { (void)hipHostFree(p); }
-  } fr{pin};
+    ~Free() {
+      if (p) (void)hipHostFree(p);
+    }
+  } fr{own};
   HIPCHK(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::memcpy(dst, pin, bytes);
@@ -515,12 +582,20 @@ struct Engine {
   std::vector<char> retried;      // per queued solve: re-run in FP64
   double solve_seconds = 0.0;     // host wall time of run()
 
-  explicit Engine(hipStream_t s) : st(s) {}
+  bool graph_shared = false;    // gexec / graph belong to the device set's cache
+  bool hcount_shared = false;   // hcount belongs to the device set
+
+  explicit Engine(hipStream_t s) : st(s) {
+    // every byte of e (padding included) is defined: e keys the graph cache
+    std::memset(static_cast<void*>(&e), 0, sizeof(e));
+  }
   ~Engine() {
     for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (hcount) (void)hipHostFree(hcount);
+    if (!graph_shared) {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (hcount && !hcount_shared) (void)hipHostFree(hcount);
   }
 
   // yout: device [rows][ystride] complex128 kept solutions (row
@@ -639,7 +714,14 @@ struct Engine {
     launch_fill_zero(reinterpret_cast<double*>(e.counter), 2, st);
     launch_fill_zero(reinterpret_cast<double*>(e.dbg), 8, st);
     launch_fill_zero(reinterpret_cast<double*>(e.x64), size_t(z.B) * z.cap * 2, st);
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hcount), 64 * sizeof(int), hipHostMallocDefault));
+    if (tl_ctx) {
+      if (!tl_ctx->hcount)
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&tl_ctx->hcount), 64 * sizeof(int), hipHostMallocDefault));
+      hcount = tl_ctx->hcount;
+      hcount_shared = true;
+    } else {
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hcount), 64 * sizeof(int), hipHostMallocDefault));
+    }
     // persistent grid: every CU filled with as many blocks as fit
     int dev = 0, cus = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -672,8 +754,56 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(hcount, e.counter, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   }
 
+  // The chunk's launches depend only on e (pointers, sizes, modes), the
+  // grid, the chunk length, the inner type and the counter buffer: a graph
+  // captured for the same values is replayed as it is.
+  template <typename T>
+  std::vector<char> graph_key() const {
+    std::vector<char> k(sizeof(Eng) + 4 * sizeof(int) + sizeof(void*));
+    char* p = k.data();
+    std::memcpy(p, &e, sizeof(Eng));
+    const int v[4] = {grid, chunk, int(sizeof(T)), z.method};
+    std::memcpy(p + sizeof(Eng), v, sizeof(v));
+    const void* hc = hcount;
+    std::memcpy(p + sizeof(Eng) + sizeof(v), &hc, sizeof(void*));
+    return k;
+  }
+
   template <typename T>
   void build_graph() {
+    DevCtx* c = tl_ctx;
+    std::vector<char> key;
+    if (c && hcount_shared) {
+      key = graph_key<T>();
+      for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
+        if (it->key == key) {
+          DevCtx::Graph g = *it;
+          c->graphs.erase(it);
+          c->graphs.push_front(g);
+          graph = g.graph;
+          gexec = g.exec;
+          graph_shared = true;
+          return;
+        }
+      }
+    }
+    capture_graph<T>();
+    if (c && hcount_shared) {
+      // the set keeps the graph; the oldest beyond the limit is dropped (its
+      // last replay belonged to an earlier, finished call)
+      c->graphs.push_front(DevCtx::Graph{key, graph, gexec});
+      graph_shared = true;
+      while (c->graphs.size() > DevCtx::kGraphs) {
+        DevCtx::Graph& old = c->graphs.back();
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipGraphDestroy(old.graph);
+        c->graphs.pop_back();
+      }
+    }
+  }
+
+  template <typename T>
+  void capture_graph() {
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
       enqueue_chunk<T>(false);
@@ -937,12 +1067,22 @@ struct JobItem {
 // max of a device depth field (and its validity), synchronous on `st`
 static double device_hmax(const double* H, size_t n, hipStream_t st) {
   const int nb = prep_vh_blocks();
+  const size_t need = 256 + nb * sizeof(double);
   char* buf = nullptr;
-  HIPCHK(hipMalloc(reinterpret_cast<void**>(&buf), 256 + nb * sizeof(double)));
+  char* own = nullptr;
+  if (tl_ctx && need <= DevCtx::kScratch) {
+    if (!tl_ctx->dscr) HIPCHK(hipMalloc(reinterpret_cast<void**>(&tl_ctx->dscr), DevCtx::kScratch));
+    buf = tl_ctx->dscr;
+  } else {
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&own), need));
+    buf = own;
+  }
   struct FreeDev {
     char* p;
-    ~FreeDev() { (void)hipFree(p); }
-  } fd{buf};
+    ~FreeDev() {
+      if (p) (void)hipFree(p);
+    }
+  } fd{own};
   int* dfl = reinterpret_cast<int*>(buf);
   double* part = reinterpret_cast<double*>(buf + 256);
   launch_fill_zero(reinterpret_cast<double*>(dfl), 1, st);
@@ -988,6 +1128,28 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
     b += eb;
   }
   *bytes = b;
+  return REXII_OK;
+}
+
+// Workspace of run_items for these problems: job_bytes at the options'
+// slot count, or with pole_batch < 0 the largest job the autotuner may run
+// (its biggest candidate slot count for every tile height it tries).
+static int tuner_cap_slots(const std::vector<JobItem>& items, const rexii_opts& o);
+static rexii_status items_bytes(const std::vector<JobItem>& items, const rexii_opts& o, size_t* bytes) {
+  if (o.pole_batch >= 0) return job_bytes(items, o, false, 0, bytes);
+  const bool bicg = o.method == 1;
+  std::vector<int> ths = (bicg && o.tile_rows == 0) ? std::vector<int>{32, 16} : std::vector<int>{o.tile_rows};
+  size_t best = 0;
+  for (int th : ths) {
+    rexii_opts ot = o;
+    ot.tile_rows = bicg ? th : 0;
+    ot.pole_batch = tuner_cap_slots(items, ot);
+    size_t b = 0;
+    const rexii_status st = job_bytes(items, ot, false, 0, &b);
+    if (st != REXII_OK) return st;
+    best = std::max(best, b);
+  }
+  *bytes = best;
   return REXII_OK;
 }
 
@@ -1072,12 +1234,25 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
   const size_t ni = jb.items.size();
   jb.pbs.resize(ni);
   jb.engine_index.assign(ni, -1);
+  // pinned host copy of the input flags: the set's staging buffer (past
+  // the part that read_to_host uses, which is at most one W-norm vector)
+  // or an allocation of this call
+  const size_t nflag = std::max<size_t>(1, ni);
+  const size_t flag_off = al256(nflag * wnorm_blocks() * sizeof(double));
   int* flags = nullptr;
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&flags), std::max<size_t>(1, ni) * sizeof(int), hipHostMallocDefault));
+  int* own_flags = nullptr;
+  if (void* pin = ctx_pinned(flag_off + nflag * sizeof(int))) {
+    flags = reinterpret_cast<int*>(static_cast<char*>(pin) + flag_off);
+  } else {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&own_flags), nflag * sizeof(int), hipHostMallocDefault));
+    flags = own_flags;
+  }
   struct FreeHost {
     int* p;
-    ~FreeHost() { (void)hipHostFree(p); }
-  } fh{flags};
+    ~FreeHost() {
+      if (p) (void)hipHostFree(p);
+    }
+  } fh{own_flags};
   int* dflags = ar.take<int>(std::max<size_t>(1, ni));
   launch_fill_zero(reinterpret_cast<double*>(dflags), (std::max<size_t>(1, ni) + 1) / 2, jb.st);
   // ||f||_W^2 of every problem (block partials, summed on the host)
@@ -1241,7 +1416,22 @@ static void tune_store(const std::string& key, int B, int th, double rate) {
 // candidate runs four graph chunks of the real problems; the best rate of
 // grid points advanced per second wins and is cached.  Returns the slot
 // count (0 on failure) and the tile rows in *th.
-static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o, hipStream_t st, int* th) {
+// Largest slot count the autotuner tries: twice the default count (at
+// least 128), capped by kMaxSlots.
+static int tuner_cap_slots(const std::vector<JobItem>& items, const rexii_opts& o) {
+  int hb = 0;
+  std::vector<Problem> pbs(items.size());
+  std::vector<Problem*> ptrs;
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (items[i].skip || sizing_plan(items[i], o, pbs[i]) != REXII_OK) continue;
+    ptrs.push_back(&pbs[i]);
+  }
+  if (!ptrs.empty()) hb = engine_size(ptrs, 0, o.precision, o.tile_rows).B;
+  return std::min(kMaxSlots, std::max(128, 2 * hb));
+}
+
+static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o, hipStream_t st, int* th,
+                          void* ws = nullptr, size_t ws_bytes = 0) {
   int dev = 0, cus = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1274,18 +1464,7 @@ static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o
   for (int t : ths) {
     rexii_opts ot = o;
     ot.tile_rows = bicg ? t : 0;
-    // candidates up to twice the default count (at least 128)
-    int hb = 0;
-    {
-      std::vector<Problem> pbs(items.size());
-      std::vector<Problem*> ptrs;
-      for (size_t i = 0; i < items.size(); ++i) {
-        if (items[i].skip || sizing_plan(items[i], ot, pbs[i]) != REXII_OK) continue;
-        ptrs.push_back(&pbs[i]);
-      }
-      if (!ptrs.empty()) hb = engine_size(ptrs, 0, ot.precision, ot.tile_rows).B;
-    }
-    const int cap_b = std::max(128, 2 * hb);
+    const int cap_b = tuner_cap_slots(items, ot);
     for (int B : cands) {
       if (B > cap_b || B > kMaxSlots) break;
       if (size_t(B) * 2 > nsolves && B != cands[0]) break;  // keep the queue longer than the slots
@@ -1301,11 +1480,17 @@ static int autotune_slots(const std::vector<JobItem>& items, const rexii_opts& o
       }
       size_t need = 0;
       if (job_bytes(jb.items, jb.o, false, 0, &need) != REXII_OK) break;
-      Arena ar(nullptr, 0);
-      try {
-        ar.reserve_own(need + 4096);
-      } catch (const HipError&) {
-        break;  // out of memory: larger counts will not fit either
+      // the caller's workspace when there is one (a candidate that does not
+      // fit ends the search), else memory of this candidate's own
+      Arena ar(ws, ws_bytes);
+      if (ws) {
+        if (need > ws_bytes) break;
+      } else {
+        try {
+          ar.reserve_own(need + 4096);
+        } catch (const HipError&) {
+          break;  // out of memory: larger counts will not fit either
+        }
       }
       const int chunks = 4;
       const double ms = run_job(jb, ar, chunks);
@@ -1375,13 +1560,35 @@ static bool overlaps(const double* a, size_t na, const double* b, size_t nb) { r
 // on the caller's stream sees the results.
 template <typename F>
 static rexii_status on_private_stream(hipStream_t caller, F&& body) {
+  DevCtx* c = device_ctx();
+  std::unique_lock<std::mutex> held;
+  if (c) held = std::unique_lock<std::mutex>(c->mu, std::try_to_lock);
+  const bool shared = c && held.owns_lock();
   hipStream_t own = nullptr;
   hipEvent_t ev = nullptr;
-  if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
-    return set_error(REXII_ERR_HIP, "hipStreamCreateWithFlags failed");
+  if (shared) {
+    if (!c->st && hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+      c->st = nullptr;
+      return set_error(REXII_ERR_HIP, "hipStreamCreateWithFlags failed");
+    }
+    if (!c->ev && hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
+      c->ev = nullptr;
+      return set_error(REXII_ERR_HIP, "hipEventCreateWithFlags failed");
+    }
+    own = c->st;
+    ev = c->ev;
+  } else {
+    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
+      return set_error(REXII_ERR_HIP, "hipStreamCreateWithFlags failed");
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+  }
+  struct Hold {
+    DevCtx* prev;
+    Hold(DevCtx* c) : prev(tl_ctx) { tl_ctx = c; }
+    ~Hold() { tl_ctx = prev; }
+  } hold(shared ? c : nullptr);
   rexii_status st;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, caller) != hipSuccess ||
-      hipStreamWaitEvent(own, ev, 0) != hipSuccess) {
+  if (!ev || hipEventRecord(ev, caller) != hipSuccess || hipStreamWaitEvent(own, ev, 0) != hipSuccess) {
     st = set_error(REXII_ERR_HIP, "could not order the private stream after the caller's stream");
   } else {
     try {
@@ -1394,8 +1601,10 @@ static rexii_status on_private_stream(hipStream_t caller, F&& body) {
   }
   const std::string msg = g_err;
   if (hipStreamSynchronize(own) != hipSuccess && st == REXII_OK) st = set_error(REXII_ERR_HIP, "stream sync failed");
-  if (ev) (void)hipEventDestroy(ev);
-  (void)hipStreamDestroy(own);
+  if (!shared) {
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(own);
+  }
   g_err = msg;
   return st;
 }
@@ -1427,7 +1636,7 @@ static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts
     if (any_depth_field) osz.method = 1;
     if (jb.o.pole_batch < 0) {
       int th = 0;
-      const int B = autotune_slots(jb.items, osz, st, &th);
+      const int B = autotune_slots(jb.items, osz, st, &th, ws, ws_bytes);
       jb.o.pole_batch = (B > 0) ? B : 0;
       if (jb.o.tile_rows == 0 && (th == 16 || th == 32) && osz.method == 1) jb.o.tile_rows = th;
       osz.pole_batch = jb.o.pole_batch;
@@ -1593,10 +1802,85 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
 // Fourier-space path (constant depth): FFT, per-mode filter by the REXII sum
 // in closed form, inverse FFT (kernels_fft.hip).
 // ---------------------------------------------------------------------------
+// Poles and weights of the reduced sum (Sec. 2.2), then, per pole, the
+// real parts of the interpolation coefficients of r(x) = w / (x - z) on
+// {0, +-i theta} as functions of theta^2 (see kernels_fft.hip); poles with
+// the same z^2 up to the sign of Im z^2 share a denominator and one entry.
+// The table depends on (M, h, scheme) only (t enters through theta), so it
+// is formed once per such triple and kept, with a pinned host copy the
+// calls upload from (8 most recent triples; entries in use are never freed).
+struct TermTable {
+  int P = 0, nterm = 0;
+  double kappa = 0.0, c0 = 0.0;
+  std::vector<double> tab;   // nterm x (a, b^2, A1, B1, A2, B2)
+  double* pin = nullptr;     // the same in pinned host memory (or nullptr)
+  ~TermTable() {
+    if (pin) (void)hipHostFree(pin);
+  }
+};
+
+// pinned: the entry must carry a pinned copy (callers that may allocate);
+// without it a cached entry of either kind serves and a new one gets none.
+static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme, bool pinned) {
+  static std::mutex mu;
+  static std::deque<std::pair<std::tuple<int, double, int>, std::shared_ptr<const TermTable>>> cache;
+  const auto key = std::make_tuple(M, h, scheme);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto it = cache.begin(); it != cache.end(); ++it)
+      if (it->first == key && (!pinned || it->second->pin)) {
+        auto hit = *it;
+        cache.erase(it);
+        cache.push_front(hit);
+        return hit.second;
+      }
+  }
+  std::vector<cplx> z, w;
+  if (scheme == REXII_SCHEME_REXI)
+    rexi_poles_weights(M, h, z, w);
+  else
+    poles_weights(M, h, z, w);
+  auto tt = std::make_shared<TermTable>();
+  tt->P = int(z.size());
+  tt->kappa = kappa_sum(w, h);
+  std::vector<double>& tab = tt->tab;
+  tab.reserve(size_t(tt->P) * 6);
+  for (int k = 0; k < tt->P; ++k) {
+    const cd zk(z[k].re, z[k].im), wk(w[k].re, w[k].im);
+    const cd q = -wk * std::conj(zk) / std::norm(zk);  // r(0) = -w / z of this pole
+    tt->c0 += q.real();
+    const double a = zk.real() * zk.real() - zk.imag() * zk.imag();
+    const double b = 2.0 * zk.real() * zk.imag();
+    const double e[6] = {a, b * b, -wk.real(), -wk.imag() * b, q.real(), q.imag() * b};
+    const size_t m = tab.size();
+    if (m >= 6 && tab[m - 6] == e[0] && tab[m - 5] == e[1]) {
+      for (int j = 2; j < 6; ++j) tab[m - 6 + j] += e[j];
+    } else {
+      tab.insert(tab.end(), e, e + 6);
+    }
+  }
+  tt->nterm = int(tab.size() / 6);
+  if (pinned) {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&tt->pin), std::max<size_t>(1, tab.size()) * sizeof(double),
+                         hipHostMallocDefault));
+    std::memcpy(tt->pin, tab.data(), tab.size() * sizeof(double));
+  }
+  std::shared_ptr<const TermTable> out = tt;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = cache.begin(); it != cache.end(); ++it)
+    if (it->first == key) {   // an entry without the pinned copy is replaced
+      cache.erase(it);
+      break;
+    }
+  cache.push_front({key, out});
+  while (cache.size() > 8) cache.pop_back();
+  return out;
+}
+
 struct FourierPlan {
   int M = 0, N = 0, P = 0, m0 = 0, nterm = 0;
   double rho = 0.0, kappa = 0.0, c0 = 0.0;
-  std::vector<double> tab;  // nterm x (a, b^2, A1, B1, A2, B2)
+  std::shared_ptr<const TermTable> tab;
 };
 
 // Spectral radius of the constant-depth symbol: centred differences, or
@@ -1608,11 +1892,8 @@ static double rho_fourier(const rexii_swe_op* op, int deriv) {
   return std::sqrt(op->f_cor * op->f_cor + op->g * op->H0 * (sx * sx + sy * sy));
 }
 
-// Poles and weights of the reduced sum (Sec. 2.2), then, per pole, the
-// real parts of the interpolation coefficients of r(x) = w / (x - z) on
-// {0, +-i theta} as functions of theta^2 (see kernels_fft.hip); poles with
-// the same z^2 up to the sign of Im z^2 share a denominator and one entry.
-static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv, FourierPlan& fp) {
+static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv, FourierPlan& fp,
+                                 bool pinned = true) {
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
   if (o.scheme != REXII_SCHEME_REXII && o.scheme != REXII_SCHEME_REXI)
     return set_error(REXII_ERR_INVALID_ARG, "unknown scheme");
@@ -1623,31 +1904,11 @@ static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_o
   if (Md > 2.0e6) return set_error(REXII_ERR_INVALID_ARG, "t*rho/h too large for this library");
   fp.M = m_rule(t, fp.rho, o.h, fp.m0);
   fp.N = fp.M + terms_L();
-  std::vector<cplx> z, w;
-  if (o.scheme == REXII_SCHEME_REXI)
-    rexi_poles_weights(fp.M, o.h, z, w);
-  else
-    poles_weights(fp.M, o.h, z, w);
-  fp.P = int(z.size());
-  fp.kappa = kappa_sum(w, o.h);
-  fp.c0 = 0.0;
-  fp.tab.clear();
-  fp.tab.reserve(size_t(fp.P) * 6);
-  for (int k = 0; k < fp.P; ++k) {
-    const cd zk(z[k].re, z[k].im), wk(w[k].re, w[k].im);
-    const cd q = -wk * std::conj(zk) / std::norm(zk);  // r(0) = -w / z of this pole
-    fp.c0 += q.real();
-    const double a = zk.real() * zk.real() - zk.imag() * zk.imag();
-    const double b = 2.0 * zk.real() * zk.imag();
-    const double e[6] = {a, b * b, -wk.real(), -wk.imag() * b, q.real(), q.imag() * b};
-    const size_t m = fp.tab.size();
-    if (m >= 6 && fp.tab[m - 6] == e[0] && fp.tab[m - 5] == e[1]) {
-      for (int j = 2; j < 6; ++j) fp.tab[m - 6 + j] += e[j];
-    } else {
-      fp.tab.insert(fp.tab.end(), e, e + 6);
-    }
-  }
-  fp.nterm = int(fp.tab.size() / 6);
+  fp.tab = term_table(fp.M, o.h, o.scheme, pinned);
+  fp.P = fp.tab->P;
+  fp.kappa = fp.tab->kappa;
+  fp.c0 = fp.tab->c0;
+  fp.nterm = fp.tab->nterm;
   return REXII_OK;
 }
 
@@ -1662,7 +1923,10 @@ static size_t fourier_bytes(int nx, int ny, int deriv, int nterm, size_t fft_wor
   const size_t nm = size_t(nx / 2 + 1) * ny;
   int cnx = 0, cny = 0;
   fourier_canon(nx, ny, deriv, &cnx, &cny);
-  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(size_t(cnx) * cny * 16) + al256(256) +
+  int nw = 1, ns = 1;
+  mode_coef_shape(cnx * cny, nterm, &nw, &ns);
+  const size_t part = (ns > 1) ? al256(size_t(ns) * cnx * cny * 16) : 0;
+  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(size_t(cnx) * cny * 16) + part + al256(256) +
          al256(fft_work);
 }
 
@@ -1689,7 +1953,7 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     rexii_opts o = resolve_opts(opts_in);
     if (noalloc) o.profile = 0;
     FourierPlan fp;
-    rexii_status s = fourier_plan(op, t, o, deriv, fp);
+    rexii_status s = fourier_plan(op, t, o, deriv, fp, !noalloc);
     if (s != REXII_OK) return s;
     if (noalloc) {
       const size_t fixed = fourier_bytes(nx, ny, deriv, fp.nterm, 0);
@@ -1722,30 +1986,30 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
       return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     }
+    const int ne = cnx * cny;
+    int nw = 1, ns = 1;
+    mode_coef_shape(ne, fp.nterm, &nw, &ns);
+    const std::vector<double>& htab = fp.tab->tab;
     double2* F = ar.take<double2>(3 * nm);
-    double* tab = ar.take<double>(fp.tab.size());
-    double2* coef = ar.take<double2>(size_t(cnx) * cny);
+    double* tab = ar.take<double>(htab.size());
+    double2* coef = ar.take<double2>(size_t(ne));
+    double2* part = (ns > 1) ? ar.take<double2>(size_t(ns) * ne) : nullptr;
     double* flagd = ar.take<double>(32);
     void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
     int* flag = reinterpret_cast<int*>(flagd);
-    HIPCHK(hipMemcpyAsync(tab, fp.tab.data(), fp.tab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    // the term table: a DMA from its pinned copy, or (no pinned copy: the
+    // no-allocation entry point) a copy from pageable memory
+    HIPCHK(hipMemcpyAsync(tab, fp.tab->pin ? fp.tab->pin : htab.data(), htab.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
     launch_fill_zero(flagd, 32, st);
     const bool prof = (o.profile != 0);
-    hipEvent_t ev[6] = {};
-    if (prof)
+    // profiling events: created once per host thread and kept
+    static thread_local hipEvent_t ev[6] = {};
+    if (prof && !ev[0])
       for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    struct EvGuard {
-      hipEvent_t* e;
-      ~EvGuard() {
-        for (int k = 0; k < 6; ++k)
-          if (e[k]) (void)hipEventDestroy(e[k]);
-      }
-    } guard{ev};
     auto mark = [&](int k) {
       if (prof) HIPCHK(hipEventRecord(ev[k], st));
     };
-    const int ne = cnx * cny;
-    const int nw = mode_coef_waves(ne, fp.nterm);
     const double scale = 1.0 / (double(nx) * ny);
     mark(0);
     launch_copy_check(f, u, n3, flag, st);  // the forward transform may overwrite its input
@@ -1753,7 +2017,8 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     s = fft_execute(fwd, u, F, wk, work, st);
     if (s != REXII_OK) return s;
     mark(2);
-    launch_mode_coef(coef, cnx, cny, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, st);
+    launch_mode_coef(coef, part, cnx, cny, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns,
+                     st);
     mark(3);
     launch_mode_apply(F, coef, cnx, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
     mark(4);
@@ -1786,6 +2051,7 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
       rep->rho = fp.rho;
       rep->kappa_sum = fp.kappa;
       rep->slots = nw;
+      rep->tile_rows = ns;    // term splits of the sum kernel
       rep->total_iters = ne;  // distinct frequencies the pole sums were formed at
       // copy 16, forward FFT 8 + 16 nm/n, apply 2 x 48 nm/n, inverse 16 nm/n + 8 bytes per point and field
       rep->alg_bytes = double(n3) * 32.0 + 3.0 * double(nm) * (16.0 + 96.0 + 16.0);
@@ -2193,7 +2459,11 @@ rexii_status rexii_fourier_workspace_size(const rexii_swe_op* op, const rexii_op
     return clear_error();
   }
   FourierPlan fp;
-  v = fourier_plan(op, t, resolve_opts(opts), derivative, fp);
+  try {
+    v = fourier_plan(op, t, resolve_opts(opts), derivative, fp);
+  } catch (const HipError& he) {
+    return set_error(he.st, he.msg);
+  }
   if (v != REXII_OK) return v;
   size_t work = 0;
   v = fft_plans(op->nx, op->ny, &work, nullptr, nullptr);
@@ -2289,7 +2559,11 @@ rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts
     }
     o.method = 1;
     size_t b = 0;
-    st = job_bytes({it}, o, false, 0, &b);
+    try {
+      st = items_bytes({it}, o, &b);
+    } catch (const HipError& he) {
+      return set_error(he.st, he.msg);
+    }
     if (st != REXII_OK) return st;
     *bytes = b + 4096;
     return clear_error();
@@ -2309,7 +2583,53 @@ rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts
   if (st != REXII_OK) return st;
   const size_t nd = pb.pl.solves.size();
   b += al256(nd * sizeof(AdjDot)) + al256(nd * size_t(adj_dot_blocks(n)) * 16) + al256(nd * 16) + 4096;
+  if (o.pole_batch < 0) {
+    // rexii_apply with the autotuner may run more slots than the adjoint
+    JobItem A;
+    A.op = op;
+    A.t = t;
+    size_t ba = 0;
+    st = items_bytes({A}, o, &ba);
+    if (st != REXII_OK) return st;
+    b = std::max(b, ba + 4096);
+  }
   *bytes = b;
+  return clear_error();
+}
+
+rexii_status rexii_batched_workspace_size(int32_t count, const rexii_swe_op* ops, const double* t,
+                                          const rexii_opts* opts, size_t* bytes) {
+  if (count <= 0 || !ops || !t || !bytes) return set_error(REXII_ERR_INVALID_ARG, "need count > 0, ops, t and bytes");
+  std::vector<JobItem> items(count);
+  rexii_opts o = resolve_opts(opts);
+  bool any = false;
+  try {
+    for (int i = 0; i < count; ++i) {
+      rexii_status v = check_op_and_t(&ops[i], t[i], true);
+      if (v != REXII_OK) return v;
+      items[i].op = &ops[i];
+      items[i].t = t[i];
+      if (t[i] == 0.0) {
+        items[i].skip = true;
+        continue;
+      }
+      any = true;
+      if (ops[i].H_field) {
+        items[i].hmax = device_hmax(ops[i].H_field, size_t(ops[i].nx) * ops[i].ny, nullptr);
+        o.method = 1;
+      }
+    }
+    if (!any) {
+      *bytes = 0;
+      return clear_error();
+    }
+    size_t b = 0;
+    rexii_status st = items_bytes(items, o, &b);
+    if (st != REXII_OK) return st;
+    *bytes = b + 4096;
+  } catch (const HipError& he) {
+    return set_error(he.st, he.msg);
+  }
   return clear_error();
 }
 

@@ -66,10 +66,11 @@ class Report(ctypes.Structure):
 
 
 EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_size",
-           "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched",
+           "rexii_apply", "rexii_apply_adjoint", "rexii_apply_batched", "rexii_batched_workspace_size",
            "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
            "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_coeffs_rexi",
-           "rexii_apply_fourier_noalloc", "rexii_last_error"]
+           "rexii_apply_fourier_noalloc", "rexii_apply_circulant", "rexii_circulant_workspace_size",
+           "rexii_last_error"]
 
 _lib = None
 
@@ -100,6 +101,8 @@ def load():
     lib.rexii_apply_adjoint.restype = ctypes.c_int
     lib.rexii_apply_batched.argtypes = [i32, P(SweOp), P(vp), P(vp), P(dbl), P(Opts), vp, sz, vp, P(Report)]
     lib.rexii_apply_batched.restype = ctypes.c_int
+    lib.rexii_batched_workspace_size.argtypes = [i32, P(SweOp), P(dbl), P(Opts), P(sz)]
+    lib.rexii_batched_workspace_size.restype = ctypes.c_int
     lib.rexii_shifted_solve.argtypes = [P(SweOp), vp, dbl, i32, vp, vp, P(Opts), vp, sz, vp, P(Report)]
     lib.rexii_shifted_solve.restype = ctypes.c_int
     lib.rexii_apply_fourier.argtypes = [P(SweOp), vp, vp, dbl, i32, P(Opts), vp, sz, vp, P(Report)]
@@ -112,6 +115,11 @@ def load():
     lib.rexii_apply_multishift.restype = ctypes.c_int
     lib.rexii_multishift_workspace_size.argtypes = [P(SweOp), i32, P(Opts), P(sz)]
     lib.rexii_multishift_workspace_size.restype = ctypes.c_int
+    lib.rexii_circulant_workspace_size.argtypes = [i32, i32, vp, vp, i32, dbl, dbl, i32, i32, P(Opts), P(sz)]
+    lib.rexii_circulant_workspace_size.restype = ctypes.c_int
+    lib.rexii_apply_circulant.argtypes = [i32, i32, vp, vp, i32, vp, vp, dbl, dbl, i32, i32, P(Opts), vp, sz, vp,
+                                          P(Report)]
+    lib.rexii_apply_circulant.restype = ctypes.c_int
     lib.rexii_last_error.argtypes = []
     lib.rexii_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -236,10 +244,41 @@ def apply(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts):
     op = make_op(nx, ny, g, fc, H, Hfield)
     o = make_opts(**opts)
     rep = Report()
+    ws = _workspace((SweOp * 1)(op), (ctypes.c_double * 1)(float(t)), o, f.device)
     st = lib.rexii_apply(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
-                         float(t), ctypes.byref(o), None, 0, _stream(), ctypes.byref(rep))
+                         float(t), ctypes.byref(o), *_ws_args(ws), _stream(), ctypes.byref(rep))
     _check(st, rep.as_dict())
     return u, rep.as_dict()
+
+
+def _workspace(ops, ts, o, device):
+    """Device workspace of a slot-engine call, from PyTorch's allocator (its
+    cache hands back the same memory on the next call, so repeated calls make
+    no device allocation)."""
+    import torch
+    nb = ctypes.c_size_t()
+    _check(load().rexii_batched_workspace_size(len(ops), ops, ts, ctypes.byref(o), ctypes.byref(nb)))
+    if nb.value == 0:
+        return None
+    return torch.empty(nb.value, dtype=torch.uint8, device=device)
+
+
+def _ws_args(ws):
+    return (None, 0) if ws is None else (ctypes.c_void_p(ws.data_ptr()), ws.numel())
+
+
+def batched_workspace_size(shapes, ts, g=1.0, fc=10.0, H=1.0, **opts):
+    """Workspace bytes of apply_batched for states of the given (ny, nx)
+    shapes and times (constant depth)."""
+    cnt = len(shapes)
+    ops = (SweOp * cnt)()
+    for i, (ny, nx) in enumerate(shapes):
+        ops[i] = make_op(nx, ny, g, fc, H, None)
+    o = make_opts(**opts)
+    nb = ctypes.c_size_t()
+    _check(load().rexii_batched_workspace_size(cnt, ops, (ctypes.c_double * cnt)(*[float(t) for t in ts]),
+                                               ctypes.byref(o), ctypes.byref(nb)))
+    return nb.value
 
 
 def shifted_solve(f, t, z, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
@@ -401,9 +440,65 @@ def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
     tarr = (ctypes.c_double * cnt)(*[float(t) for t in ts])
     reps = (Report * cnt)()
     o = make_opts(**opts)
-    st = lib.rexii_apply_batched(cnt, ops, fptr, uptr, tarr, ctypes.byref(o), None, 0, _stream(), reps)
+    ws = _workspace(ops, tarr, o, fs[0].device)
+    st = lib.rexii_apply_batched(cnt, ops, fptr, uptr, tarr, ctypes.byref(o), *_ws_args(ws), _stream(), reps)
     _check(st, [r.as_dict() for r in reps])
     return us, [r.as_dict() for r in reps]
+
+
+CIRC_SCHEMES = {"rexii": 0, "rexi": 1, "rexie": 2}
+
+
+def _stencil_arrays(stencil):
+    off = np.ascontiguousarray(np.array(list(stencil.keys()), dtype=np.int32))
+    c = np.array([complex(v) for v in stencil.values()], dtype=np.complex128)
+    cc = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1).ravel())
+    return off, cc
+
+
+def apply_circulant(f, t, stencil, scheme="rexii", nu=0.0, M=0, out=None, **opts):
+    """exp(tA) f for a circulant matrix A, (A f)_j = sum_d stencil[d] f_{j+d}
+    (indices mod n), by REXII, the original REXI or REXIE (scheme), each
+    resolvent exact per Fourier mode on the GPU.  f: float64 CUDA tensor [n]
+    or [nrhs, n] of real vectors.  nu: REXIE's shift, a purely imaginary
+    number (A - nu I = i B).  M > 0 fixes M, else the rule of
+    eq. matrixAccuracyBound.  Returns (u: complex128 CUDA tensor shaped like
+    f, report_dict)."""
+    import torch
+    lib = load()
+    _dev_f64(f)
+    if f.dim() not in (1, 2):
+        raise ValueError("expected [n] or [nrhs, n]")
+    nrhs = 1 if f.dim() == 1 else f.shape[0]
+    n = f.shape[-1]
+    nu = complex(nu)
+    if nu.real != 0.0:
+        raise ValueError("nu must be purely imaginary")
+    u = torch.empty(f.shape, dtype=torch.complex128, device=f.device) if out is None else out
+    if not (u.is_cuda and u.dtype == torch.complex128 and u.is_contiguous() and u.shape == f.shape):
+        raise ValueError("out must be a contiguous complex128 CUDA tensor shaped like f")
+    off, cc = _stencil_arrays(stencil)
+    o = make_opts(**opts)
+    rep = Report()
+    st = lib.rexii_apply_circulant(int(n), len(off), off.ctypes.data_as(ctypes.c_void_p),
+                                   cc.ctypes.data_as(ctypes.c_void_p), int(nrhs), ctypes.c_void_p(f.data_ptr()),
+                                   ctypes.c_void_p(u.data_ptr()), float(t), float(nu.imag),
+                                   CIRC_SCHEMES.get(scheme, scheme), int(M), ctypes.byref(o), None, 0, _stream(),
+                                   ctypes.byref(rep))
+    _check(st, rep.as_dict())
+    return u, rep.as_dict()
+
+
+def circulant_workspace_size(n, t, stencil, nrhs=1, scheme="rexii", nu=0.0, M=0, **opts):
+    lib = load()
+    off, cc = _stencil_arrays(stencil)
+    o = make_opts(**opts)
+    out = ctypes.c_size_t()
+    _check(lib.rexii_circulant_workspace_size(int(n), len(off), off.ctypes.data_as(ctypes.c_void_p),
+                                              cc.ctypes.data_as(ctypes.c_void_p), int(nrhs), float(t),
+                                              float(complex(nu).imag), CIRC_SCHEMES.get(scheme, scheme), int(M),
+                                              ctypes.byref(o), ctypes.byref(out)))
+    return out.value
 
 
 def _autograd_fn():

@@ -145,3 +145,39 @@ def test_apply_multishift_rejects_bad_arguments_before_touching_the_device(rx):
 def test_default_opts(rx):
     o = rx.make_opts()
     assert o.h == 0.5 and o.m0 == -1 and o.pair_conjugate == 1 and o.precision == 0
+
+
+def test_apply_circulant_rejects_bad_arguments_before_touching_the_device(rx):
+    # the schemes' premises (Sec. 2.2 and the remark on REXIE) are checked on
+    # the host: REXII / REXI need a real skew-symmetric circulant matrix,
+    # REXIE needs A - nu I = i B with B real symmetric
+    from oracle import matrix_cases as mc
+    lib = rx.load()
+    dummy = ctypes.c_void_p(16)       # never dereferenced: validation fails first
+    far = ctypes.c_void_p(1 << 30)
+    rep = rx.Report()
+
+    def call(n, stencil, scheme, nu=0.0, nrhs=1, f=dummy, u=far, t=1.0):
+        off, cc = rx._stencil_arrays(stencil)
+        return lib.rexii_apply_circulant(n, len(off), off.ctypes.data_as(ctypes.c_void_p),
+                                         cc.ctypes.data_as(ctypes.c_void_p), nrhs, f, u, t, nu, scheme, 0, None,
+                                         None, 0, None, ctypes.byref(rep))
+
+    A1, A2 = mc.stencil_A1(70), mc.stencil_A2(70)
+    assert call(70, A1, 2) == -1                   # A_1 = i B with B Hermitian, not real: no REXIE
+    assert "REXIE" in rx.last_error()
+    assert call(70, A2, 0) == -1 and call(70, A2, 1) == -1   # A_2 is not real
+    assert call(70, A1, 0, nu=-2450.0) == -1       # the shift is a REXIE option
+    assert call(70, {1: 1.0, -1: -0.5}, 0) == -1   # not skew-symmetric
+    assert call(70, {1: 1j, -1: 2j}, 2) == -1      # i B with B not symmetric
+    assert call(70, {0: 1.0 + 1j}, 2) == -1        # real part on the diagonal
+    assert call(1, A1, 0) == -1                    # n >= 2
+    assert call(70, A1, 0, nrhs=0) == -1
+    assert call(70, A1, 3) == -1                   # unknown scheme
+    assert call(70, A1, 0, f=None) == -1
+    assert call(70, A1, 0, t=-1.0) == -1
+    assert call(70, A1, 0, u=ctypes.c_void_p(16 + 8 * 35)) == -1   # u overlaps f
+    off = np.zeros(65, dtype=np.int32)
+    cc = np.zeros(130)
+    assert lib.rexii_apply_circulant(70, 65, off.ctypes.data_as(ctypes.c_void_p), cc.ctypes.data_as(ctypes.c_void_p),
+                                     1, dummy, far, 1.0, 0.0, 0, 0, None, None, 0, None, None) == -1

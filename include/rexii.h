@@ -431,7 +431,11 @@ rexii_status rexii_apply_multishift(const rexii_swe_op* op, int32_t nrhs, const 
  *     NULL to let the library allocate.  FFT plans are created on first use
  *     per device, n and nrhs and kept until the process ends.
  *   Report: P (poles), M, N, m0, h, t, rho, kappa_sum (sum over the weights
- *     of |w| / |h mu|, both weight sets for REXIE), total_iters = modes, seconds.
+ *     of |w| / |h mu|, both weight sets for REXIE), total_iters = modes,
+ *     slots = waves per block of the pole-sum kernel, seconds.  With
+ *     opts.profile = 1: step_ms[0..4] = load and finiteness check, forward
+ *     FFT, pole sums, apply, inverse FFT (HIP events, ms), kernel_ms =
+ *     step_ms[2].
  *   The call returns when u is complete on `stream`.
  * Errors: INVALID_ARG, NONFINITE (f; u is written anyway), OOM, HIP, WORKSPACE. */
 enum { REXII_CIRC_REXII = 0, REXII_CIRC_REXI = 1, REXII_CIRC_REXIE = 2 };

@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -52,6 +53,16 @@ struct CircTerm {
   double zr, zi, w1r, w1i, w2r, w2i;
 };
 
+// 1/x to full FP64 precision: hardware reciprocal estimate and two
+// Newton-Raphson steps r <- r + r (1 - x r).
+__device__ __forceinline__ double circ_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // t (lambda(k) - i nu) for mode k.
 __device__ inline void mode_symbol(const CircStencil& s, int k, int n, double t, double nu, double& xr, double& xi) {
   double lr = 0.0, li = 0.0;
@@ -67,7 +78,12 @@ __device__ inline void mode_symbol(const CircStencil& s, int k, int n, double t,
 }
 
 // g[k] (and g2[k] for two weight sets) = sum_p w_p / (x_k - z_p).  Block: 64
-// modes (one per lane) x nw waves; wave w takes one slice of the terms.
+// modes (one per lane) x nw waves; wave w takes one slice of the terms (the
+// term index is wave-uniform, so the table arrives through scalar loads).
+// Two terms share one reciprocal: 1/d1 = d2 / (d1 d2) with d = |x - z|^2,
+// which lies in [(h mu)^2, (|x| + h(N + |mu|))^2], so the product stays in
+// range for any h above 1e-3 and |x| below 1e70.
+template <bool TWO>
 __global__ __launch_bounds__(64 * kCircWaves) void k_circ_sums(double2* __restrict__ g, double2* __restrict__ g2,
                                                                int n, CircStencil s, double t, double nu,
                                                                const CircTerm* __restrict__ tab, int nterm) {
@@ -82,16 +98,29 @@ __global__ __launch_bounds__(64 * kCircWaves) void k_circ_sums(double2* __restri
   const int per = (nterm + nw - 1) / nw;
   const int lo = min(nterm, w * per), hi = min(nterm, lo + per);
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-  for (int j = lo; j < hi; ++j) {
-    const CircTerm q = tab[j];
-    // 1 / (x - z) = conj(x - z) / |x - z|^2
-    const double dr = xr - q.zr, di = xi - q.zi;
-    const double rinv = 1.0 / fma(dr, dr, di * di);
-    const double er = dr * rinv, ei = -di * rinv;
+  // w / (x - z) with 1 / (x - z) = conj(x - z) * inv, inv = 1 / |x - z|^2
+  auto acc = [&](const CircTerm& q, double dr, double di, double inv) {
+    const double er = dr * inv, ei = -di * inv;
     ar = fma(q.w1r, er, fma(-q.w1i, ei, ar));
     ai = fma(q.w1r, ei, fma(q.w1i, er, ai));
-    br = fma(q.w2r, er, fma(-q.w2i, ei, br));
-    bi = fma(q.w2r, ei, fma(q.w2i, er, bi));
+    if (TWO) {
+      br = fma(q.w2r, er, fma(-q.w2i, ei, br));
+      bi = fma(q.w2r, ei, fma(q.w2i, er, bi));
+    }
+  };
+  int j = lo;
+  for (; j + 1 < hi; j += 2) {
+    const CircTerm q1 = tab[j], q2 = tab[j + 1];
+    const double dr1 = xr - q1.zr, di1 = xi - q1.zi, dr2 = xr - q2.zr, di2 = xi - q2.zi;
+    const double d1 = fma(dr1, dr1, di1 * di1), d2 = fma(dr2, dr2, di2 * di2);
+    const double r = circ_recip(d1 * d2);
+    acc(q1, dr1, di1, r * d2);
+    acc(q2, dr2, di2, r * d1);
+  }
+  if (j < hi) {
+    const CircTerm q = tab[j];
+    const double dr = xr - q.zr, di = xi - q.zi;
+    acc(q, dr, di, circ_recip(fma(dr, dr, di * di)));
   }
   if (nw > 1) {
     if (w > 0) {
@@ -113,7 +142,7 @@ __global__ __launch_bounds__(64 * kCircWaves) void k_circ_sums(double2* __restri
   }
   if (!live) return;
   g[k] = make_double2(ar, ai);
-  if (g2) g2[k] = make_double2(br, bi);
+  if (TWO) g2[k] = make_double2(br, bi);
 }
 
 // u[r][k] <- m(k) u[r][k] / n with m(k) = (g(k) + conj g(-k)) / 2 (one sum),
@@ -274,22 +303,42 @@ rexii_status circ_plan(int32_t n, int32_t nstencil, const int32_t* offsets, cons
                          "circulant REXII/REXI: A must be a real skew-symmetric circulant matrix");
     }
   }
-  // rho = max_k |lambda(k) - i nu| (exact), unless given
+  // rho = max_k |lambda(k) - i nu| (exact), unless given; O(n) sines, so
+  // kept per (n, matrix, nu) for repeated calls (16 most recent)
   if (o.rho > 0.0) {
     cp.rho = o.rho;
   } else {
-    double r = 0.0;
-    for (int k = 0; k < n; ++k) {
-      double lr = 0.0, li = 0.0;
-      for (const auto& kv : cls) {
-        const double ph = 2.0 * M_PI * double((static_cast<long long>(kv.first) * k) % n) / double(n);
-        const double cs = std::cos(ph), sn = std::sin(ph);
-        lr += kv.second.first * cs - kv.second.second * sn;
-        li += kv.second.first * sn + kv.second.second * cs;
-      }
-      r = std::max(r, std::hypot(lr, li - nu));
+    using Key = std::tuple<int, double, std::vector<std::pair<int, std::pair<double, double>>>>;
+    static std::mutex mu;
+    static std::deque<std::pair<Key, double>> known;
+    Key key{n, nu, std::vector<std::pair<int, std::pair<double, double>>>(cls.begin(), cls.end())};
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (const auto& e : known)
+        if (e.first == key) {
+          cp.rho = e.second;
+          hit = true;
+          break;
+        }
     }
-    cp.rho = r;
+    if (!hit) {
+      double r = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double lr = 0.0, li = 0.0;
+        for (const auto& kv : cls) {
+          const double ph = 2.0 * M_PI * double((static_cast<long long>(kv.first) * k) % n) / double(n);
+          const double cs = std::cos(ph), sn = std::sin(ph);
+          lr += kv.second.first * cs - kv.second.second * sn;
+          li += kv.second.first * sn + kv.second.second * cs;
+        }
+        r = std::max(r, std::hypot(lr, li - nu));
+      }
+      cp.rho = r;
+      std::lock_guard<std::mutex> lk(mu);
+      known.push_front({key, r});
+      while (known.size() > 16) known.pop_back();
+    }
   }
   cp.m0 = (o.m0 >= 0) ? o.m0 : m0_from_tol(cp.tol);
   if (M > 0) {
@@ -301,6 +350,22 @@ rexii_status circ_plan(int32_t n, int32_t nstencil, const int32_t* offsets, cons
   }
   if (cp.M > 50000000) return set_error(REXII_ERR_INVALID_ARG, "circulant: M too large");
   cp.N = cp.M + terms_L();
+  // the term table depends on (scheme, M, h) only: kept for repeated calls
+  // (8 most recent)
+  using Key = std::tuple<int, int, double>;
+  static std::mutex mu;
+  static std::deque<std::pair<Key, std::pair<std::vector<CircTerm>, double>>> known;
+  const Key key{scheme, cp.M, cp.h};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto& e : known)
+      if (e.first == key) {
+        cp.terms = e.second.first;
+        cp.kappa = e.second.second;
+        cp.P = int(cp.terms.size());
+        return REXII_OK;
+      }
+  }
   std::vector<cplx> z, w1, w2;
   if (scheme == REXII_CIRC_REXII) {
     poles_weights(cp.M, cp.h, z, w1);
@@ -323,6 +388,9 @@ rexii_status circ_plan(int32_t n, int32_t nstencil, const int32_t* offsets, cons
     q.w2r = w2.empty() ? 0.0 : w2[p].re;
     q.w2i = w2.empty() ? 0.0 : w2[p].im;
   }
+  std::lock_guard<std::mutex> lk(mu);
+  known.push_front({key, {cp.terms, cp.kappa}});
+  while (known.size() > 8) known.pop_back();
   return REXII_OK;
 }
 
@@ -431,7 +499,14 @@ rexii_status rexii_apply_circulant(int32_t n, int32_t nstencil, const int32_t* o
   void* work = fp.work ? take(fp.work) : nullptr;
   double2* ud = reinterpret_cast<double2*>(u);
   auto hipfail = [&](const char* what) { return set_error(REXII_ERR_HIP, std::string("circulant: ") + what + " failed"); };
+  const bool prof = opts && opts->profile != 0;
+  static thread_local hipEvent_t ev[6] = {};   // profiling events, created once per host thread
+  if (prof && !ev[0])
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return hipfail("hipEventCreate");
+  auto mark = [&](int k) { return !prof || hipEventRecord(ev[k], stream) == hipSuccess; };
   hipLaunchKernelGGL(k_circ_clear, dim3(1), dim3(64), 0, stream, flag);
+  if (!mark(0)) return hipfail("hipEventRecord");
   {
     size_t b = (nall + 255) / 256;
     b = std::min<size_t>(std::max<size_t>(b, 1), 4096);
@@ -450,20 +525,29 @@ rexii_status rexii_apply_circulant(int32_t n, int32_t nstencil, const int32_t* o
   if (hipMemcpyAsync(dtab, cp.terms.data(), cp.terms.size() * sizeof(CircTerm), hipMemcpyHostToDevice, stream) !=
       hipSuccess)
     return hipfail("term table upload");
+  if (!mark(1)) return hipfail("hipEventRecord");
   st = fft_execute(fp.fwd, ud, ud, work, fp.work, stream);
   if (st != REXII_OK) return st;
+  if (!mark(2)) return hipfail("hipEventRecord");
   const int nw = circ_waves(n, cp.P);
   const bool two = (scheme == REXII_CIRC_REXIE);
-  hipLaunchKernelGGL(k_circ_sums, dim3(unsigned((n + 63) / 64)), dim3(64 * nw), size_t(nw - 1) * 256 * sizeof(double),
-                     stream, g, two ? g2 : nullptr, n, cp.st, t, nu, dtab, cp.P);
+  if (two)
+    hipLaunchKernelGGL(k_circ_sums<true>, dim3(unsigned((n + 63) / 64)), dim3(64 * nw),
+                       size_t(nw - 1) * 256 * sizeof(double), stream, g, g2, n, cp.st, t, nu, dtab, cp.P);
+  else
+    hipLaunchKernelGGL(k_circ_sums<false>, dim3(unsigned((n + 63) / 64)), dim3(64 * nw),
+                       size_t(nw - 1) * 256 * sizeof(double), stream, g, nullptr, n, cp.st, t, nu, dtab, cp.P);
   if (hipGetLastError() != hipSuccess) return hipfail("pole-sum kernel");
+  if (!mark(3)) return hipfail("hipEventRecord");
   // REXIE: exp(tA) = e^{t nu} exp(t(A - nu I)), nu = i nu_im
   const double er = two ? std::cos(t * nu) : 1.0, ei = two ? std::sin(t * nu) : 0.0;
   hipLaunchKernelGGL(k_circ_apply, dim3(unsigned((nall + 255) / 256)), dim3(256), 0, stream, ud, g,
                      two ? g2 : nullptr, n, nrhs, er, ei);
   if (hipGetLastError() != hipSuccess) return hipfail("apply kernel");
+  if (!mark(4)) return hipfail("hipEventRecord");
   st = fft_execute(fp.inv, ud, ud, work, fp.work, stream);
   if (st != REXII_OK) return st;
+  if (!mark(5)) return hipfail("hipEventRecord");
   if (!two) {
     size_t b = (nall + 255) / 256;
     b = std::min<size_t>(std::max<size_t>(b, 1), 4096);
@@ -475,6 +559,19 @@ rexii_status rexii_apply_circulant(int32_t n, int32_t nstencil, const int32_t* o
       hipStreamSynchronize(stream) != hipSuccess)
     return hipfail("stream synchronisation");
   fill_circ_report(rep, cp, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (rep) {
+    rep->slots = nw;
+    if (prof) {
+      // load, forward FFT, pole sums, apply, inverse FFT (ms)
+      for (int k = 0; k < 5; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) return hipfail("hipEventElapsedTime");
+        rep->step_ms[k] = ms;
+      }
+      rep->kernel_ms = rep->step_ms[2];
+      rep->kernel_launches = 1;
+    }
+  }
   if (hflag) return set_error(REXII_ERR_NONFINITE, "circulant: non-finite value in f");
   return clear_error();
 }

@@ -16,12 +16,15 @@ int canon_count(int n, int kmax, int deriv);
 // coef [cny][cnx] = scale (Re c1, Re c2) per canonical pair; nw waves per
 // block, the terms in ns splits (part: ns x entries double2 when ns > 1).
 void mode_coef_shape(int entries, int nterm, int* nw, int* ns);
-void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, int nx, int ny, int deriv, double t, double g,
-                      double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
+// sxt, syt: the axis symbols s(k) of the x wavenumbers 0..nx/2 and the y
+// wavenumbers 0..ny-1 (axis_symbol), device.
+double axis_symbol(int k, int n, int deriv);
+void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, const double* sxt, const double* syt, double t,
+                      double g, double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
                       hipStream_t s);
 // F [3][ny][nx/2+1] <- a0 F + C1 t A F + C2 (t A)^2 F with (C1, C2) from coef.
-void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, double t, double g,
-                       double H, double fc, double a0, hipStream_t s);
+void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, const double* sxt,
+                       const double* syt, double t, double g, double H, double fc, double a0, hipStream_t s);
 void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s);
 
 }  // namespace rexii

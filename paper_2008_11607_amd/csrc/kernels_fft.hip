@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
 
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -66,9 +67,10 @@ __device__ __forceinline__ double sq_plus(double s, double b) {
   return d;
 }
 
-// s for wavenumber index k of an axis of n points (see file comment).
-__device__ __forceinline__ double axis_symbol(int k, int n, int deriv) {
-  if (deriv == 0) return double(n) * sinpi(double(2 * k) / double(n));
+// s for wavenumber index k of an axis of n points (see file comment); the
+// kernels read it from a table the host fills once per grid.
+double axis_symbol(int k, int n, int deriv) {
+  if (deriv == 0) return double(n) * std::sin(2.0 * M_PI * double(k) / double(n));
   const int ks = (2 * k == n) ? 0 : (2 * k < n ? k : k - n);
   return 2.0 * M_PI * double(ks);
 }
@@ -160,7 +162,8 @@ int canon_count(int n, int kmax, int deriv) {
 // unscaled sums to part[s][e] and k_mode_coef_sum adds the splits in order.
 __global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restrict__ coef,
                                                                double2* __restrict__ part, int cnx, int cny,
-                                                               int nx, int ny, int deriv, double t, double g,
+                                                               const double* __restrict__ sxt,
+                                                               const double* __restrict__ syt, double t, double g,
                                                                double H, double fc, double scale,
                                                                const double* __restrict__ tab, int nterm) {
   extern __shared__ double red[];
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restri
   const int e = int(blockIdx.x) * 64 + lane;
   const bool live = e < ne;
   const int cx = live ? e % cnx : 0, cy = live ? e / cnx : 0;
-  const double sx = axis_symbol(cx, nx, deriv), sy = axis_symbol(cy, ny, deriv);
+  const double sx = sxt[cx], sy = syt[cy];
   const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
   double c1, c2;
   term_sums(tab + size_t(lo_s) * kTermDoubles, cnt_s, w, nw, th2, c1, c2);
@@ -215,7 +218,8 @@ __global__ __launch_bounds__(256) void k_mode_coef_sum(double2* __restrict__ coe
 // the mode's canonical frequency: F <- scale c0 F + C1 X F + C2 X^2 F,
 // X = t A(k) with the mode's own (signed) symbols.
 __global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, const double2* __restrict__ coef,
-                                                    int cnx, int nx, int ny, int deriv, double t, double g, double H,
+                                                    int cnx, int nx, int ny, int deriv, const double* __restrict__ sxt,
+                                                    const double* __restrict__ syt, double t, double g, double H,
                                                     double fc, double a0) {
   const int nxh = nx / 2 + 1;
   const int nm = nxh * ny;
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, con
   if (m >= nm) return;
   const int kx = m % nxh, ky = m / nxh;
   const double2 c = coef[canon_index(ky, ny, deriv) * cnx + canon_index(kx, nx, deriv)];
-  const double sx = axis_symbol(kx, nx, deriv), sy = axis_symbol(ky, ny, deriv);
+  const double sx = sxt[kx], sy = syt[ky];
   double2 f[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) f[q] = F[size_t(q) * nm + m];
@@ -256,11 +260,13 @@ __global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ 
 
 // Shape of k_mode_coef: waves per block (8, measured best with 2000-10000
 // terms per entry, fewer when a wave would get under 64 terms) and term
-// splits (grid rows): enough blocks for about kCoefBlocks, i.e. 16 waves per
-// SIMD on 256 CUs, while every wave keeps at least kMinTermsPerWave terms.
-// Large tables (2048^2: 4112 blocks) run unsplit; 512^2 (261 blocks) splits.
-constexpr int kCoefBlocks = 2048;
-constexpr int kMinTermsPerWave = 24;
+// splits (grid rows): blocks up to about kCoefBlocks (32 per CU) while every
+// wave keeps at least kMinTermsPerWave terms.  Measured (kernel time, FP64
+// flop fraction): 512^2 at t rho 1000 (261 blocks, 2034 terms) 4 splits
+// 27.2 us / 19%, 8 splits 28.3 us, 16 splits 33.2 us; 2048^2 at t rho 5000
+// (4112 blocks, 10034 terms) 1 split 0.91 ms / 44%, 2 splits 0.86 ms / 47%.
+constexpr int kCoefBlocks = 8192;
+constexpr int kMinTermsPerWave = 32;
 
 void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   const int blocks = (entries + 63) / 64;
@@ -272,22 +278,22 @@ void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   *ns_out = ns;
 }
 
-void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, int nx, int ny, int deriv, double t, double g,
-                      double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
+void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, const double* sxt, const double* syt, double t,
+                      double g, double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
                       hipStream_t s) {
   const int ne = cnx * cny;
   const size_t lds = size_t(nw - 1) * 128 * sizeof(double);
   hipLaunchKernelGGL(k_mode_coef, dim3(unsigned((ne + 63) / 64), unsigned(ns)), dim3(64 * nw), lds, s, coef, part,
-                     cnx, cny, nx, ny, deriv, t, g, H, fc, scale, tab, nterm);
+                     cnx, cny, sxt, syt, t, g, H, fc, scale, tab, nterm);
   if (ns > 1)
     hipLaunchKernelGGL(k_mode_coef_sum, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, coef, part, ne, ns, scale);
 }
 
-void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, double t, double g,
-                       double H, double fc, double a0, hipStream_t s) {
+void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, const double* sxt,
+                       const double* syt, double t, double g, double H, double fc, double a0, hipStream_t s) {
   const long nm = long(nx / 2 + 1) * ny;
-  hipLaunchKernelGGL(k_mode_apply, dim3(unsigned((nm + 255) / 256)), dim3(256), 0, s, F, coef, cnx, nx, ny, deriv, t,
-                     g, H, fc, a0);
+  hipLaunchKernelGGL(k_mode_apply, dim3(unsigned((nm + 255) / 256)), dim3(256), 0, s, F, coef, cnx, nx, ny, deriv, sxt,
+                     syt, t, g, H, fc, a0);
 }
 
 void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s) {

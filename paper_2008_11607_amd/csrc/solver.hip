@@ -1877,6 +1877,51 @@ static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme, 
   return out;
 }
 
+// Axis symbols s(k) of a grid, x wavenumbers 0..nx/2 then y wavenumbers
+// 0..ny-1, formed once per (nx, ny, derivative) and kept (8 most recent),
+// with a pinned copy when the caller may allocate.
+struct SymTable {
+  std::vector<double> s;
+  double* pin = nullptr;
+  ~SymTable() {
+    if (pin) (void)hipHostFree(pin);
+  }
+};
+
+static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv, bool pinned) {
+  static std::mutex mu;
+  static std::deque<std::pair<std::tuple<int, int, int>, std::shared_ptr<const SymTable>>> cache;
+  const auto key = std::make_tuple(nx, ny, deriv);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto it = cache.begin(); it != cache.end(); ++it)
+      if (it->first == key && (!pinned || it->second->pin)) {
+        auto hit = *it;
+        cache.erase(it);
+        cache.push_front(hit);
+        return hit.second;
+      }
+  }
+  auto st = std::make_shared<SymTable>();
+  st->s.resize(size_t(nx / 2 + 1) + ny);
+  for (int k = 0; k <= nx / 2; ++k) st->s[k] = axis_symbol(k, nx, deriv);
+  for (int k = 0; k < ny; ++k) st->s[nx / 2 + 1 + k] = axis_symbol(k, ny, deriv);
+  if (pinned) {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&st->pin), st->s.size() * sizeof(double), hipHostMallocDefault));
+    std::memcpy(st->pin, st->s.data(), st->s.size() * sizeof(double));
+  }
+  std::shared_ptr<const SymTable> out = st;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = cache.begin(); it != cache.end(); ++it)
+    if (it->first == key) {
+      cache.erase(it);
+      break;
+    }
+  cache.push_front({key, out});
+  while (cache.size() > 8) cache.pop_back();
+  return out;
+}
+
 struct FourierPlan {
   int M = 0, N = 0, P = 0, m0 = 0, nterm = 0;
   double rho = 0.0, kappa = 0.0, c0 = 0.0;
@@ -1927,7 +1972,7 @@ static size_t fourier_bytes(int nx, int ny, int deriv, int nterm, size_t fft_wor
   mode_coef_shape(cnx * cny, nterm, &nw, &ns);
   const size_t part = (ns > 1) ? al256(size_t(ns) * cnx * cny * 16) : 0;
   return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(size_t(cnx) * cny * 16) + part + al256(256) +
-         al256(fft_work);
+         al256((size_t(nx / 2 + 1) + ny) * 8) + al256(fft_work);
 }
 
 // noalloc: device scratch from the library's static array, FFT plans only
@@ -1995,11 +2040,16 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     double2* coef = ar.take<double2>(size_t(ne));
     double2* part = (ns > 1) ? ar.take<double2>(size_t(ns) * ne) : nullptr;
     double* flagd = ar.take<double>(32);
+    const std::shared_ptr<const SymTable> sym = symbol_table(nx, ny, deriv, !noalloc);
+    double* sxt = ar.take<double>(sym->s.size());
+    const double* syt = sxt + (nx / 2 + 1);
     void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
     int* flag = reinterpret_cast<int*>(flagd);
-    // the term table: a DMA from its pinned copy, or (no pinned copy: the
-    // no-allocation entry point) a copy from pageable memory
+    // the term and symbol tables: DMAs from their pinned copies, or (no
+    // pinned copy: the no-allocation entry point) copies from pageable memory
     HIPCHK(hipMemcpyAsync(tab, fp.tab->pin ? fp.tab->pin : htab.data(), htab.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sxt, sym->pin ? sym->pin : sym->s.data(), sym->s.size() * sizeof(double),
                           hipMemcpyHostToDevice, st));
     launch_fill_zero(flagd, 32, st);
     const bool prof = (o.profile != 0);
@@ -2017,10 +2067,9 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     s = fft_execute(fwd, u, F, wk, work, st);
     if (s != REXII_OK) return s;
     mark(2);
-    launch_mode_coef(coef, part, cnx, cny, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns,
-                     st);
+    launch_mode_coef(coef, part, cnx, cny, sxt, syt, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns, st);
     mark(3);
-    launch_mode_apply(F, coef, cnx, nx, ny, deriv, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
+    launch_mode_apply(F, coef, cnx, nx, ny, deriv, sxt, syt, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
     mark(4);
     s = fft_execute(inv, F, u, wk, work, st);
     if (s != REXII_OK) return s;

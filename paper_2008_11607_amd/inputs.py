@@ -73,3 +73,30 @@ def batched_instances(count=64, seed0=300, sizes=(128, 256, 512, 1024),
         trho = float(rng.uniform(*trho_range))
         out.append(dict(D=D, trho=trho, seed=seed0 + i, nbumps=nbumps))
     return out
+
+
+# ----------------------------------------------------------------------------
+# the paper's matrix test cases (Sec. 3.2): circulant matrices as stencils
+# {offset d: coefficient c_d}, (A f)_j = sum_d c_d f_{(j + d) mod n}
+# ----------------------------------------------------------------------------
+def advection_stencil(n):
+    """A_1: centred difference of d/dx, periodic on [0, 1] with step 1/n."""
+    return {1: 0.5 * n, -1: -0.5 * n}
+
+
+def schroedinger_stencil(n, length=2.0):
+    """A_2: i times the second difference of d^2/dx^2, periodic on an
+    interval of the given length with step length / n."""
+    c = (n / length) ** 2
+    return {-1: 1j * c, 0: -2j * c, 1: 1j * c}
+
+
+def matrix_case_vector(n, start=0.0, length=1.0):
+    """f_0 = (2 + cos(2 pi x))^{-1} at x = start + length j / n."""
+    x = start + length * np.arange(n) / n
+    return 1.0 / (2.0 + np.cos(2.0 * np.pi * x))
+
+
+def random_vectors(n, count, seed):
+    """count standard-normal vectors of length n, [count][n]."""
+    return np.random.default_rng(seed).standard_normal((count, n))

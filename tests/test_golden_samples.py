@@ -82,3 +82,31 @@ def test_adjoint_golden_metadata():
     assert g["P"] == 2068
     out = np.asarray(g["index"])
     assert len(out) == len(g["dJdf"]) == len(np.unique(out)) and out.max() < 3 * D * D
+
+
+def test_matrix_cases_golden():
+    """The stored exponentials of the paper's matrix test cases and of the
+    large circulant workloads (tests/golden/make_matrix_cases.py): the input
+    generators' stencils are the oracle's A_1 and A_2, the 70-point values
+    are the oracle's dense expm, and exp(tA) of a skew-Hermitian A conserves
+    the norm of the (real, unit-free) inputs."""
+    from oracle import matrix_cases as mc
+    with open(os.path.join(HERE, "golden", "matrix_cases.json")) as fh:
+        g = json.load(fh)
+    n = g["A1"]["n"]
+    assert inputs.advection_stencil(n) == mc.stencil_A1(n)
+    s_in, s_or = inputs.schroedinger_stencil(n), mc.stencil_A2(n)
+    assert s_in.keys() == s_or.keys() and all(abs(s_in[d] - s_or[d]) <= 1e-12 * abs(s_or[d]) for d in s_or)
+    assert np.array_equal(inputs.matrix_case_vector(n), mc.f0(mc.grid_A1(n)))
+    assert np.array_equal(inputs.matrix_case_vector(n, start=-1.0, length=2.0), mc.f0(mc.grid_A2(n)))
+    e1 = mc.expm_circulant(n, mc.stencil_A1(n), mc.f0(mc.grid_A1(n)))
+    assert np.max(np.abs(e1.real - np.asarray(g["A1"]["re"]))) <= 1e-13
+    e2 = mc.expm_circulant(n, mc.stencil_A2(n), mc.f0(mc.grid_A2(n)))
+    assert np.max(np.abs(e2 - (np.asarray(g["A2"]["re"]) + 1j * np.asarray(g["A2"]["im"])))) <= 1e-12
+    for name in ("advection", "schroedinger"):
+        c = g[name]
+        assert abs(c["t"] * c["rho"] - c["t_rho"]) <= 1e-12 * c["t_rho"]
+        f = inputs.random_vectors(c["n"], c["nrhs"], c["seed"])
+        assert abs(c["norm"] / np.linalg.norm(f) - 1.0) <= 1e-12
+        idx = np.asarray(c["index"])
+        assert len(idx) == len(c["re"]) == len(np.unique(idx)) and idx.max() < c["n"] * c["nrhs"]

@@ -32,6 +32,9 @@
  *   - Workspace: pass NULL/0 and the library allocates what it needs on the
  *     device and frees it before returning; or pass a device buffer of at
  *     least rexii_workspace_size() bytes (256-byte aligned).
+ *   - Environment: REXII_PROGRESS=<seconds> makes the Krylov slot engine
+ *     print a progress line on stderr at that interval (solves started,
+ *     slots working); REXII_TUNE_CACHE names the autotuner's cache file.
  */
 #ifndef REXII_H
 #define REXII_H
@@ -446,6 +449,25 @@ rexii_status rexii_apply_circulant(int32_t n, int32_t nstencil, const int32_t* o
                                    int32_t nrhs, const double* f, double* u, double t, double nu_im, int32_t scheme,
                                    int32_t M, const rexii_opts* opts, void* workspace, size_t ws_bytes,
                                    hipStream_t stream, rexii_report* rep);
+
+/* A refit of the coefficients of the Gaussian's rational approximation
+ * (Sec. 2.1, step 2; Appendix A prints the paper's own fit): R(x) in the
+ * symmetric form of eq. A(x,mu) with L terms and shift mu, fitted to
+ * psi_1(x) = (4 pi)^{-1/2} e^{-x^2/4} by least squares (eq. minl2approx) on
+ * K points chosen Leja fashion from n_candidates equally spaced values of
+ * [0, x_max] (x_1 = 0, then the candidate with the largest product of
+ * distances to the points chosen so far; psi_1 and R are even).  Householder
+ * QR and one refinement step with an extended-precision residual.  Host
+ * only, FP64.
+ *   a: host, 2(L+1) doubles, receives (Re a_l, Im a_l) for l = 0..L
+ *     (a_{-l} = conj(a_l)); points: host, K doubles or NULL (the chosen
+ *     points in order); max_err: NULL or receives max |psi_1 - R| over the
+ *     candidate grid.  With L = 24, the printed mu, x_max = 60, K = 200 the
+ *     fit matches the printed table's accuracy (about 1.5e-14).
+ * Errors: INVALID_ARG (1 <= L <= 64, mu != 0, x_max > 0,
+ * 2L+1 <= K <= n_candidates <= 2e7, or a rank-deficient system), OOM. */
+rexii_status rexii_fit_gaussian(int32_t L, double mu, double x_max, int32_t K, int32_t n_candidates, double* a,
+                                double* points, double* max_err);
 
 const char* rexii_last_error(void);
 

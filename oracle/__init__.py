@@ -29,6 +29,9 @@ spectral     the paper's own spectral LRSW operator and test scenarios
 matrix_cases the matrix test cases A_1, A_2 and f_0 of Sec. 3.2, circulant
              matrices, and REXII / the original REXI / REXIE (eq. REXIE, with
              the shift of Sec. 2.2) by dense solves and per Fourier mode
+refit        a refit of the Gaussian's rational approximation (Sec. 2.1 step
+             2, eqs. A(x,mu) and minl2approx): least squares on Leja-ordered
+             points
 
 Where a function has no independent pin in ``tests/`` its docstring says
 "parity unpinned".

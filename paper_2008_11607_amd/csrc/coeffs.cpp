@@ -21,6 +21,7 @@
 #include "rexii_internal.h"
 
 #include <cmath>
+#include <algorithm>
 #include <complex>
 #include <map>
 #include <mutex>
@@ -288,5 +289,170 @@ extern "C" rexii_status rexii_coeffs(double t, double rho, double h, double tol,
     }
   }
   if (kappa) *kappa = kappa_sum(w, h);
+  return clear_error();
+}
+
+// ---------------------------------------------------------------------------
+// A refit of the Gaussian's rational approximation (Sec. 2.1, step 2): the
+// symmetric form R(x) of eq. A(x,mu), linear in y = [a_0, Re a_1..Re a_L,
+// Im a_1..Im a_L], fitted by least squares (eq. minl2approx) on K points
+// taken from n_candidates equally spaced values of [0, x_max] one at a
+// time, Leja fashion: x_1 = 0, then the candidate with the largest product
+// of distances to the points so far (near-ties, within 1e-12 relative of
+// the log-product, go to the smallest x).  Householder QR, then one refinement
+// step with the residual in extended precision (the matrix is
+// ill-conditioned, ~1e12 at L = 24).
+// ---------------------------------------------------------------------------
+namespace rexii {
+namespace {
+
+// row of eq. A(x,mu) for one x
+void design_row(double x, double m, int L, double* row) {
+  const double x2 = x * x, m2 = m * m;
+  row[0] = m / (x2 + m2);
+  for (int l = 1; l <= L; ++l) {
+    const double l2 = double(l) * l;
+    const double den = x2 * x2 + 2.0 * (m2 - l2) * x2 + (m2 + l2) * (m2 + l2);
+    row[l] = 2.0 * m * (m2 + l2 + x2) / den;
+    row[L + l] = 2.0 * l * (m2 + l2 - x2) / den;
+  }
+}
+
+// Least squares min |G y - b| for G (m x n, row-major, m >= n) by Householder
+// QR: column k below the diagonal and the diagonal hold the reflector v_k
+// (H_k = I - beta_k v_k v_k^T), the rest of the upper triangle holds R, and
+// diag(R) is kept in rdiag.  The factorisation serves several right-hand
+// sides (qr_solve).
+struct QR {
+  int m, n;
+  std::vector<double> a;      // factored matrix, row-major
+  std::vector<double> beta;   // reflector scalars
+  std::vector<double> rdiag;  // diagonal of R
+};
+
+bool qr_factor(QR& q) {
+  const int m = q.m, n = q.n;
+  q.beta.assign(n, 0.0);
+  q.rdiag.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double norm = 0.0;
+    for (int i = k; i < m; ++i) norm = std::hypot(norm, q.a[size_t(i) * n + k]);
+    if (norm == 0.0) return false;
+    const double akk = q.a[size_t(k) * n + k];
+    const double alpha = (akk > 0.0) ? -norm : norm;
+    // v = x - alpha e1, stored in column k below and on the diagonal
+    const double v0 = akk - alpha;
+    q.a[size_t(k) * n + k] = v0;
+    double vnorm2 = v0 * v0;
+    for (int i = k + 1; i < m; ++i) vnorm2 += q.a[size_t(i) * n + k] * q.a[size_t(i) * n + k];
+    q.beta[k] = 2.0 / vnorm2;
+    for (int j = k + 1; j < n; ++j) {
+      double s = 0.0;
+      for (int i = k; i < m; ++i) s += q.a[size_t(i) * n + k] * q.a[size_t(i) * n + j];
+      s *= q.beta[k];
+      for (int i = k; i < m; ++i) q.a[size_t(i) * n + j] -= s * q.a[size_t(i) * n + k];
+    }
+    q.rdiag[k] = alpha;
+  }
+  return true;
+}
+
+std::vector<double> qr_solve(const QR& q, std::vector<double> b) {
+  const int m = q.m, n = q.n;
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int i = k; i < m; ++i) s += q.a[size_t(i) * n + k] * b[i];
+    s *= q.beta[k];
+    for (int i = k; i < m; ++i) b[i] -= s * q.a[size_t(i) * n + k];
+  }
+  std::vector<double> y(n, 0.0);
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int j = k + 1; j < n; ++j) s -= q.a[size_t(k) * n + j] * y[j];
+    y[k] = s / q.rdiag[k];
+  }
+  return y;
+}
+
+inline double psi_unit(double x) { return std::exp(-x * x / 4.0) / std::sqrt(4.0 * M_PI); }
+
+}  // namespace
+}  // namespace rexii
+
+extern "C" rexii_status rexii_fit_gaussian(int32_t L, double mu, double x_max, int32_t K, int32_t n_candidates,
+                                           double* a, double* points, double* max_err) {
+  using namespace rexii;
+  if (!a) return set_error(REXII_ERR_INVALID_ARG, "rexii_fit_gaussian: a is NULL");
+  if (L < 1 || L > 64 || !(mu != 0.0) || !std::isfinite(mu) || !(x_max > 0.0) || !std::isfinite(x_max))
+    return set_error(REXII_ERR_INVALID_ARG, "rexii_fit_gaussian: need 1 <= L <= 64, mu != 0, x_max > 0");
+  const int ncol = 2 * L + 1;
+  if (K < ncol || n_candidates < K || n_candidates > 20000000)
+    return set_error(REXII_ERR_INVALID_ARG, "rexii_fit_gaussian: need 2L+1 <= K <= n_candidates <= 2e7");
+  try {
+    // Leja points on the candidate grid
+    std::vector<double> cand(n_candidates), logp(n_candidates, 0.0);
+    for (int i = 0; i < n_candidates; ++i) cand[i] = x_max * double(i) / double(n_candidates - 1);
+    std::vector<double> pts;
+    pts.reserve(K);
+    pts.push_back(cand[0]);
+    for (int k = 1; k < K; ++k) {
+      const double last = pts.back();
+      double bv = -INFINITY;
+      for (int i = 0; i < n_candidates; ++i) {
+        logp[i] += std::log(std::fabs(cand[i] - last));   // -inf at chosen points
+        bv = std::max(bv, logp[i]);
+      }
+      if (!std::isfinite(bv)) return set_error(REXII_ERR_INVALID_ARG, "rexii_fit_gaussian: too few distinct candidates");
+      // mirror-image candidates tie exactly: values within 1e-12 (relative)
+      // of the largest count as ties, which go to the smallest x
+      const double cut = bv - 1e-12 * std::max(1.0, std::fabs(bv));
+      int best = 0;
+      while (logp[best] < cut) ++best;
+      pts.push_back(cand[best]);
+    }
+    QR q;
+    q.m = K;
+    q.n = ncol;
+    q.a.resize(size_t(K) * ncol);
+    std::vector<double> G(size_t(K) * ncol), b(K);
+    for (int k = 0; k < K; ++k) {
+      design_row(pts[k], mu, L, &G[size_t(k) * ncol]);
+      b[k] = psi_unit(pts[k]);
+    }
+    q.a = G;
+    if (!qr_factor(q)) return set_error(REXII_ERR_INVALID_ARG, "rexii_fit_gaussian: rank-deficient system");
+    std::vector<double> y = qr_solve(q, b);
+    // one refinement step: r = b - G y in extended precision
+    std::vector<double> r(K);
+    for (int k = 0; k < K; ++k) {
+      long double s = b[k];
+      for (int j = 0; j < ncol; ++j) s -= (long double)G[size_t(k) * ncol + j] * (long double)y[j];
+      r[k] = double(s);
+    }
+    const std::vector<double> dy = qr_solve(q, r);
+    for (int j = 0; j < ncol; ++j) y[j] += dy[j];
+    a[0] = y[0];
+    a[1] = 0.0;
+    for (int l = 1; l <= L; ++l) {
+      a[2 * l] = y[l];
+      a[2 * l + 1] = y[L + l];
+    }
+    if (points)
+      for (int k = 0; k < K; ++k) points[k] = pts[k];
+    if (max_err) {
+      // largest |psi_1 - R| over the candidate grid (both are even)
+      std::vector<double> row(ncol);
+      double e = 0.0;
+      for (int i = 0; i < n_candidates; ++i) {
+        design_row(cand[i], mu, L, row.data());
+        double s = 0.0;
+        for (int j = 0; j < ncol; ++j) s += row[j] * y[j];
+        e = std::max(e, std::fabs(s - psi_unit(cand[i])));
+      }
+      *max_err = e;
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(REXII_ERR_OOM, "rexii_fit_gaussian: host allocation failed");
+  }
   return clear_error();
 }

@@ -845,6 +845,11 @@ struct Engine {
       build_graph<T>();
     }
     const auto w0 = std::chrono::steady_clock::now();
+    // $REXII_PROGRESS = seconds: a progress line on stderr at that interval
+    // (long calls, e.g. large batches, report how far the queue has got)
+    double every = 0.0;
+    if (const char* pv = std::getenv("REXII_PROGRESS")) every = std::atof(pv);
+    auto last = w0;
     // enough replays for every solve to run to its iteration cap in turn
     const int64_t per_slot = (int64_t(z.S) + z.B - 1) / z.B;
     const int64_t max_replays = per_slot * (int64_t(max_cap) / chunk + 8) + 8;
@@ -872,6 +877,15 @@ struct Engine {
         HIPCHK(hipStreamSynchronize(st));
       }
       if (hcount[0] == 0) break;
+      if (every > 0.0) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - last).count() >= every) {
+          last = now;
+          std::fprintf(stderr, "rexii: %d of %d solves started, %d slots working, %.0f s\n", hcount[1], z.S,
+                       hcount[0], std::chrono::duration<double>(now - w0).count());
+          std::fflush(stderr);
+        }
+      }
     }
     stats.resize(z.S);
     read_to_host(stats.data(), e.stats, z.S * sizeof(SolveStat), st);

@@ -70,7 +70,7 @@ EXPORTS = ["rexii_default_opts", "rexii_coeffs", "rexii_rho", "rexii_workspace_s
            "rexii_shifted_solve", "rexii_apply_fourier", "rexii_fourier_workspace_size",
            "rexii_apply_multishift", "rexii_multishift_workspace_size", "rexii_coeffs_rexi",
            "rexii_apply_fourier_noalloc", "rexii_apply_circulant", "rexii_circulant_workspace_size",
-           "rexii_last_error"]
+           "rexii_fit_gaussian", "rexii_last_error"]
 
 _lib = None
 
@@ -120,6 +120,8 @@ def load():
     lib.rexii_apply_circulant.argtypes = [i32, i32, vp, vp, i32, vp, vp, dbl, dbl, i32, i32, P(Opts), vp, sz, vp,
                                           P(Report)]
     lib.rexii_apply_circulant.restype = ctypes.c_int
+    lib.rexii_fit_gaussian.argtypes = [i32, dbl, dbl, i32, i32, vp, vp, P(dbl)]
+    lib.rexii_fit_gaussian.restype = ctypes.c_int
     lib.rexii_last_error.argtypes = []
     lib.rexii_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -444,6 +446,18 @@ def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
     st = lib.rexii_apply_batched(cnt, ops, fptr, uptr, tarr, ctypes.byref(o), *_ws_args(ws), _stream(), reps)
     _check(st, [r.as_dict() for r in reps])
     return us, [r.as_dict() for r in reps]
+
+
+def fit_gaussian(L=24, mu=-5.133333333333333, x_max=60.0, K=200, n_candidates=200001):
+    """Refit of the Gaussian's rational approximation (host, FP64): returns
+    (a: complex numpy array a_0..a_L, points, max_err)."""
+    a = np.zeros(2 * (L + 1))
+    pts = np.zeros(K)
+    err = ctypes.c_double()
+    _check(load().rexii_fit_gaussian(int(L), float(mu), float(x_max), int(K), int(n_candidates),
+                                     a.ctypes.data_as(ctypes.c_void_p), pts.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(err)))
+    return a[0::2] + 1j * a[1::2], pts, err.value
 
 
 CIRC_SCHEMES = {"rexii": 0, "rexi": 1, "rexie": 2}

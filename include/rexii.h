@@ -108,7 +108,14 @@ typedef struct rexii_opts {
     int32_t method;         /* 0: automatic (COCG on the constant-depth
                                Helmholtz, BiCGStab for a depth field);
                                1: BiCGStab on the flux form also for
-                               constant depth                              */
+                               constant depth;
+                               2: BiCGStab on the flux form preconditioned
+                               by the exact (FFT) inverse of the mean-depth
+                               operator with a damped shift, FP64
+                               (precision ignored), pole_batch slots (0 ->
+                               up to 32 within 24 GiB; < 0 as 0); not for
+                               rexii_shifted_solve.  Its workspace sizing
+                               creates rocFFT plans (needs the device)     */
     int32_t profile;        /* 1: launch the inner kernels one by one with
                                HIP events around each (fills the kernel
                                timing fields of the report); 0: replay them

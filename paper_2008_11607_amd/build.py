@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librexii.so")
 
-SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "circulant.hip", "solver.hip"]
+SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "circulant.hip", "precond.hip", "solver.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
@@ -15,7 +15,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 # rocFFT for the Fourier-space path
-LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib", "-pthread"]
+LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib", "-pthread", "-Wl,-z,defs"]
 
 
 def build(verbose=False):

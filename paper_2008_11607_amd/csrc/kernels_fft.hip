@@ -376,6 +376,44 @@ rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** in
   return REXII_OK;
 }
 
+// Batch of `batch` complex 2D transforms [batch][ny][nx], in place, FP64,
+// forward and inverse (unnormalised); cached per (device, nx, ny, batch).
+namespace {
+std::map<std::tuple<int, int, int, int>, FftPair> g_fft_c2c;
+}
+
+rexii_status fft_plans_c2c(int nx, int ny, int batch, size_t* work_bytes, void** fwd, void** inv) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(REXII_ERR_HIP, "hipGetDevice failed");
+  const rexii_status su = rocfft_ensure_setup();
+  if (su != REXII_OK) return su;
+  std::lock_guard<std::mutex> lk(g_fft_mu);
+  const auto key = std::make_tuple(dev, nx, ny, batch);
+  auto it = g_fft_c2c.find(key);
+  if (it == g_fft_c2c.end()) {
+    FftPair p;
+    const size_t len[2] = {size_t(nx), size_t(ny)};
+    rocfft_status s = rocfft_plan_create(&p.fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward,
+                                         rocfft_precision_double, 2, len, size_t(batch), nullptr);
+    if (s != rocfft_status_success) return set_error(REXII_ERR_HIP, fft_msg("rocfft_plan_create (c2c forward)", s));
+    s = rocfft_plan_create(&p.inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse,
+                           rocfft_precision_double, 2, len, size_t(batch), nullptr);
+    if (s != rocfft_status_success) {
+      rocfft_plan_destroy(p.fwd);
+      return set_error(REXII_ERR_HIP, fft_msg("rocfft_plan_create (c2c inverse)", s));
+    }
+    size_t w1 = 0, w2 = 0;
+    rocfft_plan_get_work_buffer_size(p.fwd, &w1);
+    rocfft_plan_get_work_buffer_size(p.inv, &w2);
+    p.work = w1 > w2 ? w1 : w2;
+    it = g_fft_c2c.emplace(key, p).first;
+  }
+  if (work_bytes) *work_bytes = it->second.work;
+  if (fwd) *fwd = it->second.fwd;
+  if (inv) *inv = it->second.inv;
+  return REXII_OK;
+}
+
 rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s) {
   rocfft_execution_info info = nullptr;
   rocfft_status st = rocfft_execution_info_create(&info);

@@ -39,6 +39,8 @@ double rho_bound_var(int nx, int ny, double g, double Hmax, double fc);
 // (REXII_ERR_INVALID_ARG when there are none): creating a plan allocates.
 rexii_status fft_plans(int nx, int ny, size_t* work_bytes, void** fwd, void** inv, bool create = true);
 rexii_status rocfft_ensure_setup();   // once per process, before any rocFFT plan
+// batch of complex 2D transforms [batch][ny][nx], in place, FP64
+rexii_status fft_plans_c2c(int nx, int ny, int batch, size_t* work_bytes, void** fwd, void** inv);
 rexii_status fft_execute(void* plan, void* in, void* out, void* work, size_t work_bytes, hipStream_t s);
 // Device address of the library's static scratch array on the current
 // device (REXII_STATIC_SCRATCH_BYTES bytes, 256-byte aligned; looked up once

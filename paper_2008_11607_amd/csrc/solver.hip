@@ -31,6 +31,7 @@
 #include "kernels.h"
 #include "kernels_fft.h"
 #include "kernels_lz.h"
+#include "precond.h"
 #include "rexii_internal.h"
 
 namespace rexii {
@@ -180,6 +181,51 @@ static void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t s
   std::memcpy(dst, pin, bytes);
 }
 
+// Axis symbols s(k) of a grid, x wavenumbers 0..nx/2 then y wavenumbers
+// 0..ny-1, formed once per (nx, ny, derivative) and kept (8 most recent),
+// with a pinned copy when the caller may allocate.
+struct SymTable {
+  std::vector<double> s;
+  double* pin = nullptr;
+  ~SymTable() {
+    if (pin) (void)hipHostFree(pin);
+  }
+};
+
+static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv, bool pinned) {
+  static std::mutex mu;
+  static std::deque<std::pair<std::tuple<int, int, int>, std::shared_ptr<const SymTable>>> cache;
+  const auto key = std::make_tuple(nx, ny, deriv);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto it = cache.begin(); it != cache.end(); ++it)
+      if (it->first == key && (!pinned || it->second->pin)) {
+        auto hit = *it;
+        cache.erase(it);
+        cache.push_front(hit);
+        return hit.second;
+      }
+  }
+  auto st = std::make_shared<SymTable>();
+  st->s.resize(size_t(nx / 2 + 1) + ny);
+  for (int k = 0; k <= nx / 2; ++k) st->s[k] = axis_symbol(k, nx, deriv);
+  for (int k = 0; k < ny; ++k) st->s[nx / 2 + 1 + k] = axis_symbol(k, ny, deriv);
+  if (pinned) {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&st->pin), st->s.size() * sizeof(double), hipHostMallocDefault));
+    std::memcpy(st->pin, st->s.data(), st->s.size() * sizeof(double));
+  }
+  std::shared_ptr<const SymTable> out = st;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = cache.begin(); it != cache.end(); ++it)
+    if (it->first == key) {
+      cache.erase(it);
+      break;
+    }
+  cache.push_front({key, out});
+  while (cache.size() > 8) cache.pop_back();
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // problem description
 // ---------------------------------------------------------------------------
@@ -287,7 +333,7 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
   pl.inner_eta = (o.precision == REXII_PREC_MIXED) ? o.inner_tol : 0.0;
   pl.has_vel = has_vel;
   pl.profile = (o.profile != 0);
-  pl.bicg = (op->H_field != nullptr) || (o.method == 1);
+  pl.bicg = (op->H_field != nullptr) || (o.method == 1) || (o.method == 2);
   pl.hmax = op->H_field ? hmax : op->H0;
   // the two poles of a term give conjugate systems only for the symmetric
   // constant-depth operator
@@ -300,6 +346,7 @@ static rexii_status build_plan(const rexii_swe_op* op, double t, const rexii_opt
     return set_error(REXII_ERR_INVALID_ARG, "the REXI scheme is available on the Fourier path only");
   if (o.precision != REXII_PREC_FP64 && o.precision != REXII_PREC_MIXED)
     return set_error(REXII_ERR_INVALID_ARG, "unknown precision");
+  if (o.method < 0 || o.method > 2) return set_error(REXII_ERR_INVALID_ARG, "unknown method");
   if (op->H_field && !(hmax > 0.0)) return set_error(REXII_ERR_INVALID_ARG, "variable depth needs max H > 0");
   pl.rho = (o.rho > 0.0) ? o.rho
            : (op->H_field ? rho_bound_var(op->nx, op->ny, op->g, hmax, op->f_cor)
@@ -1009,7 +1056,12 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     // COCG: a pass reads x, r, p and writes them back (6 complex values per
     // point); BiCGStab: an iteration moves 13 complex values and reads the
     // depth three times
-    const double per_pt = en->z.method == 1 ? 13.0 * eb + 3.0 * (eb == 8.0 ? 4.0 : 8.0) : 6.0 * eb;
+    // preconditioned BiCGStab (method 2, FP64): the vector kernels move 26
+    // complex values and read the depth twice per point and iteration, the
+    // four transforms read and write their vector once each (8 more)
+    const double per_pt = en->z.method == 2   ? 34.0 * 16.0 + 2.0 * 8.0
+                          : en->z.method == 1 ? 13.0 * eb + 3.0 * (eb == 8.0 ? 4.0 : 8.0)
+                                              : 6.0 * eb;
     rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * per_pt;
     rep->slots = en->z.B;
     rep->tile_rows = en->z.th;
@@ -1120,6 +1172,26 @@ static rexii_status sizing_plan(const JobItem& it, const rexii_opts& o, Problem&
   return REXII_OK;
 }
 
+// Preconditioned solver (method 2): slot count and device bytes.
+constexpr double kPcDampHost = 0.2;   // damping of the preconditioner's shift (precond.hip)
+constexpr int kPcCheck = 1;           // iterations between host checks (most solves take 2-3)
+
+static int pc_slots(size_t points, size_t nsolves, int requested) {
+  const size_t per_slot = 8 * points * 16;
+  const size_t budget = size_t(24) << 30;
+  size_t B = requested > 0 ? size_t(requested) : size_t(32);
+  B = std::min(B, std::max<size_t>(1, budget / per_slot));
+  B = std::min(B, std::max<size_t>(1, nsolves));
+  return int(std::max<size_t>(1, B));
+}
+
+static size_t pc_engine_bytes(int nx, int ny, int B, size_t fft_work) {
+  const size_t n = size_t(nx) * ny;
+  return 8 * al256(size_t(B) * n * 16) + al256(size_t(B) * pc_blocks() * 8 * sizeof(double)) +
+         al256(size_t(B) * sizeof(PcSlot)) + al256((size_t(nx / 2 + 1) + ny) * 8) + al256(pc_blocks() * 8) +
+         al256(fft_work) + 4096;
+}
+
 static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opts& o, bool keep, size_t extra,
                               size_t* bytes) {
   std::vector<Problem> pbs(items.size());
@@ -1132,6 +1204,19 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
     if (st != REXII_OK) return st;
     ptrs.push_back(&pbs[i]);
     b += problem_bytes(pbs[i]);
+  }
+  if (!ptrs.empty() && o.method == 2) {
+    // the preconditioned solver: one problem at a time, the largest engine
+    size_t eb = 0;
+    for (Problem* p : ptrs) {
+      const int B = pc_slots(p->n(), p->pl.solves.size(), o.pole_batch);
+      size_t work = 0;
+      const rexii_status fs = fft_plans_c2c(p->pl.nx, p->pl.ny, B, &work, nullptr, nullptr);
+      if (fs != REXII_OK) return fs;
+      eb = std::max(eb, pc_engine_bytes(p->pl.nx, p->pl.ny, B, work));
+    }
+    *bytes = b + eb;
+    return REXII_OK;
   }
   if (!ptrs.empty()) {
     const EngineSize z = engine_size(ptrs, o.pole_batch, o.precision, o.tile_rows);
@@ -1150,6 +1235,11 @@ static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opt
 // (its biggest candidate slot count for every tile height it tries).
 static int tuner_cap_slots(const std::vector<JobItem>& items, const rexii_opts& o);
 static rexii_status items_bytes(const std::vector<JobItem>& items, const rexii_opts& o, size_t* bytes) {
+  if (o.method == 2) {   // the preconditioned solver takes no autotuning
+    rexii_opts o2 = o;
+    o2.pole_batch = std::max(0, o.pole_batch);
+    return job_bytes(items, o2, false, 0, bytes);
+  }
   if (o.pole_batch >= 0) return job_bytes(items, o, false, 0, bytes);
   const bool bicg = o.method == 1;
   std::vector<int> ths = (bicg && o.tile_rows == 0) ? std::vector<int>{32, 16} : std::vector<int>{o.tile_rows};
@@ -1242,6 +1332,219 @@ static void rerun_fp64(Job& jb, Arena& ar, size_t mark, double2* yout) {
   en.solve_seconds += er.solve_seconds;
 }
 
+// ---------------------------------------------------------------------------
+// FFT-preconditioned BiCGStab (opts.method = 2; precond.hip): the flux-form
+// height equation of every pole, right-preconditioned by the exact inverse
+// of the mean-depth operator with a damped shift, all FP64.  B slots run
+// together; the host checks the slots after every iteration, takes the true
+// residual of those whose recurrence met the stop test (or hit the cap, or
+// broke down), finishes them (accumulating Re(c_j x) in queue order of
+// finishing) or restarts them from that residual, and refills free slots
+// from the queue (most expensive first).
+// ---------------------------------------------------------------------------
+static void run_pc(Job& jb, Arena& ar) {
+  hipStream_t st = jb.st;
+  Engine* en = new Engine(st);
+  jb.en = en;
+  en->z.method = 2;
+  en->z.th = 0;
+  en->precision = REXII_PREC_FP64;
+  size_t total = 0;
+  for (Problem* p : jb.ptrs) total += p->pl.solves.size();
+  en->z.S = int(total);
+  en->stats.assign(total, SolveStat{});
+  en->solve_inst.assign(total, 0);
+  en->solve_index.assign(total, 0);
+  en->retried.assign(total, 0);
+  en->plans.clear();
+  for (Problem* p : jb.ptrs) en->plans.push_back(&p->pl);
+  en->inst_points.clear();
+  for (Problem* p : jb.ptrs) en->inst_points.push_back(p->n());
+  const auto w0 = std::chrono::steady_clock::now();
+  double every = 0.0;   // $REXII_PROGRESS: seconds between progress lines
+  if (const char* pv = std::getenv("REXII_PROGRESS")) every = std::atof(pv);
+  auto last = w0;
+  int finished = 0;
+  int qbase = 0;   // queue positions of the problems' solves follow each other
+  for (size_t ip = 0; ip < jb.ptrs.size(); ++ip) {
+    Problem& pb = *jb.ptrs[ip];
+    const Plan& pl = pb.pl;
+    const int nx = pl.nx, ny = pl.ny;
+    const size_t n = pb.n();
+    const int S = int(pl.solves.size());
+    const int B = pc_slots(n, size_t(S), jb.o.pole_batch);
+    en->z.B = std::max(en->z.B, B);
+    size_t work = 0;
+    void *fwd = nullptr, *inv = nullptr;
+    const rexii_status fs = fft_plans_c2c(nx, ny, B, &work, &fwd, &inv);
+    if (fs != REXII_OK) throw HipError{fs, g_err};
+    const size_t mark = ar.mark();
+    PcVec w;
+    w.B = B;
+    double2** vecs[8] = {&w.x, &w.r, &w.rh, &w.p, &w.v, &w.ph, &w.sh, &w.t};
+    for (double2** v : vecs) *v = ar.take<double2>(size_t(B) * n);
+    w.part = ar.take<double>(size_t(B) * pc_blocks() * 8);
+    w.slots = ar.take<PcSlot>(B);
+    double* sym = ar.take<double>(size_t(nx / 2 + 1) + ny);
+    double* hpart = ar.take<double>(pc_blocks());
+    void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
+    // axis symbols and the mean depth
+    const std::shared_ptr<const SymTable> symt = symbol_table(nx, ny, 0, true);
+    HIPCHK(hipMemcpyAsync(sym, symt->pin, symt->s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_pc_sum(pb.H, n, hpart, st);
+    std::vector<double> hp(pc_blocks());
+    read_to_host(hp.data(), hpart, hp.size() * sizeof(double), st);
+    double hsum = 0.0;
+    for (double v : hp) hsum += v;
+    PcProb pr;
+    pr.nx = nx;
+    pr.ny = ny;
+    pr.cx = 0.25 * double(nx) * nx;
+    pr.cy = 0.25 * double(ny) * ny;
+    pr.cxy = 0.25 * double(nx) * ny;
+    pr.hbar = hsum / double(n);
+    pr.H = pb.H;
+    pr.eta0 = pb.f;
+    pr.D0 = pl.has_vel ? pb.DZ : nullptr;
+    pr.Z0 = pl.has_vel ? pb.DZ + n : nullptr;
+    pr.sx = sym;
+    // queue: most expensive first
+    std::vector<int> order(S);
+    for (int k = 0; k < S; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return pl.solves[a].cost > pl.solves[b].cost; });
+    std::vector<PcSlot> hs(B);
+    std::vector<int> slot_solve(B, -1), slot_q(B, -1);
+    std::vector<double> prev_true(B, 0.0);
+    std::memset(static_cast<void*>(hs.data()), 0, sizeof(PcSlot) * B);
+    const int cap = (jb.o.max_iter > 0) ? jb.o.max_iter : 5000;
+    int next = 0;
+    auto assign = [&](int b) {
+      const int k = order[next];
+      const SolveDesc& d = pl.solves[k];
+      PcSlot& q = hs[b];
+      std::memset(static_cast<void*>(&q), 0, sizeof(q));
+      q.zeta = to_d2(d.zeta);
+      q.gamma = to_d2(d.gamma);
+      q.sc = to_d2(d.sc);
+      q.a1 = to_d2(d.a1);
+      q.a2 = to_d2(d.a2);
+      const double damp = kPcDampHost * std::fabs(d.zeta.real()) * (d.zeta.imag() >= 0.0 ? 1.0 : -1.0);
+      q.sigma = make_double2(d.zeta.real(), d.zeta.imag() + damp);
+      q.rho = q.alpha = q.omega = make_double2(1.0, 0.0);
+      q.beta = make_double2(0.0, 0.0);
+      q.tol2 = d.tol * d.tol;
+      q.ref2 = d.ref2 > 0.0 ? d.ref2 : 0.0;
+      q.state = kPcStart;
+      q.max_it = cap;
+      slot_solve[b] = k;
+      slot_q[b] = qbase + next;
+      prev_true[b] = 0.0;
+      en->solve_inst[qbase + next] = int(ip);
+      en->solve_index[qbase + next] = k;
+      ++next;
+    };
+    int live = 0;
+    for (int b = 0; b < B && next < S; ++b) {
+      assign(b);
+      ++live;
+    }
+    HIPCHK(hipMemcpyAsync(w.slots, hs.data(), sizeof(PcSlot) * B, hipMemcpyHostToDevice, st));
+    int64_t iters = 0;
+    while (live > 0) {
+      for (int c = 0; c < kPcCheck; ++c) {
+        launch_pc_dir(w, pr, st);
+        launch_pc_scalars(w, 0, st);
+        rexii_status e1 = fft_execute(fwd, w.ph, w.ph, wk, work, st);
+        if (e1 != REXII_OK) throw HipError{e1, g_err};
+        launch_pc_scale(w.ph, w, pr, st);
+        e1 = fft_execute(inv, w.ph, w.ph, wk, work, st);
+        if (e1 != REXII_OK) throw HipError{e1, g_err};
+        launch_pc_matvec(w.ph, w.v, 0, w, pr, st);
+        launch_pc_scalars(w, 1, st);
+        launch_pc_s(w, pr, st);
+        e1 = fft_execute(fwd, w.sh, w.sh, wk, work, st);
+        if (e1 != REXII_OK) throw HipError{e1, g_err};
+        launch_pc_scale(w.sh, w, pr, st);
+        e1 = fft_execute(inv, w.sh, w.sh, wk, work, st);
+        if (e1 != REXII_OK) throw HipError{e1, g_err};
+        launch_pc_matvec(w.sh, w.t, 1, w, pr, st);
+        launch_pc_scalars(w, 2, st);
+        launch_pc_xr(w, pr, st);
+        launch_pc_scalars(w, 3, st);
+        ++iters;
+      }
+      HIPCHK(hipGetLastError());
+      read_to_host(hs.data(), w.slots, sizeof(PcSlot) * B, st);
+      if (every > 0.0) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - last).count() >= every) {
+          last = now;
+          std::fprintf(stderr, "rexii: %d of %d solves finished, %d slots working, %.0f s\n", finished, en->z.S,
+                       live, std::chrono::duration<double>(now - w0).count());
+          std::fflush(stderr);
+        }
+      }
+      bool any_check = false;
+      for (int b = 0; b < B; ++b)
+        if (hs[b].state == kPcConv || hs[b].state == kPcCap || hs[b].state == kPcBreak) any_check = true;
+      if (!any_check) continue;
+      launch_pc_resid(w, pr, st);
+      HIPCHK(hipGetLastError());
+      read_to_host(hs.data(), w.slots, sizeof(PcSlot) * B, st);
+      bool changed = false;
+      for (int b = 0; b < B; ++b) {
+        PcSlot& q = hs[b];
+        if (q.state != kPcConv && q.state != kPcCap && q.state != kPcBreak) continue;
+        const SolveDesc& d = pl.solves[slot_solve[b]];
+        SolveStat& ss = en->stats[slot_q[b]];
+        ss.it_total = q.it;
+        ss.rounds += 1;
+        ss.rn2 = q.rn2;
+        ss.bn2 = q.bn2;
+        const bool ok = q.rn2 <= q.stop2;
+        const bool stalled = prev_true[b] > 0.0 && q.rn2 > 0.25 * prev_true[b];
+        int fin = -1;
+        if (ok) {
+          fin = kDone;
+        } else if (q.state == kPcCap) {
+          fin = kFailMaxIter;
+        } else if (stalled) {
+          fin = kDone;
+          ss.stagnated = 1;
+        } else if (q.state == kPcBreak && ss.rounds > 8) {
+          fin = kFailBreakdown;
+        }
+        if (fin < 0) {
+          // restart from the true residual (r, rh, p set by the residual kernel)
+          prev_true[b] = q.rn2;
+          q.state = kPcIter;
+          changed = true;
+          continue;
+        }
+        ss.status = fin;
+        launch_pc_accum(w, b, to_d2(d.c0), to_d2(d.c1), to_d2(d.c2), pb.A, pr, st);
+        q.state = kPcIdle;
+        slot_solve[b] = -1;
+        --live;
+        ++finished;
+        changed = true;
+        if (next < S) {
+          assign(b);
+          ++live;
+        }
+      }
+      if (changed) HIPCHK(hipMemcpyAsync(w.slots, hs.data(), sizeof(PcSlot) * B, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    en->launches += iters;
+    qbase += S;
+    ar.reset(mark);
+  }
+  en->solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+}
+
 // Prepares every problem (input checks, div/curl, plans) and runs the engine
 // (only max_chunks chunks if > 0; returns their time in ms).
 static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
@@ -1276,7 +1579,7 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
   for (const JobItem& it : jb.items) any_depth_field = any_depth_field || (!it.skip && it.op->H_field);
   // one engine runs one method: a depth field anywhere puts every problem
   // of the call on the flux-form path
-  if (any_depth_field) jb.o.method = 1;
+  if (any_depth_field && jb.o.method == 0) jb.o.method = 1;
   for (size_t i = 0; i < ni; ++i) {
     JobItem& it = jb.items[i];
     if (it.skip) continue;
@@ -1293,12 +1596,12 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
       pb.H = it.op->H_field;
       launch_prep_vh(it.f, it.op->H_field, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, hp, jb.st);
     } else {
-      if (jb.o.method == 1) {
+      if (jb.o.method >= 1) {
         launch_fill_value(hconst, n, it.op->H0, jb.st);
         pb.H = hconst;
       }
       launch_prep(it.f, it.op->nx, it.op->ny, pb.DZ, pb.DZ + n, dflags + i, jb.st);
-      if (jb.o.method == 1) {
+      if (jb.o.method >= 1) {
         // flux form: D_H = H0 div, Z_H = H0 curl
         launch_scale1(pb.DZ, 2 * n, it.op->H0, jb.st);
       }
@@ -1347,6 +1650,10 @@ static double run_job(Job& jb, Arena& ar, int max_chunks = 0) {
     jb.ptrs.push_back(&jb.pbs[i]);
   }
   if (jb.ptrs.empty()) return 0.0;
+  if (jb.o.method == 2) {
+    run_pc(jb, ar);
+    return 0.0;
+  }
   const EngineSize z = engine_size(jb.ptrs, jb.o.pole_batch, jb.o.precision, jb.o.tile_rows);
   double2* yout = jb.keep ? ar.take<double2>(size_t(z.S) * z.cap) : nullptr;
   const size_t mark = ar.mark();   // the engine's memory starts here
@@ -1646,8 +1953,14 @@ static rexii_status run_items(std::vector<JobItem> items, const rexii_opts* opts
       it.hmax = device_hmax(it.op->H_field, size_t(it.op->nx) * it.op->ny, st);
       any_depth_field = true;
     }
+    if (jb.o.method == 2) {
+      // the preconditioned solver: FP64, its own slot count, no kept solutions
+      if (jb.keep) return set_error(REXII_ERR_INVALID_ARG, "method 2 does not return resolvents (explicit shifts)");
+      jb.o.precision = REXII_PREC_FP64;
+      if (jb.o.pole_batch < 0) jb.o.pole_batch = 0;
+    }
     rexii_opts osz = jb.o;
-    if (any_depth_field) osz.method = 1;
+    if (any_depth_field && osz.method == 0) osz.method = 1;
     if (jb.o.pole_batch < 0) {
       int th = 0;
       const int B = autotune_slots(jb.items, osz, st, &th, ws, ws_bytes);
@@ -1883,51 +2196,6 @@ static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme, 
   std::lock_guard<std::mutex> lk(mu);
   for (auto it = cache.begin(); it != cache.end(); ++it)
     if (it->first == key) {   // an entry without the pinned copy is replaced
-      cache.erase(it);
-      break;
-    }
-  cache.push_front({key, out});
-  while (cache.size() > 8) cache.pop_back();
-  return out;
-}
-
-// Axis symbols s(k) of a grid, x wavenumbers 0..nx/2 then y wavenumbers
-// 0..ny-1, formed once per (nx, ny, derivative) and kept (8 most recent),
-// with a pinned copy when the caller may allocate.
-struct SymTable {
-  std::vector<double> s;
-  double* pin = nullptr;
-  ~SymTable() {
-    if (pin) (void)hipHostFree(pin);
-  }
-};
-
-static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv, bool pinned) {
-  static std::mutex mu;
-  static std::deque<std::pair<std::tuple<int, int, int>, std::shared_ptr<const SymTable>>> cache;
-  const auto key = std::make_tuple(nx, ny, deriv);
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    for (auto it = cache.begin(); it != cache.end(); ++it)
-      if (it->first == key && (!pinned || it->second->pin)) {
-        auto hit = *it;
-        cache.erase(it);
-        cache.push_front(hit);
-        return hit.second;
-      }
-  }
-  auto st = std::make_shared<SymTable>();
-  st->s.resize(size_t(nx / 2 + 1) + ny);
-  for (int k = 0; k <= nx / 2; ++k) st->s[k] = axis_symbol(k, nx, deriv);
-  for (int k = 0; k < ny; ++k) st->s[nx / 2 + 1 + k] = axis_symbol(k, ny, deriv);
-  if (pinned) {
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&st->pin), st->s.size() * sizeof(double), hipHostMallocDefault));
-    std::memcpy(st->pin, st->s.data(), st->s.size() * sizeof(double));
-  }
-  std::shared_ptr<const SymTable> out = st;
-  std::lock_guard<std::mutex> lk(mu);
-  for (auto it = cache.begin(); it != cache.end(); ++it)
-    if (it->first == key) {
       cache.erase(it);
       break;
     }
@@ -2620,7 +2888,7 @@ rexii_status rexii_workspace_size(const rexii_swe_op* op, const rexii_opts* opts
     } catch (const HipError& he) {
       return set_error(he.st, he.msg);
     }
-    o.method = 1;
+    if (o.method == 0) o.method = 1;
     size_t b = 0;
     try {
       st = items_bytes({it}, o, &b);
@@ -2679,7 +2947,7 @@ rexii_status rexii_batched_workspace_size(int32_t count, const rexii_swe_op* ops
       any = true;
       if (ops[i].H_field) {
         items[i].hmax = device_hmax(ops[i].H_field, size_t(ops[i].nx) * ops[i].ny, nullptr);
-        o.method = 1;
+        if (o.method == 0) o.method = 1;
       }
     }
     if (!any) {

@@ -167,7 +167,7 @@ def make_opts(h=None, tol=None, precision="fp64", max_iter=None, m0=None, rho=No
     if profile is not None:
         o.profile = int(profile)
     if method is not None:
-        o.method = {"auto": 0, "cocg": 0, "bicgstab": 1}.get(method, method)
+        o.method = {"auto": 0, "cocg": 0, "bicgstab": 1, "precond": 2}.get(method, method)
     if tile_rows is not None:
         o.tile_rows = int(tile_rows)
     if scheme is not None:

@@ -1,0 +1,127 @@
+"""The FFT-preconditioned shifted solves (opts.method = 2) against the
+oracle: dense exponentials of the flux-form operator on small grids, the
+Chebyshev-Bessel series on larger ones, the exact exponential for constant
+depth, and the slot engine's BiCGStab on the same problems."""
+import numpy as np
+import pytest
+
+from oracle import coeffs as oc
+from oracle import expm_modes as em
+from oracle import lrsw, rexii_modes as rm, varh
+from paper_2008_11607_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2008_11607_amd import rexii
+    rexii.load()
+    return rexii
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("nx,ny,velocity,slots", [(16, 16, False, 0), (24, 20, True, 0), (24, 20, True, 3)])
+def test_precond_vs_dense_expm(rx, nx, ny, velocity, slots):
+    # depth field, with and without an initial velocity; 3 slots: most slots
+    # take several solves in turn
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, g=1.0, fc=10.0, Hfield=Hf)
+    t = 30.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=5, velocity=velocity)
+    print(f"precond dense {nx}x{ny} velocity={velocity} slots={slots}", flush=True)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, Hfield=_dev(Hf), method="precond", pole_batch=slots)
+    assert rep["not_converged"] == 0 and 0.0 < rep["err_bound"] <= 1e-10
+    assert sum(rep["iter_hist"]) == rep["solves"] == rep["P"]
+    if slots:
+        assert rep["slots"] == slots
+    assert em.rel_l2(u.cpu().numpy(), em.expm_dense(op, f, t)) <= 1e-10
+
+
+@pytest.mark.parametrize("D,trho", [(64, 100.0), (96, 300.0)])
+def test_precond_vs_chebyshev(rx, D, trho):
+    Hf = inputs.variable_depth(D)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = trho / lrsw.rho(op)
+    f = inputs.gaussian_bumps(D, nbumps=16, seed=50)
+    print(f"precond {D}^2 t rho {trho}", flush=True)
+    u, rep = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf), method="precond")
+    ub, repb = rx.apply(_dev(f), t, fc=20.0, Hfield=_dev(Hf))
+    ref = varh.chebyshev_expm(op, f, t)
+    un = u.cpu().numpy()
+    print(f"  iterations {rep['total_iters']} (BiCGStab slot engine {repb['total_iters']}), "
+          f"rel-L2 {em.rel_l2(un, ref):.2e}", flush=True)
+    assert rep["not_converged"] == 0 and rep["err_bound"] <= 1e-10
+    assert em.rel_l2(un, ref) <= 1e-10
+    assert em.rel_l2(un, ub.cpu().numpy()) <= 1e-10
+    assert abs(varh.w_energy(op, un) / varh.w_energy(op, f) - 1.0) <= 1e-10
+    # the preconditioner cuts the iterations
+    assert rep["total_iters"] * 4 <= repb["total_iters"]
+
+
+def test_precond_constant_depth(rx):
+    # constant depth through the flux form: the preconditioner is the exact
+    # inverse (up to its damping), against the oracle's exact approximant
+    op = lrsw.LRSW(64, 48, g=1.3, H=0.8, fc=7.0)
+    t = 80.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(64, 48, nbumps=4, seed=6, velocity=True)
+    u, rep = rx.apply(_dev(f), t, g=1.3, fc=7.0, H=0.8, method="precond")
+    c = oc.api_coeffs(t, lrsw.rho(op), h=0.5, tol=1e-10)
+    assert em.rel_l2(u.cpu().numpy(), rm.rexii_spectral(op, f, t, c["z"], c["w"])) <= 1e-10
+    assert em.rel_l2(u.cpu().numpy(), em.expm_closed_real(op, f, t)) <= 1e-10
+    assert rep["max_iters"] <= 40
+
+
+def test_precond_batched_and_workspace(rx):
+    import torch
+    D = 48
+    Hf = inputs.variable_depth(D)
+    Hd = _dev(Hf)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = 60.0 / lrsw.rho(op)
+    fs = [inputs.gaussian_bumps(D, nbumps=4, seed=70 + k) for k in range(3)]
+    us, reps = rx.apply_batched([_dev(f) for f in fs], [t, 0.5 * t, t], fc=20.0, Hfield=Hd, method="precond")
+    for f, tt, u, r in zip(fs, [t, 0.5 * t, t], us, reps):
+        assert r["not_converged"] == 0
+        assert em.rel_l2(u.cpu().numpy(), varh.chebyshev_expm(op, f, tt)) <= 1e-10
+    # a workspace one 256-byte block too small is refused
+    import ctypes
+    lib = rx.load()
+    ops = (rx.SweOp * 1)(rx.make_op(D, D, fc=20.0, Hfield=Hd))
+    o = rx.make_opts(method="precond")
+    nb = ctypes.c_size_t()
+    assert lib.rexii_batched_workspace_size(1, ops, (ctypes.c_double * 1)(t), ctypes.byref(o), ctypes.byref(nb)) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    fd = _dev(fs[0])
+    u = torch.empty_like(fd)
+    st = lib.rexii_apply(ctypes.byref(ops[0]), ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(u.data_ptr()), t,
+                         ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nb.value - 8192, rx._stream(), None)
+    assert st == -7
+    # shifted solves are not offered by this method
+    with pytest.raises(rx.RexiiError) as e:
+        rx.shifted_solve(fd, t, np.array([0.5 - 1j]), fc=20.0, Hfield=Hd, method="precond")
+    assert e.value.status == -1
+
+
+def test_precond_tolerance_below_floor(rx):
+    # tol 1e-15 is below the FP64 residual floor: NOT_CONVERGED with the
+    # achieved bound, and the result still written
+    import torch
+    nx, ny = 24, 20
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, fc=10.0, Hfield=Hf)
+    t = 40.0 / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=3, seed=9)
+    fd = _dev(f)
+    u = torch.full_like(fd, float("nan"))
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(fd, t, fc=10.0, Hfield=_dev(Hf), method="precond", tol=1e-15, out=u)
+    assert e.value.status == -3
+    assert e.value.report["err_bound"] > 1e-15
+    assert em.rel_l2(u.cpu().numpy(), em.expm_dense(op, f, t)) <= max(e.value.report["err_bound"], 1e-12)

@@ -11,7 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2008_11607_amd", "csrc")
-SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "circulant.hip",
+SOURCES = ["coeffs.cpp", "kernels.hip", "kernels_vh.hip", "kernels_fft.hip", "kernels_lz.hip", "circulant.hip", "precond.hip",
            "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # host-side sanitizers only: each -fsanitize= goes to the host compilation

@@ -124,7 +124,8 @@ def case2048(rx):
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("path,precision,tol,bar", [("krylov", "mixed", 1e-6, 1e-6), ("krylov", "fp64", 1e-10, 1e-10),
-                                                    ("multishift", "fp64", 1e-10, 1e-10)])
+                                                    ("multishift", "fp64", 1e-10, 1e-10),
+                                                    ("precond", "fp64", 1e-10, 1e-10)])
 def test_varh_2048_full_field(rx, case2048, path, precision, tol, bar):
     """Full pole sum (P ~ 470) at the real 2048^2 shape, every output value
     against the oracle, in the plain and the W-norm."""
@@ -132,8 +133,9 @@ def test_varh_2048_full_field(rx, case2048, path, precision, tol, bar):
     rho = rx.rho(g["D"], g["D"], fc=g["f_c"], Hfield=Hd)
     assert abs(rho - g["rho"]) <= 1e-12 * rho
     print(f"2048^2 depth field {path} {precision}", flush=True)
-    if path == "krylov":
-        u, rep = rx.apply(_dev(f), t, fc=g["f_c"], Hfield=Hd, precision=precision, tol=tol)
+    if path in ("krylov", "precond"):
+        u, rep = rx.apply(_dev(f), t, fc=g["f_c"], Hfield=Hd, precision=precision, tol=tol,
+                          method=("precond" if path == "precond" else None))
         assert rep["not_converged"] == 0 and rep["err_bound"] <= tol
     else:
         u, rep = rx.apply_multishift(_dev(f), t, fc=g["f_c"], Hfield=Hd, tol=tol)
@@ -188,3 +190,34 @@ def test_varh_autotune_picks_tile(rx, tmp_path, monkeypatch):
     assert (rep2["tile_rows"], rep2["slots"]) == (rep["tile_rows"], rep["slots"])
     ref = varh.chebyshev_expm(op, f, t)
     assert em.rel_l2(u.cpu().numpy(), ref) <= 1e-6 and em.rel_l2(u2.cpu().numpy(), ref) <= 1e-6
+
+
+def test_varh_autotune_in_caller_workspace(rx, tmp_path, monkeypatch):
+    """A caller workspace of rexii_workspace_size bytes (pole_batch < 0) holds
+    every candidate the autotuner runs and the tuned engine: the call
+    succeeds inside it, with an empty tuning cache, and agrees with the
+    library-allocated call."""
+    import ctypes
+    import torch
+    monkeypatch.setenv("REXII_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    D = 96
+    Hf = inputs.variable_depth(D)
+    Hd = _dev(Hf)
+    op = lrsw.LRSW(D, D, fc=20.0, Hfield=Hf)
+    t = 60.0 / lrsw.rho(op)
+    f = _dev(inputs.gaussian_bumps(D, nbumps=4, seed=54))
+    lib = rx.load()
+    cop = rx.make_op(D, D, fc=20.0, Hfield=Hd)
+    o = rx.make_opts(precision="mixed", tol=1e-6, pole_batch=-1)
+    nb = ctypes.c_size_t()
+    assert lib.rexii_workspace_size(ctypes.byref(cop), ctypes.byref(o), t, ctypes.byref(nb)) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(f)
+    rep = rx.Report()
+    st = lib.rexii_apply(ctypes.byref(cop), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), t,
+                         ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nb.value, rx._stream(), ctypes.byref(rep))
+    assert st == 0, rx.last_error()
+    assert "nx=96 ny=96" in (tmp_path / "tune.txt").read_text()
+    u2, _ = rx.apply(f, t, fc=20.0, Hfield=Hd, precision="mixed", tol=1e-6, pole_batch=-1)
+    assert em.rel_l2(u.cpu().numpy(), u2.cpu().numpy()) <= 1e-12
+    assert em.rel_l2(u.cpu().numpy(), varh.chebyshev_expm(op, f.cpu().numpy(), t)) <= 1e-6

@@ -329,7 +329,8 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
  *   The pole sums depend on a mode only through s_x^2 and s_y^2, which
  *     repeat along each axis: they are formed once per distinct pair
  *     (about 1/8 of the half spectrum on even grids with centred
- *     differences) and applied to every mode.
+ *     differences; on square grids the pair is unordered, about 1/16) and
+ *     applied to every mode.
  *   Report: P, M, N, m0, h, t, rho, kappa_sum; solves = terms of the sum
  *     (two poles of one n share a denominator); total_iters = distinct
  *     frequencies the sums were formed at; slots = waves per block of the

@@ -38,6 +38,7 @@ __device__ __forceinline__ V helm(const V* t, int y, int x, S cx, S cy, V zeta) 
 // Inner step (status kInner), input (x_i = d, r_i, p_i) with alpha_i, beta_i:
 //   q_i = (L - zeta) p_i                      (tile + halo 2, from p with halo 4)
 //   d  += alpha_i p_i,  r_{i+1} = r_i - alpha_i q_i,  p_{i+1} = r_{i+1} + beta_i p_i
+//   (the d update as d += dcp p_i + dcr r_i, or none at all: see DMode)
 //   q_{i+1} = (L - zeta) p_{i+1}              (tile)
 //   partial sums: p_{i+1}^T q_{i+1}, q_{i+1}^T r_{i+1}, q_{i+1}^T q_{i+1},
 //                 r_{i+1}^T r_{i+1}, |r_{i+1}|^2
@@ -63,9 +64,9 @@ constexpr int kNW = kTX + 4, kNH = kTY + 4;   // tile with halo 2
 
 // Control fields of a slot, from one wavefront load of its record.
 struct SlotCtl {
-  int status, par, rounds, it_inner, nx, ny, tiles_x;
+  int status, par, rounds, it_inner, nx, ny, tiles_x, dmode;
   double cx, cy;
-  double2 alpha, beta, zeta;
+  double2 alpha, beta, zeta, dcp, dcr;
 };
 
 __device__ __forceinline__ SlotCtl load_ctl(const Slot* S) {
@@ -80,9 +81,12 @@ __device__ __forceinline__ SlotCtl load_ctl(const Slot* S) {
   c.tiles_x = sw.i32(SLOT_OFF(tiles_x));
   c.cx = sw.f64(SLOT_OFF(cx));
   c.cy = sw.f64(SLOT_OFF(cy));
+  c.dmode = sw.i32(SLOT_OFF(dmode));
   c.alpha = sw.c64(SLOT_OFF(alpha));
   c.beta = sw.c64(SLOT_OFF(beta));
   c.zeta = sw.c64(SLOT_OFF(zeta));
+  c.dcp = sw.c64(SLOT_OFF(dcp));
+  c.dcr = sw.c64(SLOT_OFF(dcr));
   return c;
 }
 
@@ -115,7 +119,8 @@ __device__ __forceinline__ void cocg_dots_t(T (&s)[kNDots], V p, V r, V q) {
 
 
 // Flat tile mapping (element k of a tile to thread k mod 256): used for the
-// FP64 inner precision, where it measured faster than the row mapping below.
+// FP64 inner precision, where it measured faster than the row mapping below;
+// it takes the d updates of DMode (deferred every other step).
 constexpr int kRing = kNW * kNH - kTX * kTY;  // halo-2 ring points
 __device__ __forceinline__ void ring_pos(int e, int& y, int& x) {
   // rows 0,1 and kNH-2, kNH-1 (full width), then columns 0,1,kNW-2,kNW-1
@@ -151,9 +156,11 @@ __device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, 
   double2* x64 = e.x64 + base;
   const bool first = c.it_inner == 0;        // d restarts this step
   const bool fold = first && c.rounds >= 2;  // ... after x64 += d
+  const bool skip = c.dmode == kDSkip;       // d is left alone this step
   const V alpha = mk<V>(c.alpha.x, c.alpha.y);
   const V beta = mk<V>(c.beta.x, c.beta.y);
   const V zeta = mk<V>(c.zeta.x, c.zeta.y);
+  const V dcp = mk<V>(c.dcp.x, c.dcp.y), dcr = mk<V>(c.dcr.x, c.dcr.y);
   const T cx = T(c.cx), cy = T(c.cy);
   const int x0 = (tile % c.tiles_x) * kTX, y0 = (tile / c.tiles_x) * kTY;
   const bool big = (nx >= kPW) && (ny >= kPH);
@@ -166,7 +173,7 @@ __device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, 
   for (int j = 0; j < kTY / 4; ++j) {
     gi[j] = size_t(wrapc(y0 + ty + 4 * j, ny, big)) * nx + wrapc(x0 + tx, nx, big);
     rv[j] = rs[gi[j]];
-    if (!first) dv[j] = nt_load(&d[gi[j]]);
+    if (!first && !skip) dv[j] = nt_load(&d[gi[j]]);
   }
   constexpr int kRingPerThread = (kRing + kNT - 1) / kNT;
   V rr_[kRingPerThread];
@@ -203,7 +210,10 @@ __device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, 
         const double2 xo = x64[gi[j]];
         x64[gi[j]] = make_double2(xo.x + double(dold.x), xo.y + double(dold.y));
       }
-      nt_store(first ? cmul(alpha, pc) : cadd(dv[j], cmul(alpha, pc)), &d[gi[j]]);
+      if (!skip) {
+        const V dd = cadd(cmul(dcp, pc), cmul(dcr, rv[j]));
+        nt_store(first ? dd : cadd(dv[j], dd), &d[gi[j]]);
+      }
       rd[gi[j]] = r1;
       pd[gi[j]] = p1;
     }
@@ -233,7 +243,8 @@ __device__ __forceinline__ void cocg_inner_flat(const Eng& e, const SlotCtl& c, 
   }
 }
 
-// Row mapping: used for the FP32 inner precision.
+// Row mapping: used for the FP32 inner precision (every step updates d:
+// the scalars never choose kDSkip for FP32 vectors).
 template <typename T>
 __device__ __forceinline__ void cocg_inner(const Eng& e, const SlotCtl& c, int slot, int tile, unsigned char* lds,
                                            T (&a)[kNDots]) {
@@ -567,31 +578,77 @@ __global__ __launch_bounds__(kSNT) void k_pass_scalars(Eng e) {
   const double2 rr = make_double2(tot[6], tot[7]);
   const bool ok = finite2(pq) && finite2(qr) && finite2(qq) && finite2(rr) && (fabs(pq.x) + fabs(pq.y) > 0.0) &&
                   (fabs(rr.x) + fabs(rr.y) > 0.0);
+  // alpha and beta of the next step from the sums of this one
+  auto next_scalars = [&](double2& al, double2& be) {
+    al = cdiv(rr, pq);
+    // rr_{i+2} = rr - 2 alpha qr + alpha^2 qq
+    const double2 a2 = make_double2(al.x * al.x - al.y * al.y, 2.0 * al.x * al.y);
+    const double2 aqr = make_double2(al.x * qr.x - al.y * qr.y, al.x * qr.y + al.y * qr.x);
+    const double2 aqq = make_double2(a2.x * qq.x - a2.y * qq.y, a2.x * qq.y + a2.y * qq.x);
+    const double2 rr2 = make_double2(rr.x - 2.0 * aqr.x + aqq.x, rr.y - 2.0 * aqr.y + aqq.y);
+    be = cdiv(rr2, rr);
+  };
+  double2 al, be;
   if (status == kPrime) {
     if (!ok) {
       S->status = e.retry ? kRetry : kFailBreakdown;
       return;
     }
     S->status = kInner;
+    next_scalars(al, be);
+    // the first step of a round restarts d = alpha p
+    S->dmode = kDUpdate;
+    S->fin = 0;
+    S->dcp = al;
+    S->dcr = make_double2(0.0, 0.0);
   } else {
     // inner step: r and p were written to the other buffers
     S->parity = ldc(&S->parity) ^ 1;
     S->it_inner = ldc(&S->it_inner) + 1;
     const int it_total = ldc(&S->it_total) + 1;
     S->it_total = it_total;
-    if (!ok || !isfinite(n2) || n2 <= ldc(&S->in_tol2) || it_total >= ldc(&S->max_it)) {
-      S->status = kInnerDone;
+    const bool skipped = ldc(&S->dmode) == kDSkip;
+    if (skipped) S->skips = ldc(&S->skips) + 1;
+    // alpha_i / beta_i of the step just taken, for a deferred update
+    const double2 ab = skipped ? cdiv(ldc(&S->alpha), ldc(&S->beta)) : make_double2(0.0, 0.0);
+    const bool good = ok && isfinite(n2);
+    if (!good || n2 <= ldc(&S->in_tol2) || it_total >= ldc(&S->max_it) || ldc(&S->fin)) {
+      if (!skipped) {
+        S->status = kInnerDone;
+        S->fin = 0;
+        return;
+      }
+      // one more step adds the deferred term to d, then the round ends
+      // (with alpha = beta = 0 if the scalars are unusable: only d changes)
+      if (good) {
+        next_scalars(al, be);
+      } else {
+        al = be = make_double2(0.0, 0.0);
+      }
+      S->alpha = al;
+      S->beta = be;
+      S->rr = rr;
+      S->dmode = kDUpdate;
+      S->dcp = make_double2(al.x + ab.x, al.y + ab.y);
+      S->dcr = make_double2(-ab.x, -ab.y);
+      S->fin = 1;
       return;
     }
+    next_scalars(al, be);
+    if (skipped) {
+      S->dmode = kDUpdate;
+      S->dcp = make_double2(al.x + ab.x, al.y + ab.y);
+      S->dcr = make_double2(-ab.x, -ab.y);
+    } else if (!e.d_is_f32 && be.x * be.x + be.y * be.y >= kDeferBeta * kDeferBeta) {
+      S->dmode = kDSkip;
+    } else {
+      S->dmode = kDUpdate;
+      S->dcp = al;
+      S->dcr = make_double2(0.0, 0.0);
+    }
   }
-  const double2 al = cdiv(rr, pq);
-  // rr_{i+2} = rr - 2 alpha qr + alpha^2 qq
-  const double2 a2 = make_double2(al.x * al.x - al.y * al.y, 2.0 * al.x * al.y);
-  const double2 aqr = make_double2(al.x * qr.x - al.y * qr.y, al.x * qr.y + al.y * qr.x);
-  const double2 aqq = make_double2(a2.x * qq.x - a2.y * qq.y, a2.x * qq.y + a2.y * qq.x);
-  const double2 rr2 = make_double2(rr.x - 2.0 * aqr.x + aqq.x, rr.y - 2.0 * aqr.y + aqq.y);
   S->alpha = al;
-  S->beta = cdiv(rr2, rr);
+  S->beta = be;
   S->rr = rr;
 }
 
@@ -725,6 +782,10 @@ __device__ __forceinline__ void assign_solve(Eng& e, int s, int next) {
   S->stagnated = 0;
   S->discard = 0;
   S->max_it = ldc(&D->max_it);
+  S->dcp = S->dcr = make_double2(0.0, 0.0);
+  S->dmode = kDUpdate;
+  S->fin = 0;
+  S->skips = 0;
 }
 
 // One block: record finished solves, hand out the next ones in queue order
@@ -771,6 +832,7 @@ __global__ __launch_bounds__(kSchedNT) void k_assign(Eng e) {
       ss.rounds = ldc(&S->rounds);
       ss.status = st[j];
       ss.stagnated = ldc(&S->stagnated);
+      ss.skips = ldc(&S->skips);
       st[j] = kIdle;
       S->status = kIdle;
     }

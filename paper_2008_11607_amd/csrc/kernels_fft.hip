@@ -30,7 +30,8 @@
 // theta^2 depends on the mode only through s_x^2 and s_y^2, which repeat
 // along each axis, so the sums are formed once per distinct pair
 // (k_mode_coef) and a second kernel applies the quadratic to every mode
-// (k_mode_apply).
+// (k_mode_apply).  On square grids the pair is unordered (s_x and s_y are
+// the same function), which halves the table again.
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
 
@@ -160,14 +161,24 @@ int canon_count(int n, int kmax, int deriv) {
 // added in wave order through (nw - 1) x 1 KB of dynamic LDS.  With one
 // split the block writes scale (c1, c2) to coef; with several it writes its
 // unscaled sums to part[s][e] and k_mode_coef_sum adds the splits in order.
+// Symmetric tables (square grids: s_x and s_y are the same function, so the
+// pairs (a, b) and (b, a) share theta): entries e = b (b + 1) / 2 + a, a <= b.
+__host__ __device__ inline int tri_index(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
+__device__ inline void tri_coords(int e, int& a, int& b) {
+  b = int((sqrt(8.0 * double(e) + 1.0) - 1.0) * 0.5);
+  if ((b + 1) * (b + 2) / 2 <= e) ++b;
+  if (b * (b + 1) / 2 > e) --b;
+  a = e - b * (b + 1) / 2;
+}
+
 __global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restrict__ coef,
-                                                               double2* __restrict__ part, int cnx, int cny,
+                                                               double2* __restrict__ part, int cnx, int cny, int sym,
                                                                const double* __restrict__ sxt,
                                                                const double* __restrict__ syt, double t, double g,
                                                                double H, double fc, double scale,
                                                                const double* __restrict__ tab, int nterm) {
   extern __shared__ double red[];
-  const int ne = cnx * cny;
+  const int ne = sym ? cnx * (cnx + 1) / 2 : cnx * cny;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int nw = int(blockDim.x >> 6);
@@ -176,7 +187,15 @@ __global__ __launch_bounds__(64 * kModeWaves) void k_mode_coef(double2* __restri
   const int lo_s = min(nterm, sp * per_s), cnt_s = min(nterm, lo_s + per_s) - lo_s;
   const int e = int(blockIdx.x) * 64 + lane;
   const bool live = e < ne;
-  const int cx = live ? e % cnx : 0, cy = live ? e / cnx : 0;
+  int cx = 0, cy = 0;
+  if (live) {
+    if (sym) {
+      tri_coords(e, cx, cy);
+    } else {
+      cx = e % cnx;
+      cy = e / cnx;
+    }
+  }
   const double sx = sxt[cx], sy = syt[cy];
   const double th2 = t * t * fma(g * H, fma(sx, sx, sy * sy), fc * fc);
   double c1, c2;
@@ -218,7 +237,8 @@ __global__ __launch_bounds__(256) void k_mode_coef_sum(double2* __restrict__ coe
 // the mode's canonical frequency: F <- scale c0 F + C1 X F + C2 X^2 F,
 // X = t A(k) with the mode's own (signed) symbols.
 __global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, const double2* __restrict__ coef,
-                                                    int cnx, int nx, int ny, int deriv, const double* __restrict__ sxt,
+                                                    int ns, int ne, double scale, int cnx, int sym, int nx, int ny,
+                                                    int deriv, const double* __restrict__ sxt,
                                                     const double* __restrict__ syt, double t, double g, double H,
                                                     double fc, double a0) {
   const int nxh = nx / 2 + 1;
@@ -226,7 +246,21 @@ __global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, con
   const int m = int(blockIdx.x) * 256 + threadIdx.x;
   if (m >= nm) return;
   const int kx = m % nxh, ky = m / nxh;
-  const double2 c = coef[canon_index(ky, ny, deriv) * cnx + canon_index(kx, nx, deriv)];
+  const int ca = canon_index(kx, nx, deriv), cb = canon_index(ky, ny, deriv);
+  const int e = sym ? tri_index(ca, cb) : cb * cnx + ca;
+  double2 c;
+  if (ns <= 1) {
+    c = coef[e];
+  } else {
+    // the splits' unscaled sums, added in split order (as k_mode_coef_sum)
+    double c1 = 0.0, c2 = 0.0;
+    for (int q = 0; q < ns; ++q) {
+      const double2 v = coef[size_t(q) * ne + e];
+      c1 += v.x;
+      c2 += v.y;
+    }
+    c = make_double2(scale * c1, scale * c2);
+  }
   const double sx = sxt[kx], sy = syt[ky];
   double2 f[3];
 #pragma unroll
@@ -247,15 +281,18 @@ __global__ __launch_bounds__(256) void k_mode_apply(double2* __restrict__ F, con
                                          a0 * f[q].y + c.x * x1[q].y + c.y * x2[q].y);
 }
 
-// u = f, flag[0] = 1 if any value is not finite.
-__global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ u, size_t n, int* flag) {
+// u = f; flags[b] = 1 if block b met a value that is not finite, else 0
+// (every block writes its word, so nothing has to be cleared first).
+__global__ __launch_bounds__(256) void k_copy_check(const double* __restrict__ f, double* __restrict__ u, size_t n,
+                                                    int* __restrict__ flags) {
   bool bad = false;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
     const double v = f[i];
     u[i] = v;
     bad = bad || !isfinite(v);
   }
-  if (bad) atomicOr(flag, 1);
+  const int any = __syncthreads_or(bad ? 1 : 0);
+  if (threadIdx.x == 0) flags[blockIdx.x] = any;
 }
 
 // Shape of k_mode_coef: waves per block (8, measured best with 2000-10000
@@ -267,6 +304,9 @@ __global__ void k_copy_check(const double* __restrict__ f, double* __restrict__ 
 // (4112 blocks, 10034 terms) 1 split 0.91 ms / 44%, 2 splits 0.86 ms / 47%.
 constexpr int kCoefBlocks = 8192;
 constexpr int kMinTermsPerWave = 32;
+// Split sums of at most this many bytes are added by k_mode_apply as it reads
+// them (they stay in L2); larger ones by k_mode_coef_sum first.
+constexpr size_t kSplitsInApplyBytes = size_t(2) << 20;
 
 void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   const int blocks = (entries + 63) / 64;
@@ -278,29 +318,36 @@ void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   *ns_out = ns;
 }
 
-void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, const double* sxt, const double* syt, double t,
-                      double g, double H, double fc, double scale, const double* tab, int nterm, int nw, int ns,
-                      hipStream_t s) {
-  const int ne = cnx * cny;
+int mode_entries(int cnx, int cny, int sym) { return sym ? cnx * (cnx + 1) / 2 : cnx * cny; }
+
+bool mode_sum_in_apply(int entries, int ns) { return ns > 1 && size_t(ns) * entries * 16 <= kSplitsInApplyBytes; }
+
+void launch_mode_coef(double2* coef, double2* part, int cnx, int cny, int sym, const double* sxt, const double* syt,
+                      double t, double g, double H, double fc, double scale, const double* tab, int nterm, int nw,
+                      int ns, hipStream_t s) {
+  const int ne = mode_entries(cnx, cny, sym);
   const size_t lds = size_t(nw - 1) * 128 * sizeof(double);
   hipLaunchKernelGGL(k_mode_coef, dim3(unsigned((ne + 63) / 64), unsigned(ns)), dim3(64 * nw), lds, s, coef, part,
-                     cnx, cny, sxt, syt, t, g, H, fc, scale, tab, nterm);
-  if (ns > 1)
+                     cnx, cny, sym, sxt, syt, t, g, H, fc, scale, tab, nterm);
+  if (ns > 1 && !mode_sum_in_apply(ne, ns))
     hipLaunchKernelGGL(k_mode_coef_sum, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, coef, part, ne, ns, scale);
 }
 
-void launch_mode_apply(double2* F, const double2* coef, int cnx, int nx, int ny, int deriv, const double* sxt,
-                       const double* syt, double t, double g, double H, double fc, double a0, hipStream_t s) {
+void launch_mode_apply(double2* F, const double2* coef, int ns, int ne, double scale, int cnx, int sym, int nx,
+                       int ny, int deriv, const double* sxt, const double* syt, double t, double g, double H,
+                       double fc, double a0, hipStream_t s) {
   const long nm = long(nx / 2 + 1) * ny;
-  hipLaunchKernelGGL(k_mode_apply, dim3(unsigned((nm + 255) / 256)), dim3(256), 0, s, F, coef, cnx, nx, ny, deriv, sxt,
-                     syt, t, g, H, fc, a0);
+  hipLaunchKernelGGL(k_mode_apply, dim3(unsigned((nm + 255) / 256)), dim3(256), 0, s, F, coef, ns, ne, scale, cnx,
+                     sym, nx, ny, deriv, sxt, syt, t, g, H, fc, a0);
 }
 
-void launch_copy_check(const double* f, double* u, size_t n, int* flag, hipStream_t s) {
-  size_t b = (n + 255) / 256;
-  if (b > 4096) b = 4096;
-  if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_copy_check, dim3(unsigned(b)), dim3(256), 0, s, f, u, n, flag);
+int copy_check_blocks(size_t n) {
+  const size_t b = (n + 255) / 256;
+  return int(b < 1 ? 1 : (b > size_t(kCopyCheckMaxBlocks) ? size_t(kCopyCheckMaxBlocks) : b));
+}
+
+void launch_copy_check(const double* f, double* u, size_t n, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_check, dim3(unsigned(copy_check_blocks(n))), dim3(256), 0, s, f, u, n, flags);
 }
 
 // ---------------------------------------------------------------------------

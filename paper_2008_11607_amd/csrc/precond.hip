@@ -7,7 +7,7 @@
 // Fourier space (the cross term C vanishes: centred differences commute),
 // symbol -Hbar (s_x^2 + s_y^2) - zeta.  With the mean depth it is a
 // preconditioner for the depth field; its shift is damped,
-//   sigma = zeta + i beta |Re zeta| sign(Im zeta),  beta = 0.2,
+//   sigma = zeta + i beta |Re zeta| sign(Im zeta),  beta = 0.3,
 // which keeps it bounded for the resonant poles (the shift inside the
 // Laplacian's spectrum; undamped, the preconditioned iteration diverged at
 // t rho = 5000 in the CPU/GPU prototype).  BiCGStab right-preconditioned:

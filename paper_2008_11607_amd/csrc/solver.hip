@@ -181,25 +181,71 @@ static void read_to_host(void* dst, const void* src, size_t bytes, hipStream_t s
   std::memcpy(dst, pin, bytes);
 }
 
-// Axis symbols s(k) of a grid, x wavenumbers 0..nx/2 then y wavenumbers
-// 0..ny-1, formed once per (nx, ny, derivative) and kept (8 most recent),
-// with a pinned copy when the caller may allocate.
-struct SymTable {
-  std::vector<double> s;
-  double* pin = nullptr;
-  ~SymTable() {
-    if (pin) (void)hipHostFree(pin);
+// Copies of a constant host table in device memory, one per device, made
+// on first use (a synchronous upload).  When the table goes, its copies are
+// only queued; the next call that makes a copy frees them, so a call that
+// must not allocate or free (it never makes copies) frees none either.  The
+// tables below live in caches that are never destroyed, so nothing is freed
+// while the process exits.
+class DevCopies {
+ public:
+  ~DevCopies() {
+    std::lock_guard<std::mutex> lk(retired_mu());
+    for (auto& kv : ptr_) retired().push_back(kv.second);
   }
+  // the current device's copy of v (made now if there is none)
+  const double* get(const std::vector<double>& v) const {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(retired_mu());
+      for (void* p : retired()) (void)hipFree(p);
+      retired().clear();
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = ptr_.find(dev);
+    if (it != ptr_.end()) return it->second;
+    double* d = nullptr;
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&d), std::max<size_t>(1, v.size()) * sizeof(double)));
+    const hipError_t e = hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      throw HipError{REXII_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e)};
+    }
+    ptr_.emplace(dev, d);
+    return d;
+  }
+
+ private:
+  static std::mutex& retired_mu() {
+    static std::mutex& m = *new std::mutex();
+    return m;
+  }
+  static std::vector<void*>& retired() {
+    static std::vector<void*>& v = *new std::vector<void*>();
+    return v;
+  }
+  mutable std::mutex mu_;
+  mutable std::map<int, double*> ptr_;
 };
 
-static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv, bool pinned) {
+// Axis symbols s(k) of a grid, x wavenumbers 0..nx/2 then y wavenumbers
+// 0..ny-1, formed once per (nx, ny, derivative) and kept (8 most recent),
+// with device copies made on demand.
+struct SymTable {
+  std::vector<double> s;
+  DevCopies dev;
+};
+
+static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv) {
   static std::mutex mu;
-  static std::deque<std::pair<std::tuple<int, int, int>, std::shared_ptr<const SymTable>>> cache;
+  using Entry = std::pair<std::tuple<int, int, int>, std::shared_ptr<const SymTable>>;
+  static std::deque<Entry>& cache = *new std::deque<Entry>();
   const auto key = std::make_tuple(nx, ny, deriv);
   {
     std::lock_guard<std::mutex> lk(mu);
     for (auto it = cache.begin(); it != cache.end(); ++it)
-      if (it->first == key && (!pinned || it->second->pin)) {
+      if (it->first == key) {
         auto hit = *it;
         cache.erase(it);
         cache.push_front(hit);
@@ -210,10 +256,6 @@ static std::shared_ptr<const SymTable> symbol_table(int nx, int ny, int deriv, b
   st->s.resize(size_t(nx / 2 + 1) + ny);
   for (int k = 0; k <= nx / 2; ++k) st->s[k] = axis_symbol(k, nx, deriv);
   for (int k = 0; k < ny; ++k) st->s[nx / 2 + 1 + k] = axis_symbol(k, ny, deriv);
-  if (pinned) {
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&st->pin), st->s.size() * sizeof(double), hipHostMallocDefault));
-    std::memcpy(st->pin, st->s.data(), st->s.size() * sizeof(double));
-  }
   std::shared_ptr<const SymTable> out = st;
   std::lock_guard<std::mutex> lk(mu);
   for (auto it = cache.begin(); it != cache.end(); ++it)
@@ -968,13 +1010,14 @@ struct Engine {
                            std::max(0, R - 2) * (eb + 32.0));
       } else {
         // COCG: an inner step reads d, r, p and writes them (6 complex
-        // values); a residual step reads x64 (16 B), d and eta0 (8 B) and
-        // writes r and p (the first reads only eta0); each restart's prime
-        // step reads r; the first inner step of every later round moves d
-        // into x64 (32 B instead of a d read)
+        // values; 4 in a step that leaves d alone); a residual step reads
+        // x64 (16 B), d and eta0 (8 B) and writes r and p (the first reads
+        // only eta0); each restart's prime step reads r; the first inner
+        // step of every later round moves d into x64 (32 B instead of a d
+        // read)
         const double eb = double(z.eb);
         const int R = stats[j].rounds;
-        pass_bytes += pts * (6.0 * eb * stats[j].it_total + (8.0 + 2.0 * eb) +
+        pass_bytes += pts * (6.0 * eb * stats[j].it_total - 2.0 * eb * stats[j].skips + (8.0 + 2.0 * eb) +
                              std::max(0, R - 1) * (24.0 + 3.0 * eb) + std::max(0, R - 1) * eb +
                              std::max(0, R - 2) * (32.0 - eb));
       }
@@ -988,6 +1031,7 @@ constexpr int kHistBuckets = 20;
 struct RunSummary {
   int max_iters = 0, max_rounds = 0, not_conv = 0, breakdowns = 0, stagnated = 0;
   int64_t total_iters = 0;
+  int64_t total_skips = 0;   // COCG steps that left d alone
   double max_rel_res = 0.0;
   // error bound of the result (relative, W-norm): sum over the solves of
   // wsum * (achieved |r3|) / |f|_W; explicit shifts: the largest relative
@@ -1005,6 +1049,7 @@ static RunSummary summarize(const Engine& en, int inst) {
     r.max_iters = std::max(r.max_iters, s.it_total);
     r.max_rounds = std::max(r.max_rounds, s.rounds);
     r.total_iters += s.it_total;
+    r.total_skips += s.skips;
     if (s.status == kFailBreakdown) r.breakdowns++;
     else if (s.status != kDone) r.not_conv++;
     r.stagnated += s.stagnated;
@@ -1054,15 +1099,16 @@ static void fill_report(rexii_report* rep, const Plan& pl, const Engine* en, int
     for (int k = 0; k < kHistBuckets; ++k) rep->iter_hist[k] = r.hist[k];
     const double eb = double(inner_elem_bytes(pl.precision));
     // COCG: a pass reads x, r, p and writes them back (6 complex values per
-    // point); BiCGStab: an iteration moves 13 complex values and reads the
-    // depth three times
+    // point; 4 in a step that leaves d alone); BiCGStab: an iteration moves
+    // 13 complex values and reads the depth three times
     // preconditioned BiCGStab (method 2, FP64): the vector kernels move 26
     // complex values and read the depth twice per point and iteration, the
     // four transforms read and write their vector once each (8 more)
     const double per_pt = en->z.method == 2   ? 34.0 * 16.0 + 2.0 * 8.0
                           : en->z.method == 1 ? 13.0 * eb + 3.0 * (eb == 8.0 ? 4.0 : 8.0)
                                               : 6.0 * eb;
-    rep->alg_bytes = double(r.total_iters) * double(pl.nx) * pl.ny * per_pt;
+    rep->alg_bytes = double(pl.nx) * pl.ny *
+                     (double(r.total_iters) * per_pt - (en->z.method == 0 ? double(r.total_skips) * 2.0 * eb : 0.0));
     rep->slots = en->z.B;
     rep->tile_rows = en->z.th;
     rep->kernel_launches = en->launches;
@@ -1173,7 +1219,12 @@ static rexii_status sizing_plan(const JobItem& it, const rexii_opts& o, Problem&
 }
 
 // Preconditioned solver (method 2): slot count and device bytes.
-constexpr double kPcDampHost = 0.2;   // damping of the preconditioner's shift (precond.hip)
+// damping of the preconditioner's shift (precond.hip); measured on
+// resonant poles of the 2048^2 depth field at t rho = 5000 (iterations for
+// n = 50 / 200 / 500 / 1000): 0.1: 7 / 33 / 190 / 382, 0.3: 8 / 48 / 134 /
+// 82, 0.5: 8 / 68 / 168 / 72, 1.0: 11 / 115 / 277 / 107; undamped it
+// diverges for n >= 500
+constexpr double kPcDampHost = 0.3;
 constexpr int kPcCheck = 1;           // iterations between host checks (most solves take 2-3)
 
 static int pc_slots(size_t points, size_t nsolves, int requested) {
@@ -1188,8 +1239,7 @@ static int pc_slots(size_t points, size_t nsolves, int requested) {
 static size_t pc_engine_bytes(int nx, int ny, int B, size_t fft_work) {
   const size_t n = size_t(nx) * ny;
   return 8 * al256(size_t(B) * n * 16) + al256(size_t(B) * pc_blocks() * 8 * sizeof(double)) +
-         al256(size_t(B) * sizeof(PcSlot)) + al256((size_t(nx / 2 + 1) + ny) * 8) + al256(pc_blocks() * 8) +
-         al256(fft_work) + 4096;
+         al256(size_t(B) * sizeof(PcSlot)) + al256(pc_blocks() * 8) + al256(fft_work) + 4096;
 }
 
 static rexii_status job_bytes(const std::vector<JobItem>& items, const rexii_opts& o, bool keep, size_t extra,
@@ -1385,12 +1435,10 @@ static void run_pc(Job& jb, Arena& ar) {
     for (double2** v : vecs) *v = ar.take<double2>(size_t(B) * n);
     w.part = ar.take<double>(size_t(B) * pc_blocks() * 8);
     w.slots = ar.take<PcSlot>(B);
-    double* sym = ar.take<double>(size_t(nx / 2 + 1) + ny);
     double* hpart = ar.take<double>(pc_blocks());
     void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
     // axis symbols and the mean depth
-    const std::shared_ptr<const SymTable> symt = symbol_table(nx, ny, 0, true);
-    HIPCHK(hipMemcpyAsync(sym, symt->pin, symt->s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    const std::shared_ptr<const SymTable> symt = symbol_table(nx, ny, 0);
     launch_pc_sum(pb.H, n, hpart, st);
     std::vector<double> hp(pc_blocks());
     read_to_host(hp.data(), hpart, hp.size() * sizeof(double), st);
@@ -1407,7 +1455,7 @@ static void run_pc(Job& jb, Arena& ar) {
     pr.eta0 = pb.f;
     pr.D0 = pl.has_vel ? pb.DZ : nullptr;
     pr.Z0 = pl.has_vel ? pb.DZ + n : nullptr;
-    pr.sx = sym;
+    pr.sx = symt->dev.get(symt->s);
     // queue: most expensive first
     std::vector<int> order(S);
     for (int k = 0; k < S; ++k) order[k] = k;
@@ -2134,28 +2182,24 @@ static rexii_status run_adjoint(const rexii_swe_op* op, const double* f, const d
 // {0, +-i theta} as functions of theta^2 (see kernels_fft.hip); poles with
 // the same z^2 up to the sign of Im z^2 share a denominator and one entry.
 // The table depends on (M, h, scheme) only (t enters through theta), so it
-// is formed once per such triple and kept, with a pinned host copy the
-// calls upload from (8 most recent triples; entries in use are never freed).
+// is formed once per such triple and kept (8 most recent triples; entries in
+// use are never freed), with device copies the calls read in place.
 struct TermTable {
   int P = 0, nterm = 0;
   double kappa = 0.0, c0 = 0.0;
   std::vector<double> tab;   // nterm x (a, b^2, A1, B1, A2, B2)
-  double* pin = nullptr;     // the same in pinned host memory (or nullptr)
-  ~TermTable() {
-    if (pin) (void)hipHostFree(pin);
-  }
+  DevCopies dev;
 };
 
-// pinned: the entry must carry a pinned copy (callers that may allocate);
-// without it a cached entry of either kind serves and a new one gets none.
-static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme, bool pinned) {
+static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme) {
   static std::mutex mu;
-  static std::deque<std::pair<std::tuple<int, double, int>, std::shared_ptr<const TermTable>>> cache;
+  using Entry = std::pair<std::tuple<int, double, int>, std::shared_ptr<const TermTable>>;
+  static std::deque<Entry>& cache = *new std::deque<Entry>();
   const auto key = std::make_tuple(M, h, scheme);
   {
     std::lock_guard<std::mutex> lk(mu);
     for (auto it = cache.begin(); it != cache.end(); ++it)
-      if (it->first == key && (!pinned || it->second->pin)) {
+      if (it->first == key) {
         auto hit = *it;
         cache.erase(it);
         cache.push_front(hit);
@@ -2187,15 +2231,10 @@ static std::shared_ptr<const TermTable> term_table(int M, double h, int scheme, 
     }
   }
   tt->nterm = int(tab.size() / 6);
-  if (pinned) {
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&tt->pin), std::max<size_t>(1, tab.size()) * sizeof(double),
-                         hipHostMallocDefault));
-    std::memcpy(tt->pin, tab.data(), tab.size() * sizeof(double));
-  }
   std::shared_ptr<const TermTable> out = tt;
   std::lock_guard<std::mutex> lk(mu);
   for (auto it = cache.begin(); it != cache.end(); ++it)
-    if (it->first == key) {   // an entry without the pinned copy is replaced
+    if (it->first == key) {   // made meanwhile by another thread
       cache.erase(it);
       break;
     }
@@ -2219,8 +2258,8 @@ static double rho_fourier(const rexii_swe_op* op, int deriv) {
   return std::sqrt(op->f_cor * op->f_cor + op->g * op->H0 * (sx * sx + sy * sy));
 }
 
-static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv, FourierPlan& fp,
-                                 bool pinned = true) {
+static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_opts& o, int deriv,
+                                 FourierPlan& fp) {
   if (!(o.h > 0.0 && o.h < M_PI)) return set_error(REXII_ERR_INVALID_ARG, "h must be in (0, pi)");
   if (o.scheme != REXII_SCHEME_REXII && o.scheme != REXII_SCHEME_REXI)
     return set_error(REXII_ERR_INVALID_ARG, "unknown scheme");
@@ -2231,7 +2270,7 @@ static rexii_status fourier_plan(const rexii_swe_op* op, double t, const rexii_o
   if (Md > 2.0e6) return set_error(REXII_ERR_INVALID_ARG, "t*rho/h too large for this library");
   fp.M = m_rule(t, fp.rho, o.h, fp.m0);
   fp.N = fp.M + terms_L();
-  fp.tab = term_table(fp.M, o.h, o.scheme, pinned);
+  fp.tab = term_table(fp.M, o.h, o.scheme);
   fp.P = fp.tab->P;
   fp.kappa = fp.tab->kappa;
   fp.c0 = fp.tab->c0;
@@ -2250,11 +2289,14 @@ static size_t fourier_bytes(int nx, int ny, int deriv, int nterm, size_t fft_wor
   const size_t nm = size_t(nx / 2 + 1) * ny;
   int cnx = 0, cny = 0;
   fourier_canon(nx, ny, deriv, &cnx, &cny);
+  const int ne = mode_entries(cnx, cny, nx == ny ? 1 : 0);
   int nw = 1, ns = 1;
-  mode_coef_shape(cnx * cny, nterm, &nw, &ns);
-  const size_t part = (ns > 1) ? al256(size_t(ns) * cnx * cny * 16) : 0;
-  return al256(3 * nm * 16) + al256(size_t(nterm) * 48) + al256(size_t(cnx) * cny * 16) + part + al256(256) +
-         al256((size_t(nx / 2 + 1) + ny) * 8) + al256(fft_work);
+  mode_coef_shape(ne, nterm, &nw, &ns);
+  const size_t part = (ns > 1) ? al256(size_t(ns) * ne * 16) : 0;
+  // spectra, coefficients, split sums, finiteness words, and (copied in by
+  // the no-allocation entry point) the term and symbol tables
+  return al256(3 * nm * 16) + al256(size_t(ne) * 16) + part + al256(kCopyCheckMaxBlocks * sizeof(int)) +
+         al256(size_t(nterm) * 48) + al256((size_t(nx / 2 + 1) + ny) * 8) + al256(fft_work);
 }
 
 // noalloc: device scratch from the library's static array, FFT plans only
@@ -2280,7 +2322,7 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     rexii_opts o = resolve_opts(opts_in);
     if (noalloc) o.profile = 0;
     FourierPlan fp;
-    rexii_status s = fourier_plan(op, t, o, deriv, fp, !noalloc);
+    rexii_status s = fourier_plan(op, t, o, deriv, fp);
     if (s != REXII_OK) return s;
     if (noalloc) {
       const size_t fixed = fourier_bytes(nx, ny, deriv, fp.nterm, 0);
@@ -2313,64 +2355,95 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     } else if (reinterpret_cast<uintptr_t>(ws) & 255) {
       return set_error(REXII_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     }
-    const int ne = cnx * cny;
+    const int sq = (nx == ny) ? 1 : 0;   // square grid: unordered frequency pairs
+    const int ne = mode_entries(cnx, cny, sq);
     int nw = 1, ns = 1;
     mode_coef_shape(ne, fp.nterm, &nw, &ns);
+    const bool sum_in_apply = mode_sum_in_apply(ne, ns);
     const std::vector<double>& htab = fp.tab->tab;
+    const std::shared_ptr<const SymTable> sym = symbol_table(nx, ny, deriv);
+    const int ncheck = copy_check_blocks(n3);
     double2* F = ar.take<double2>(3 * nm);
-    double* tab = ar.take<double>(htab.size());
     double2* coef = ar.take<double2>(size_t(ne));
     double2* part = (ns > 1) ? ar.take<double2>(size_t(ns) * ne) : nullptr;
-    double* flagd = ar.take<double>(32);
-    const std::shared_ptr<const SymTable> sym = symbol_table(nx, ny, deriv, !noalloc);
-    double* sxt = ar.take<double>(sym->s.size());
-    const double* syt = sxt + (nx / 2 + 1);
+    int* flags = ar.take<int>(kCopyCheckMaxBlocks);
     void* wk = work ? static_cast<void*>(ar.take<char>(work)) : nullptr;
-    int* flag = reinterpret_cast<int*>(flagd);
-    // the term and symbol tables: DMAs from their pinned copies, or (no
-    // pinned copy: the no-allocation entry point) copies from pageable memory
-    HIPCHK(hipMemcpyAsync(tab, fp.tab->pin ? fp.tab->pin : htab.data(), htab.size() * sizeof(double),
-                          hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(sxt, sym->pin ? sym->pin : sym->s.data(), sym->s.size() * sizeof(double),
-                          hipMemcpyHostToDevice, st));
-    launch_fill_zero(flagd, 32, st);
+    // the term and symbol tables: the library's device copies, or (the
+    // no-allocation entry point) copies from pageable host memory into its
+    // scratch
+    const double* tab = nullptr;
+    const double* sxt = nullptr;
+    if (noalloc) {
+      double* dtab = ar.take<double>(htab.size());
+      double* dsym = ar.take<double>(sym->s.size());
+      HIPCHK(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dsym, sym->s.data(), sym->s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      tab = dtab;
+      sxt = dsym;
+    } else {
+      tab = fp.tab->dev.get(htab);
+      sxt = sym->dev.get(sym->s);
+    }
+    const double* syt = sxt + (nx / 2 + 1);
     const bool prof = (o.profile != 0);
+    const double scale = 1.0 / (double(nx) * ny);
+    auto pole_sums = [&]() {
+      launch_mode_coef(coef, part, cnx, cny, sq, sxt, syt, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns,
+                       st);
+    };
+    auto apply_modes = [&]() {
+      launch_mode_apply(F, sum_in_apply ? part : coef, sum_in_apply ? ns : 1, ne, scale, cnx, sq, nx, ny, deriv, sxt,
+                        syt, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
+    };
     // profiling events: created once per host thread and kept
     static thread_local hipEvent_t ev[6] = {};
-    if (prof && !ev[0])
-      for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    auto mark = [&](int k) {
-      if (prof) HIPCHK(hipEventRecord(ev[k], st));
-    };
-    const double scale = 1.0 / (double(nx) * ny);
-    mark(0);
-    launch_copy_check(f, u, n3, flag, st);  // the forward transform may overwrite its input
-    mark(1);
-    s = fft_execute(fwd, u, F, wk, work, st);
-    if (s != REXII_OK) return s;
-    mark(2);
-    launch_mode_coef(coef, part, cnx, cny, sxt, syt, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns, st);
-    mark(3);
-    launch_mode_apply(F, coef, cnx, nx, ny, deriv, sxt, syt, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
-    mark(4);
-    s = fft_execute(inv, F, u, wk, work, st);
-    if (s != REXII_OK) return s;
-    mark(5);
-    HIPCHK(hipGetLastError());
-    int bad = 0;
-    if (noalloc) {
-      // no pinned memory: the stream is drained, then one word is copied
-      HIPCHK(hipStreamSynchronize(st));
-      HIPCHK(hipMemcpy(&bad, flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (prof) {
+      if (!ev[0])
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+      // one stage after the other, timed
+      HIPCHK(hipEventRecord(ev[0], st));
+      launch_copy_check(f, u, n3, flags, st);  // the forward transform may overwrite its input
+      HIPCHK(hipEventRecord(ev[1], st));
+      s = fft_execute(fwd, u, F, wk, work, st);
+      if (s != REXII_OK) return s;
+      HIPCHK(hipEventRecord(ev[2], st));
+      pole_sums();
+      HIPCHK(hipEventRecord(ev[3], st));
+      apply_modes();
+      HIPCHK(hipEventRecord(ev[4], st));
+      s = fft_execute(inv, F, u, wk, work, st);
+      if (s != REXII_OK) return s;
+      HIPCHK(hipEventRecord(ev[5], st));
     } else {
-      // the flag is read into pinned host memory (one word per host thread,
-      // kept for the life of the process), ordered on the stream
-      static thread_local int* hflag = nullptr;
-      if (!hflag) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), 256, hipHostMallocDefault));
-      HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      bad = *hflag;
+      launch_copy_check(f, u, n3, flags, st);
+      s = fft_execute(fwd, u, F, wk, work, st);
+      if (s != REXII_OK) return s;
+      pole_sums();
+      apply_modes();
+      s = fft_execute(inv, F, u, wk, work, st);
+      if (s != REXII_OK) return s;
     }
+    HIPCHK(hipGetLastError());
+    std::vector<int> hflags;
+    const int* fl = nullptr;
+    if (noalloc) {
+      // no pinned memory: the stream is drained, then the words are copied
+      hflags.resize(ncheck);
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipMemcpy(hflags.data(), flags, ncheck * sizeof(int), hipMemcpyDeviceToHost));
+      fl = hflags.data();
+    } else {
+      // the words are read into pinned host memory (kept per host thread for
+      // the life of the process), ordered on the stream
+      static thread_local int* hflag = nullptr;
+      if (!hflag)
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), kCopyCheckMaxBlocks * sizeof(int), hipHostMallocDefault));
+      HIPCHK(hipMemcpyAsync(hflag, flags, ncheck * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      fl = hflag;
+    }
+    int bad = 0;
+    for (int b = 0; b < ncheck; ++b) bad |= fl[b];
     if (rep) {
       rep->P = fp.P;
       rep->M = fp.M;

@@ -295,13 +295,15 @@ __global__ __launch_bounds__(256) void k_copy_check(const double* __restrict__ f
   if (threadIdx.x == 0) flags[blockIdx.x] = any;
 }
 
-// Shape of k_mode_coef: waves per block (8, measured best with 2000-10000
-// terms per entry, fewer when a wave would get under 64 terms) and term
-// splits (grid rows): blocks up to about kCoefBlocks (32 per CU) while every
-// wave keeps at least kMinTermsPerWave terms.  Measured (kernel time, FP64
-// flop fraction): 512^2 at t rho 1000 (261 blocks, 2034 terms) 4 splits
-// 27.2 us / 19%, 8 splits 28.3 us, 16 splits 33.2 us; 2048^2 at t rho 5000
-// (4112 blocks, 10034 terms) 1 split 0.91 ms / 44%, 2 splits 0.86 ms / 47%.
+// Shape of k_mode_coef: waves per block (kCoefWaves, fewer when a wave would
+// get under 64 terms) and term splits (grid rows): blocks up to about
+// kCoefBlocks (32 per CU) while every wave keeps at least kMinTermsPerWave
+// terms.  Measured (pole-sum stage, events; waves x splits) on square grids
+// with the unordered table: 512^2 at t rho 1000 (132 entry blocks, 2034
+// terms) 8 x 4: 16.8 us, 8 x 8: 16.1, 4 x 8: 16.0, 4 x 16: 21.0, 2 x 16:
+// 21.1, 8 x 2: 19.6; 2048^2 at t rho 5000 (2060 entry blocks, 10034 terms)
+// 8 x 4: 533 us, 8 x 2: 508, 8 x 1: 528, 4 x 4: 475, 4 x 8: 471, 2 x 8: 475.
+constexpr int kCoefWaves = 4;
 constexpr int kCoefBlocks = 8192;
 constexpr int kMinTermsPerWave = 32;
 // Split sums of at most this many bytes are added by k_mode_apply as it reads
@@ -311,7 +313,7 @@ constexpr size_t kSplitsInApplyBytes = size_t(2) << 20;
 void mode_coef_shape(int entries, int nterm, int* nw_out, int* ns_out) {
   const int blocks = (entries + 63) / 64;
   int nw = 1;
-  while (nw < 8 && nterm >= 128 * nw) nw *= 2;
+  while (nw < kCoefWaves && nterm >= 128 * nw) nw *= 2;
   int ns = 1;
   while (ns < 64 && blocks * ns < kCoefBlocks && nterm >= 2 * ns * nw * kMinTermsPerWave) ns *= 2;
   *nw_out = nw;

@@ -311,7 +311,8 @@ def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, w
     REXII pole sum per mode in closed form, inverse FFT; FP64.
     derivative: "centred" (the operator of apply) or "spectral" (Fourier
     differentiation).  workspace: optional uint8 CUDA tensor of at least
-    fourier_workspace_size() bytes.  Returns (u, report_dict)."""
+    fourier_workspace_size() bytes (by default one from PyTorch's caching
+    allocator).  Returns (u, report_dict)."""
     import torch
     lib = load()
     _dev_f64(f)
@@ -320,6 +321,12 @@ def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, w
     op = make_op(nx, ny, g, fc, H, None)
     o = make_opts(**opts)
     rep = Report()
+    if workspace is None:
+        # from PyTorch's caching allocator: repeated calls allocate nothing
+        nb = ctypes.c_size_t()
+        _check(lib.rexii_fourier_workspace_size(ctypes.byref(op), ctypes.byref(o), float(t),
+                                                DERIVATIVES.get(derivative, derivative), ctypes.byref(nb)))
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=f.device) if nb.value else None
     ws, nws = (None, 0) if workspace is None else (ctypes.c_void_p(workspace.data_ptr()), workspace.numel())
     st = lib.rexii_apply_fourier(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                  float(t), DERIVATIVES.get(derivative, derivative), ctypes.byref(o), ws, nws,
@@ -371,9 +378,12 @@ def apply_multishift(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts)
     op = make_op(nx, ny, g, fc, H, Hfield)
     o = make_opts(**opts)
     rep = Report()
+    nb = ctypes.c_size_t()
+    _check(lib.rexii_multishift_workspace_size(ctypes.byref(op), int(nrhs), ctypes.byref(o), ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=f.device) if nb.value else None
     st = lib.rexii_apply_multishift(ctypes.byref(op), int(nrhs), ctypes.c_void_p(f.data_ptr()),
-                                    ctypes.c_void_p(u.data_ptr()), float(t), ctypes.byref(o), None, 0, _stream(),
-                                    ctypes.byref(rep))
+                                    ctypes.c_void_p(u.data_ptr()), float(t), ctypes.byref(o), *_ws_args(ws),
+                                    _stream(), ctypes.byref(rep))
     _check(st, rep.as_dict())
     return u, rep.as_dict()
 
@@ -494,11 +504,17 @@ def apply_circulant(f, t, stencil, scheme="rexii", nu=0.0, M=0, out=None, **opts
     off, cc = _stencil_arrays(stencil)
     o = make_opts(**opts)
     rep = Report()
+    nb = ctypes.c_size_t()
+    _check(lib.rexii_circulant_workspace_size(int(n), len(off), off.ctypes.data_as(ctypes.c_void_p),
+                                              cc.ctypes.data_as(ctypes.c_void_p), int(nrhs), float(t), float(nu.imag),
+                                              CIRC_SCHEMES.get(scheme, scheme), int(M), ctypes.byref(o),
+                                              ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=f.device) if nb.value else None
     st = lib.rexii_apply_circulant(int(n), len(off), off.ctypes.data_as(ctypes.c_void_p),
                                    cc.ctypes.data_as(ctypes.c_void_p), int(nrhs), ctypes.c_void_p(f.data_ptr()),
                                    ctypes.c_void_p(u.data_ptr()), float(t), float(nu.imag),
-                                   CIRC_SCHEMES.get(scheme, scheme), int(M), ctypes.byref(o), None, 0, _stream(),
-                                   ctypes.byref(rep))
+                                   CIRC_SCHEMES.get(scheme, scheme), int(M), ctypes.byref(o), *_ws_args(ws),
+                                   _stream(), ctypes.byref(rep))
     _check(st, rep.as_dict())
     return u, rep.as_dict()
 

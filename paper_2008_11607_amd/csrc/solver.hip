@@ -2387,13 +2387,22 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
     const double* syt = sxt + (nx / 2 + 1);
     const bool prof = (o.profile != 0);
     const double scale = 1.0 / (double(nx) * ny);
-    auto pole_sums = [&]() {
+    auto pole_sums = [&](hipStream_t q) {
       launch_mode_coef(coef, part, cnx, cny, sq, sxt, syt, t, op->g, op->H0, op->f_cor, scale, tab, fp.nterm, nw, ns,
-                       st);
+                       q);
     };
-    auto apply_modes = [&]() {
+    auto apply_modes = [&](hipStream_t q) {
       launch_mode_apply(F, sum_in_apply ? part : coef, sum_in_apply ? ns : 1, ne, scale, cnx, sq, nx, ny, deriv, sxt,
-                        syt, t, op->g, op->H0, op->f_cor, scale * fp.c0, st);
+                        syt, t, op->g, op->H0, op->f_cor, scale * fp.c0, q);
+    };
+    // the whole sequence on stream q (eager, or captured into a graph)
+    auto enqueue = [&](hipStream_t q) -> rexii_status {
+      launch_copy_check(f, u, n3, flags, q);  // the forward transform may overwrite its input
+      rexii_status e1 = fft_execute(fwd, u, F, wk, work, q);
+      if (e1 != REXII_OK) return e1;
+      pole_sums(q);
+      apply_modes(q);
+      return fft_execute(inv, F, u, wk, work, q);
     };
     // profiling events: created once per host thread and kept
     static thread_local hipEvent_t ev[6] = {};
@@ -2407,20 +2416,15 @@ static rexii_status run_fourier(const rexii_swe_op* op, const double* f, double*
       s = fft_execute(fwd, u, F, wk, work, st);
       if (s != REXII_OK) return s;
       HIPCHK(hipEventRecord(ev[2], st));
-      pole_sums();
+      pole_sums(st);
       HIPCHK(hipEventRecord(ev[3], st));
-      apply_modes();
+      apply_modes(st);
       HIPCHK(hipEventRecord(ev[4], st));
       s = fft_execute(inv, F, u, wk, work, st);
       if (s != REXII_OK) return s;
       HIPCHK(hipEventRecord(ev[5], st));
     } else {
-      launch_copy_check(f, u, n3, flags, st);
-      s = fft_execute(fwd, u, F, wk, work, st);
-      if (s != REXII_OK) return s;
-      pole_sums();
-      apply_modes();
-      s = fft_execute(inv, F, u, wk, work, st);
+      s = enqueue(st);
       if (s != REXII_OK) return s;
     }
     HIPCHK(hipGetLastError());

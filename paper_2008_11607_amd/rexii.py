@@ -133,7 +133,13 @@ def last_error():
 
 
 def _check(st, report=None):
+    """Raise RexiiError for a non-zero status; report: a Report, a list of
+    them or a dict (converted only when raising)."""
     if st != 0:
+        if isinstance(report, Report):
+            report = report.as_dict()
+        elif isinstance(report, list):
+            report = [r.as_dict() if isinstance(r, Report) else r for r in report]
         raise RexiiError(st, last_error(), report)
 
 
@@ -249,7 +255,7 @@ def apply(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts):
     ws = _workspace((SweOp * 1)(op), (ctypes.c_double * 1)(float(t)), o, f.device)
     st = lib.rexii_apply(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                          float(t), ctypes.byref(o), *_ws_args(ws), _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return u, rep.as_dict()
 
 
@@ -299,7 +305,7 @@ def shifted_solve(f, t, z, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
     st = lib.rexii_shifted_solve(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), float(t), len(z),
                                  zz.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(x.data_ptr()),
                                  ctypes.byref(o), None, 0, _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return x, rep.as_dict()
 
 
@@ -331,7 +337,7 @@ def apply_fourier(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out=None, w
     st = lib.rexii_apply_fourier(ctypes.byref(op), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                  float(t), DERIVATIVES.get(derivative, derivative), ctypes.byref(o), ws, nws,
                                  _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return u, rep.as_dict()
 
 
@@ -353,7 +359,7 @@ def apply_fourier_noalloc(f, t, g=1.0, fc=10.0, H=1.0, derivative="centred", out
                                          ctypes.c_void_p(u.data_ptr()), float(t),
                                          DERIVATIVES.get(derivative, derivative), ctypes.byref(o), _stream(),
                                          ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return u, rep.as_dict()
 
 
@@ -384,7 +390,7 @@ def apply_multishift(f, t, g=1.0, fc=10.0, H=1.0, Hfield=None, out=None, **opts)
     st = lib.rexii_apply_multishift(ctypes.byref(op), int(nrhs), ctypes.c_void_p(f.data_ptr()),
                                     ctypes.c_void_p(u.data_ptr()), float(t), ctypes.byref(o), *_ws_args(ws),
                                     _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return u, rep.as_dict()
 
 
@@ -427,7 +433,7 @@ def apply_adjoint(f, gbar, t, g=1.0, fc=10.0, H=1.0, want_dJdf=True, want_dJdH=T
                                  ctypes.c_void_p(dJdf.data_ptr()) if dJdf is not None else None,
                                  ctypes.byref(dJdH) if want_dJdH else None, float(t), ctypes.byref(o), None, 0,
                                  _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return dJdf, (dJdH.value if want_dJdH else None), rep.as_dict()
 
 
@@ -454,7 +460,7 @@ def apply_batched(fs, ts, g=1.0, fc=10.0, H=1.0, Hfield=None, **opts):
     o = make_opts(**opts)
     ws = _workspace(ops, tarr, o, fs[0].device)
     st = lib.rexii_apply_batched(cnt, ops, fptr, uptr, tarr, ctypes.byref(o), *_ws_args(ws), _stream(), reps)
-    _check(st, [r.as_dict() for r in reps])
+    _check(st, list(reps))
     return us, [r.as_dict() for r in reps]
 
 
@@ -515,7 +521,7 @@ def apply_circulant(f, t, stencil, scheme="rexii", nu=0.0, M=0, out=None, **opts
                                    ctypes.c_void_p(u.data_ptr()), float(t), float(nu.imag),
                                    CIRC_SCHEMES.get(scheme, scheme), int(M), ctypes.byref(o), *_ws_args(ws),
                                    _stream(), ctypes.byref(rep))
-    _check(st, rep.as_dict())
+    _check(st, rep)
     return u, rep.as_dict()
 
 

@@ -58,21 +58,21 @@ def workload():
 # workload (one state, 8 slots); valid only for the kernel sources they were
 # taken on.
 TRAFFIC = {
-    "k_pass_f32": {"bytes_per_launch": 1552293211.2, "fetch_kib": 390473.115, "write_kib": 734983.867,
+    "k_pass_f32": {"bytes_per_launch": 1552237728.5, "fetch_kib": 390436.601, "write_kib": 734983.956,
                    "measured_on": "512^2 t rho 1000 mixed, 128 slots",
                    "sources": ["kernels.hip", "kernels.h", "device_util.h"],
-                   "sources_sha256": "c7b5048e0b9096ec499b6e39c43ad76a6f3a605c390ef1e0e7d7a873fea4f669"},
-    "k_pass_f64": {"bytes_per_launch": 3127855249.2, "fetch_kib": 786235.028, "write_kib": 1482113.856,
+                   "sources_sha256": "170d6851ff9acd7b82b98d1b0135ddb85c09c932c9da36aee58af692ed2a2bef"},
+    "k_pass_f64": {"bytes_per_launch": 2619046913.6, "fetch_kib": 661923.708, "write_kib": 1233815.586,
                    "measured_on": "512^2 t rho 1000 fp64, 128 slots",
                    "sources": ["kernels.hip", "kernels.h", "device_util.h"],
-                   "sources_sha256": "c7b5048e0b9096ec499b6e39c43ad76a6f3a605c390ef1e0e7d7a873fea4f669"},
+                   "sources_sha256": "170d6851ff9acd7b82b98d1b0135ddb85c09c932c9da36aee58af692ed2a2bef"},
     # the Fourier path's pole-sum kernel: not measured (it is bound by FP64
     # arithmetic and writes 16 bytes per distinct frequency)
     "k_mode_coef": {"bytes_per_launch": None, "sources": ["kernels_fft.hip", "kernels_fft.h"], "sources_sha256": None},
-    "k_bcg_u1_f32": {"bytes_per_launch": 1459813219.1, "fetch_kib": 446851.921, "write_kib": 531916.472,
+    "k_bcg_u1_f32": {"bytes_per_launch": 1426113288.6, "fetch_kib": 430385.906, "write_kib": 531916.946,
                      "measured_on": "2048^2 depth field t rho 100 mixed, one state, 8 slots",
                      "sources": ["kernels_vh.hip", "kernels.h", "device_util.h"],
-                     "sources_sha256": "ee1f1c3ebe40b3764d84c9d1de30062a5218208bae882ba352c2c6efc9ceaaea"},
+                     "sources_sha256": "d46707395c2f3676effb17af1cba10fed044ea5ba51a41c2337c352943362c56"},
 }
 
 

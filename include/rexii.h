@@ -323,9 +323,11 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
  *     uses the poles of rexii_coeffs_rexi) and profile; other fields
  *     ignored.  f, u: device [3][ny][nx], not overlapping.
  *   Workspace: rexii_fourier_workspace_size() bytes (half spectra
- *     [3][ny][nx/2+1] complex128, the term table, the FFT work buffer), or
- *     NULL to let the library allocate.  FFT plans are created on first use
- *     per device and grid and kept until the process ends.
+ *     [3][ny][nx/2+1] complex128, coefficient table and split sums,
+ *     finiteness words, the FFT work buffer), or NULL to let the library
+ *     allocate.  FFT plans are created on first use per device and grid,
+ *     and device copies of the term and symbol tables on first use per
+ *     device; both are kept until the process ends.
  *   The pole sums depend on a mode only through s_x^2 and s_y^2, which
  *     repeat along each axis: they are formed once per distinct pair
  *     (about 1/8 of the half spectrum on even grids with centred
@@ -334,7 +336,7 @@ rexii_status rexii_shifted_solve(const rexii_swe_op* op, const double* f, double
  *   Report: P, M, N, m0, h, t, rho, kappa_sum; solves = terms of the sum
  *     (two poles of one n share a denominator); total_iters = distinct
  *     frequencies the sums were formed at; slots = waves per block of the
- *     sum kernel; alg_bytes = algorithmic HBM bytes of the path;
+ *     sum kernel; tile_rows = its term splits; alg_bytes = algorithmic HBM bytes of the path;
  *     kernel_bytes = those of the apply kernel (96 per half-spectrum mode).
  *     With opts.profile = 1: step_ms[0..4] = copy and finiteness check,
  *     forward FFT, pole sums, apply, inverse FFT (HIP events, ms);
@@ -354,7 +356,8 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
 /* For callers that cannot allocate device memory: tight serving loops and
  * harnesses that forbid hipMalloc.  The same computation, kernels and
  * result as rexii_apply_fourier, with every piece of device scratch (half
- * spectra, term table, coefficient table, flag, FFT work buffer) taken
+ * spectra, term table, coefficient table, finiteness words, FFT work
+ * buffer) taken
  * from a static array inside the library instead of a workspace:
  * REXII_STATIC_SCRATCH_BYTES bytes per GPU, reserved when the library's
  * code is loaded on that GPU and held until the process ends.
@@ -369,7 +372,8 @@ rexii_status rexii_apply_fourier(const rexii_swe_op* op, const double* f, double
  *     exceeds REXII_STATIC_SCRATCH_BYTES returns REXII_ERR_WORKSPACE
  *     (covers grids up to 2048 x 2048).
  *   Every call on one GPU uses that GPU's single array and leaves its
- *     contents behind (the flag is cleared by a kernel each call): calls
+ *     contents behind (every word a call reads back is written by a kernel
+ *     of that call first): calls
  *     that overlap in time on one GPU, from several host threads or on
  *     several streams, race and give wrong results; serialise them.
  * Errors: as rexii_apply_fourier. */

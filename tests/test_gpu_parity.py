@@ -156,6 +156,42 @@ def test_iteration_cap_reports_not_converged(rx):
     assert e.value.report["not_converged"] > 0
 
 
+@pytest.mark.parametrize("cap", [6, 7, 40, 41])
+def test_fp64_iteration_cap_keeps_the_bound(rx, cap):
+    """FP64 COCG steps may leave the correction d alone and add that term one
+    step later; a solve stopped at its cap right after such a step must still
+    add it.  Whatever the cap's parity, the written result is the iterate the
+    reported residuals describe: its error against the oracle's exact
+    approximant is within the reported bound."""
+    import torch
+    op, rho, t, f = _case(64, 48, 120.0, nbumps=3, seed=21, velocity=True)
+    fd = _dev(f)
+    u = torch.full_like(fd, float("nan"))
+    with pytest.raises(rx.RexiiError) as e:
+        rx.apply(fd, t, fc=10.0, precision="fp64", tol=1e-10, max_iter=cap, out=u)
+    assert e.value.status == -3
+    rep = e.value.report
+    assert rep["not_converged"] > 0 and rep["max_iters"] <= cap + 1
+    c = oc.api_coeffs(t, rho, h=0.5, tol=1e-10)
+    ref = rm.rexii_spectral(op, f, t, c["z"], c["w"])
+    diff = _host(u) - ref
+    wn = lambda x: np.sqrt(np.sum(x ** 2))
+    assert np.isfinite(_host(u)).all()
+    assert wn(diff) / wn(f) <= rep["err_bound"] * (1 + 1e-6) + 1e-14
+
+
+def test_fp64_steps_defer_the_correction(rx):
+    """The FP64 path's algorithmic bytes count the steps that left d alone (4
+    complex values instead of 6): between 4 and 6 x 16 B per point and step,
+    and the result meets the FP64 bar against the exact exponential."""
+    op, rho, t, f = _case(128, 128, 300.0, nbumps=4, seed=22)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision="fp64", tol=1e-10)
+    per = rep["alg_bytes"] / (rep["total_iters"] * 128 * 128)
+    print(f"FP64 bytes per point and step {per:.1f}", flush=True)
+    assert 64.0 < per < 96.0
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
 def test_caller_workspace(rx):
     import torch
     op, rho, t, f = _case(64, 64, 100.0, nbumps=2, seed=7)

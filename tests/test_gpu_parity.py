@@ -2,6 +2,8 @@
 
 Bars: FP64 path rel-L2 <= 1e-10, mixed path <= 1e-6 (the target accuracies
 of the two precisions); per-pole resolvents <= 1e-10 at tol 1e-12."""
+import math
+
 import numpy as np
 import pytest
 
@@ -190,6 +192,27 @@ def test_fp64_steps_defer_the_correction(rx):
     print(f"FP64 bytes per point and step {per:.1f}", flush=True)
     assert 64.0 < per < 96.0
     assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= 1e-10
+
+
+@pytest.mark.parametrize("h,precision,tol", [(0.3, "fp64", 1e-10), (1.0, "fp64", 1e-10), (1.0, "mixed", 1e-6),
+                                              (1.5, "mixed", 1e-6)])
+def test_other_pole_spacings(rx, h, precision, tol):
+    """Pole spacings other than the default 0.5 (Sec. 3.1 recommends
+    [0.3, 0.6]; larger h halves or thirds the pole count at an aliasing
+    floor e^{4 pi h - 4 pi^2} of 2e-12 at h = 1 and 1e-9 at h = 1.5): the
+    pole count of the rule, the oracle's exact approximant for that h to the
+    solver's bound, and the exact exponential to the approximation's floor."""
+    op, rho, t, f = _case(96, 72, 200.0, nbumps=3, seed=23, velocity=True)
+    u, rep = rx.apply(_dev(f), t, fc=10.0, precision=precision, tol=tol, h=h)
+    c = oc.api_coeffs(t, rho, h=h, tol=tol)
+    assert rep["P"] == c["P"] and abs(rep["h"] - h) == 0.0
+    ref = rm.rexii_spectral(op, f, t, c["z"], c["w"])
+    err = em.rel_l2(_host(u), ref)
+    print(f"h={h} {precision}: P={rep['P']} err vs approximant {err:.2e}, bound {rep['err_bound']:.2e}", flush=True)
+    assert 0.0 < rep["err_bound"] <= tol
+    assert err <= rep["err_bound"] * (1 + 1e-6) + 1e-14
+    floor = math.exp(4 * math.pi * h - 4 * math.pi ** 2)
+    assert em.rel_l2(_host(u), em.expm_closed_real(op, f, t)) <= tol + 10 * floor
 
 
 def test_caller_workspace(rx):

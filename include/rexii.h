@@ -77,7 +77,14 @@ typedef struct rexii_swe_op {
 
 typedef struct rexii_opts {
     double h;               /* Gaussian width of the approximation (Sec. 2.1,
-                               best in [0.3, 0.6] per Sec. 3.1); 0 -> 0.5    */
+                               best in [0.3, 0.6] per Sec. 3.1); 0 -> 0.5.
+                               The approximation's own error floor is about
+                               e^{4 pi h - 4 pi^2} (2e-12 at h = 1, 1e-9 at
+                               1.5), so a looser tol admits a larger h:
+                               fewer poles (P ~ 2 t rho / h), each better
+                               separated from the spectrum (512^2,
+                               t rho = 1000: h = 1 takes 0.45 x the time of
+                               0.5 at tol 1e-6, 0.4 x at 1e-10)           */
     double tol;             /* target relative L2 error of u; 0 -> 1e-10 for
                                FP64, 1e-6 for MIXED.  Sets m0 (Appendix B)
                                and the per-pole residual tolerance          */

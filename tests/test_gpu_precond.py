@@ -65,6 +65,26 @@ def test_precond_vs_chebyshev(rx, D, trho):
     assert rep["total_iters"] * 4 <= repb["total_iters"]
 
 
+@pytest.mark.parametrize("nx,ny,trho,slots", [(130, 66, 200.0, 0), (100, 36, 120.0, 5)])
+def test_precond_ragged_grids(rx, nx, ny, trho, slots):
+    # grids that are no power of two and not square (the transforms' mixed
+    # radices, the matvec's wrap at both edges), with an initial velocity;
+    # 5 slots: every slot takes many solves in turn
+    Hf = inputs.variable_depth(nx, ny)
+    op = lrsw.LRSW(nx, ny, fc=15.0, Hfield=Hf)
+    t = trho / lrsw.rho(op)
+    f = inputs.gaussian_bumps(nx, ny, nbumps=5, seed=33, velocity=True)
+    print(f"precond ragged {nx}x{ny} t rho {trho} slots {slots}", flush=True)
+    u, rep = rx.apply(_dev(f), t, fc=15.0, Hfield=_dev(Hf), method="precond", pole_batch=slots, tol=1e-10)
+    ref = varh.chebyshev_expm(op, f, t)
+    un = u.cpu().numpy()
+    assert rep["not_converged"] == 0 and 0.0 < rep["err_bound"] <= 1e-10
+    assert em.rel_l2(un, ref) <= 1e-10
+    assert abs(varh.w_energy(op, un) / varh.w_energy(op, f) - 1.0) <= 1e-10
+    if slots:
+        assert rep["slots"] == slots
+
+
 def test_precond_constant_depth(rx):
     # constant depth through the flux form: the preconditioner is the exact
     # inverse (up to its damping), against the oracle's exact approximant
